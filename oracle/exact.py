@@ -1,0 +1,210 @@
+"""Exact references for tiny systems.  Test infrastructure only.
+
+* U = 0: G = (1 + exp(-beta K))^{-1} block by block in momentum space,
+  (1 + exp(-beta h))^{-1} = 1/2 + tanh(beta |f| / 2) h / (2 |f|), with h(k) of
+  eq. h0kMat at the shifted grid of eq. kpoints and the Fourier matrix
+  U_{k,r} = exp(-i k.r)/L of eq. NewBlMat; energy per site
+  e = -(1/N_c) sum_k |f(k)| tanh(beta |f(k)| / 2); D = 1/4.
+* Brute force: Z = sum_X W(X), W = 2^{-N M} det(1 + B^up_M..B^up_1)
+  det(1 + B^dn_M..B^dn_1) over every HS configuration (eq. ConfgWeight), with
+  estimators taken on G(l = M).
+* Exact diagonalisation of the Trotterised partition function
+  Tr[(exp(-dtau H_U) exp(-dtau H_0))^M] in the 4^N-dimensional Fock space
+  for M in {1, 2}, H_U = U sum_i (n_up n_dn - (n_up + n_dn)/2)
+  (eq. HubbModel).  Observables are inserted at the left end of the product.
+"""
+import itertools
+
+import numpy as np
+
+from .dqmc import Model
+from .lattice import Lattice
+
+
+# ---- U = 0 --------------------------------------------------------------------------
+def fourier_matrix(lat):
+    """Per-sublattice unitary DFT on the plain grid, U_{k,r} = exp(-i k.r)/L."""
+    L, Nc = lat.L, lat.Nc
+    Uc = np.zeros((Nc, Nc), dtype=complex)
+    for kI in range(Nc):
+        l1, l2 = kI % L, kI // L
+        for rI in range(Nc):
+            n1, n2 = rI % L, rI // L
+            Uc[kI, rI] = np.exp(-2j * np.pi * (l1 * n1 + l2 * n2) / L) / L
+    Z = np.zeros_like(Uc)
+    return np.block([[Uc, Z], [Z, Uc]])
+
+
+def kspace_block_matrix(lat, fn):
+    """Assemble U^dagger Lambda U where Lambda is block diagonal with the 2x2
+    block fn(h(k+A)) at plain momentum index k (A enters through f(k+A))."""
+    Nc = lat.Nc
+    f = lat.f_of_k(lat.kpoints())
+    Lam = np.zeros((lat.N, lat.N), dtype=complex)
+    for kI in range(Nc):
+        h = np.array([[0.0, f[kI]], [np.conj(f[kI]), 0.0]])
+        blk = fn(h, f[kI])
+        Lam[kI, kI] = blk[0, 0]
+        Lam[kI, Nc + kI] = blk[0, 1]
+        Lam[Nc + kI, kI] = blk[1, 0]
+        Lam[Nc + kI, Nc + kI] = blk[1, 1]
+    Uf = fourier_matrix(lat)
+    return Uf.conj().T @ Lam @ Uf
+
+
+def exp_h_closed(h, f, c):
+    """exp(c h) for h = [[0,f],[f*,0]]: cosh(c|f|) 1 + sinh(c|f|)/|f| h."""
+    a = abs(f)
+    s = c if a < 1e-12 else np.sinh(c * a) / a
+    return np.cosh(c * a) * np.eye(2) + s * h
+
+
+def green_u0(lat, beta):
+    def g(h, f):
+        a = abs(f)
+        if a < 1e-14:
+            return 0.5 * np.eye(2)
+        return 0.5 * np.eye(2) + np.tanh(beta * a / 2) * h / (2 * a)
+    return kspace_block_matrix(lat, g)
+
+
+def energy_u0(lat, beta):
+    f = np.abs(lat.f_of_k(lat.kpoints()))
+    return -np.sum(f * np.tanh(beta * f / 2)) / lat.Nc
+
+
+# ---- brute force over HS configurations ---------------------------------------------
+def brute_force(model, batch=4096):
+    """Exact Z and weighted averages of D, <H_0>, S_zz(Gamma), S_zz(b1/L) by
+    summing W(X) over all 2^(N M) configurations (eq. ConfgWeight)."""
+    M, N, Nc, L = model.M, model.N, model.Nc, model.L
+    nf = M * N
+    if nf > 20:
+        raise ValueError("too many fields for brute force")
+    lat = model.lat
+    K = model.K
+    pos = np.array([[I % L, I // L] for I in range(Nc)])
+    ph = np.exp(2j * np.pi * pos[:, 0] / L)
+    tot = {"Z": 0.0, "D": 0.0, "H0": 0.0, "SzzG": 0.0, "Szzdk": 0.0}
+    wmin = np.inf
+    max_imag = 0.0
+    allcfg = np.array(list(itertools.product((1, -1), repeat=nf)), dtype=float)
+    for s0 in range(0, len(allcfg), batch):
+        X = allcfg[s0:s0 + batch].reshape(-1, M, N)
+        B = len(X)
+        dets, Gs = [], []
+        for spin in (0, 1):
+            sgn = 1.0 if spin == 0 else -1.0
+            P = np.broadcast_to(np.eye(N, dtype=complex), (B, N, N)).copy()
+            for l in range(M):
+                v = np.exp(sgn * model.lam * X[:, l, :])
+                P = v[:, :, None] * (model.Ep[None] @ P)
+            A = np.eye(N)[None] + P
+            dets.append(np.linalg.det(A))
+            Gs.append(np.linalg.inv(A))
+        W = dets[0] * dets[1] * 2.0 ** (-nf)
+        max_imag = max(max_imag, float(np.max(np.abs(W.imag) / np.abs(W))))
+        W = W.real
+        wmin = min(wmin, float(W.min()))
+        nu = 1 - np.einsum("bii->bi", Gs[0])
+        nd = 1 - np.einsum("bii->bi", Gs[1])
+        D = np.mean(nu * nd, axis=1)
+        H0 = -(np.einsum("ij,bji->b", K, Gs[0]) + np.einsum("ij,bji->b", K, Gs[1]))
+        sz = nu - nd
+        SS = 0.25 * (sz[:, :, None] * sz[:, None, :]
+                     + (np.eye(N)[None] - np.transpose(Gs[0], (0, 2, 1))) * Gs[0]
+                     + (np.eye(N)[None] - np.transpose(Gs[1], (0, 2, 1))) * Gs[1])
+        SzzG = np.zeros(B, dtype=complex)
+        Szzdk = np.zeros(B, dtype=complex)
+        for sub in (0, 1):
+            blk = SS[:, sub * Nc:(sub + 1) * Nc, sub * Nc:(sub + 1) * Nc]
+            SzzG += blk.sum(axis=(1, 2))
+            Szzdk += np.einsum("bij,i,j->b", blk, ph.conj(), ph)
+        SzzG /= 2 * Nc
+        Szzdk /= 2 * Nc
+        tot["Z"] += W.sum()
+        tot["D"] += (W * D).sum().real
+        tot["H0"] += (W * H0).sum().real
+        tot["SzzG"] += (W * SzzG).sum().real
+        tot["Szzdk"] += (W * Szzdk).sum().real
+    Z = tot["Z"]
+    return {"Z": Z, "D": tot["D"] / Z, "H0": tot["H0"] / Z, "SzzG": tot["SzzG"] / Z,
+            "Szzdk": tot["Szzdk"] / Z, "wmin": wmin, "w_max_rel_imag": max_imag}
+
+
+# ---- Fock-space exact diagonalisation ------------------------------------------------
+def fock_hopping(K):
+    """Many-body matrix of sum_ij K_ij c_i^+ c_j on one spin species
+    (Jordan-Wigner ordering of modes 0..N-1; state bit i = occupation of i)."""
+    N = K.shape[0]
+    dim = 1 << N
+    H = np.zeros((dim, dim), dtype=complex)
+    for a in range(dim):
+        for j in range(N):
+            if not (a >> j) & 1:
+                continue
+            sj = (-1) ** bin(a & ((1 << j) - 1)).count("1")
+            a1 = a ^ (1 << j)
+            for i in range(N):
+                if K[i, j] == 0:
+                    continue
+                if (a1 >> i) & 1:
+                    continue
+                si = (-1) ** bin(a1 & ((1 << i) - 1)).count("1")
+                H[a1 | (1 << i), a] += K[i, j] * sj * si
+    return H
+
+
+def exact_trotter(model):
+    """Z = Tr[T^M], T = exp(-dtau H_U) exp(-dtau H_0) and <O> = Tr[O T^M]/Z for
+    O in {D, H_0, S_zz(Gamma), S_zz(b1/L)}; M in {1, 2}."""
+    M, N, Nc, L = model.M, model.N, model.Nc, model.L
+    if M not in (1, 2):
+        raise ValueError("exact_trotter supports M = 1 or 2")
+    dim = 1 << N
+    H = fock_hopping(model.K)
+    w, V = np.linalg.eigh(H)
+    E = (V * np.exp(-model.dtau * w)) @ V.conj().T
+    occ = np.array([[(a >> i) & 1 for i in range(N)] for a in range(dim)], dtype=float)
+    nn = occ @ occ.T                                   # sum_i n_i(a) n_i(b)
+    ntot = occ.sum(axis=1)
+    HU = model.U * (nn - (ntot[:, None] + ntot[None, :]) / 2.0)
+    Dm = np.exp(-model.dtau * HU)                      # [a_up, b_dn]
+    Docc = nn / N
+    pos = np.array([[I % L, I // L] for I in range(Nc)])
+    ph = np.exp(2j * np.pi * pos[:, 0] / L)
+    SG = np.zeros((dim, dim))
+    Sdk = np.zeros((dim, dim))
+    for sub in (0, 1):
+        oa = occ[:, sub * Nc:(sub + 1) * Nc]
+        s = 0.5 * (oa[:, None, :] - oa[None, :, :])    # s^z_i for state (a, b)
+        SG += np.sum(s, axis=2) ** 2
+        Sdk += np.abs(np.sum(s * ph[None, None, :], axis=2)) ** 2
+    SG /= 2 * Nc
+    Sdk /= 2 * Nc
+    EH = E @ H
+    if M == 1:
+        dE = np.diag(E)
+        dEH = np.diag(EH)
+
+        def tr(O, left_up=False, left_dn=False):
+            eu = dEH if left_up else dE
+            ed = dEH if left_dn else dE
+            return np.einsum("ab,a,b->", O * Dm, eu, ed)
+    else:
+        P = E * E.T
+        Pt = E * EH.T
+
+        def tr(O, left_up=False, left_dn=False):
+            pu = Pt if left_up else P
+            pd = Pt if left_dn else P
+            return np.sum(pu * ((O * Dm) @ pd @ Dm.T))
+    one = np.ones((dim, dim))
+    Z = tr(one)
+    return {"Z": Z.real, "D": (tr(Docc) / Z).real,
+            "H0": ((tr(one, left_up=True) + tr(one, left_dn=True)) / Z).real,
+            "SzzG": (tr(SG) / Z).real, "Szzdk": (tr(Sdk) / Z).real}
+
+
+def tiny_model(U=3.8, dtau=0.25, M=2, theta1=0.0, theta2=0.0, L=2):
+    return Model(L, U, M * dtau, dtau, theta1=theta1, theta2=theta2, n_stab=max(1, M))
