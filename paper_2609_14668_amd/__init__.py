@@ -1,0 +1,247 @@
+"""Python binding of libdqmc.so (include/dqmc.h): argument marshalling only.
+
+Every step of the DQMC sweep runs in the library's HIP kernels on the GPU;
+PyTorch is used here only to own the device workspace and to supply the HIP
+stream.  The module-level functions carry the C names; ``Simulation`` wraps a
+handle.  If the library has not been built, importing the binding raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdqmc.so")
+
+DQMC_OK = 0
+STATUS = {0: "DQMC_OK", -1: "DQMC_EINVAL", -2: "DQMC_ENOMEM", -3: "DQMC_EHIP", -4: "DQMC_ENUMERIC",
+          -5: "DQMC_ESTATE", -6: "DQMC_EUNSUPPORTED"}
+OBS_FIELDS = ("n", "D", "ekin", "e", "Szz_G", "Szz_dk", "m2", "Rm2", "phase_cos", "phase_sin")
+
+
+class DqmcError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("t", ctypes.c_double), ("U", ctypes.c_double),
+                ("beta", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("theta1", ctypes.c_double), ("theta2", ctypes.c_double),
+                ("n_delay", ctypes.c_int32), ("n_stab", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("sym_measure", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in OBS_FIELDS] + [("n_meas", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64), ("flushes", ctypes.c_int64),
+                ("sweeps", ctypes.c_int64), ("drift_max", ctypes.c_double), ("drift_last", ctypes.c_double),
+                ("numeric_err", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "dqmc_workspace_size": [ctypes.POINTER(InstanceDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "dqmc_create": [ctypes.POINTER(InstanceDesc), ctypes.c_int32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "dqmc_destroy": [_P],
+    "dqmc_set_fields": [_P, ctypes.c_int32, _P],
+    "dqmc_get_fields": [_P, ctypes.c_int32, _P],
+    "dqmc_sweep": [_P, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_replay": [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_get_green": [_P, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_set_green": [_P, ctypes.c_int32, _P],
+    "dqmc_wrap": [_P, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_flush_test": [_P, ctypes.c_int32, _P, _P, ctypes.c_int32],
+    "dqmc_measure": [_P, ctypes.c_int32, ctypes.POINTER(Obs)],
+    "dqmc_reset_obs": [_P],
+    "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
+    "dqmc_shape": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                   ctypes.POINTER(ctypes.c_int32)],
+    "dqmc_status_string": [ctypes.c_int32],
+    "dqmc_last_error": [_P],
+}
+
+_lib = None
+
+
+def load():
+    """Load libdqmc.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdqmc.so is not built (run: python -m paper_2609_14668_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("dqmc_status_string", "dqmc_last_error") else ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _descs(descs):
+    arr = (InstanceDesc * len(descs))()
+    for i, d in enumerate(descs):
+        for k, _ in InstanceDesc._fields_:
+            setattr(arr[i], k, d[k])
+    return arr
+
+
+def dqmc_workspace_size(descs):
+    lib = load()
+    arr = _descs(descs)
+    out = ctypes.c_size_t(0)
+    st = lib.dqmc_workspace_size(arr, len(descs), ctypes.byref(out))
+    if st != DQMC_OK:
+        raise DqmcError(st, "workspace_size")
+    return out.value
+
+
+class Simulation:
+    """A handle over a batch of Markov chains (one dict per chain, keys as in
+    dqmc_instance_desc).  The workspace is a torch uint8 tensor on the GPU."""
+
+    def __init__(self, descs, device="cuda"):
+        import torch
+        self.lib = load()
+        self.descs = [dict(d) for d in descs]
+        self._arr = _descs(self.descs)
+        size = dqmc_workspace_size(self.descs)
+        self.ws = torch.empty(size + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.ws.device)
+        h = _P()
+        st = self.lib.dqmc_create(self._arr, len(descs), self._ws_ptr, size, self.stream.cuda_stream,
+                                  ctypes.byref(h))
+        if st != DQMC_OK:
+            raise DqmcError(st, "dqmc_create")
+        self.h = h
+        self.n = len(descs)
+        self.shapes = [self.shape(i) for i in range(self.n)]
+
+    # ---- helpers
+    def _chk(self, st, what):
+        if st != DQMC_OK:
+            msg = self.lib.dqmc_last_error(self.h)
+            raise DqmcError(st, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dqmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, inst):
+        N = ctypes.c_int32()
+        M = ctypes.c_int32()
+        c = ctypes.c_int32()
+        self._chk(self.lib.dqmc_shape(self.h, inst, ctypes.byref(N), ctypes.byref(M), ctypes.byref(c)), "shape")
+        return N.value, M.value, bool(c.value)
+
+    # ---- C entry points
+    def dqmc_sweep(self, n_sweeps, measure=True):
+        self._chk(self.lib.dqmc_sweep(self.h, n_sweeps, int(bool(measure)), None), "sweep")
+
+    sweep = dqmc_sweep
+
+    def dqmc_replay(self, bits, ratios=None, n_sweeps=1, measure=False):
+        """bits: torch.uint8 CUDA tensor [n_inst, bits_per_inst]; ratios: float64 same shape or None."""
+        bits = bits.contiguous()
+        rp = ratios.data_ptr() if ratios is not None else None
+        self._chk(self.lib.dqmc_replay(self.h, bits.data_ptr(), bits.shape[1], rp, n_sweeps, int(bool(measure)),
+                                       None), "replay")
+
+    replay = dqmc_replay
+
+    def dqmc_get_green(self, inst=0, spin=0):
+        N, _, cx = self.shapes[inst]
+        out = np.empty((N, N, 2) if cx else (N, N), dtype=np.float64)
+        self._chk(self.lib.dqmc_get_green(self.h, inst, spin, out.ctypes.data), "get_green")
+        return out[..., 0] + 1j * out[..., 1] if cx else out
+
+    green = dqmc_get_green
+
+    def dqmc_set_green(self, inst, G):
+        N, _, cx = self.shapes[inst]
+        if cx:
+            buf = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1), dtype=np.float64)
+        else:
+            buf = np.ascontiguousarray(np.real(G), dtype=np.float64)
+        self._chk(self.lib.dqmc_set_green(self.h, inst, buf.ctypes.data), "set_green")
+
+    set_green = dqmc_set_green
+
+    def dqmc_get_fields(self, inst=0):
+        N, M, _ = self.shapes[inst]
+        out = np.empty((M, N), dtype=np.int8)
+        self._chk(self.lib.dqmc_get_fields(self.h, inst, out.ctypes.data), "get_fields")
+        return out
+
+    fields = dqmc_get_fields
+
+    def dqmc_set_fields(self, inst, x):
+        x = np.ascontiguousarray(x, dtype=np.int8)
+        self._chk(self.lib.dqmc_set_fields(self.h, inst, x.ctypes.data), "set_fields")
+
+    set_fields = dqmc_set_fields
+
+    def dqmc_wrap(self, direction, slice_):
+        self._chk(self.lib.dqmc_wrap(self.h, direction, slice_, None), "wrap")
+
+    wrap = dqmc_wrap
+
+    def dqmc_flush_test(self, inst, X, Y):
+        N, _, cx = self.shapes[inst]
+        k = X.shape[1]
+
+        def pack(A):
+            if cx:
+                return np.ascontiguousarray(np.stack([A.real, A.imag], axis=-1), dtype=np.float64)
+            return np.ascontiguousarray(np.real(A), dtype=np.float64)
+        Xb = pack(np.asfortranarray(X).T.copy())      # column j contiguous (column-major N x k)
+        Yb = pack(np.ascontiguousarray(Y))            # row m contiguous (k x N)
+        self._chk(self.lib.dqmc_flush_test(self.h, inst, Xb.ctypes.data, Yb.ctypes.data, k), "flush_test")
+
+    flush_test = dqmc_flush_test
+
+    def dqmc_measure(self, inst=0):
+        o = Obs()
+        self._chk(self.lib.dqmc_measure(self.h, inst, ctypes.byref(o)), "measure")
+        d = {f: getattr(o, f) for f in OBS_FIELDS}
+        d["n_meas"] = o.n_meas
+        return d
+
+    measure = dqmc_measure
+
+    def dqmc_reset_obs(self):
+        self._chk(self.lib.dqmc_reset_obs(self.h), "reset_obs")
+
+    reset_obs = dqmc_reset_obs
+
+    def dqmc_get_series(self, inst=0, max_sweeps=4096):
+        out = np.zeros((max_sweeps, len(OBS_FIELDS)), dtype=np.float64)
+        n = ctypes.c_int32()
+        self._chk(self.lib.dqmc_get_series(self.h, inst, out.ctypes.data, max_sweeps, ctypes.byref(n)), "series")
+        return {f: out[:n.value, k].copy() for k, f in enumerate(OBS_FIELDS)}
+
+    series = dqmc_get_series
+
+    def dqmc_get_stats(self, inst=0):
+        s = Stats()
+        self._chk(self.lib.dqmc_get_stats(self.h, inst, ctypes.byref(s)), "stats")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    stats = dqmc_get_stats

@@ -1,0 +1,728 @@
+// Host side of the library: workspace layout, lattice tables, the sweep
+// schedule and the C ABI declared in include/dqmc.h.
+//
+// The schedule is the paper's sweep (Sec. III): per instance an upward pass
+// (wrap G to slice l, update slice l) and a downward pass (update slice l,
+// wrap back), with a QR/UDV recomputation of G every n_stab slices (Sec. II B).
+// All instances of a handle advance in lock step, one slice per step; every
+// kernel handles all instances (blockIdx.y) and reads the per-instance
+// schedule state from device memory, so the host issues the same launch
+// sequence for every step and never waits on the device inside a sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "dqmc.h"
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace {
+
+constexpr int WINDOW = 64;
+constexpr int QR_NB = 32;
+constexpr int TRSM_ROWS = 32;
+constexpr int MAX_SERIES = 4096;
+constexpr int MAX_DELAY = 192;
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool factor_L(int L, std::vector<int>& f) {
+  f.clear();
+  int n = L;
+  while (n % 4 == 0) { f.push_back(4); n /= 4; }
+  while (n % 2 == 0) { f.push_back(2); n /= 2; }
+  for (int p : {3, 5, 7, 11, 13})
+    while (n % p == 0) { f.push_back(p); n /= p; }
+  return n == 1 && f.size() < 16;
+}
+
+bool is_twisted(const dqmc_instance_desc& d) {
+  const double tp = 2.0 * M_PI;
+  auto nz = [&](double th) { double r = std::fmod(th, tp); return std::fabs(r) > 1e-15 && std::fabs(std::fabs(r) - tp) > 1e-15; };
+  return nz(d.theta1) || nz(d.theta2);
+}
+
+struct Offs {
+  size_t st, obs, series, fields, tab, roots, factors, perm, acc, wcoef;
+  size_t vec[VEC_COUNT];
+  size_t mat[MAT_COUNT];
+  size_t stackU, stackT, stackD;
+  size_t end;
+};
+
+struct Plan {
+  bool cplx = false;
+  int Nmax = 0, Mmax = 0, n_stab = 0;
+  size_t insts_off = 0, total = 0;
+  std::vector<Offs> offs;
+};
+
+dqmc_status validate(const dqmc_instance_desc* d, int n, std::string& err) {
+  if (!d || n < 1) { err = "need at least one instance"; return DQMC_EINVAL; }
+  for (int i = 0; i < n; ++i) {
+    const dqmc_instance_desc& x = d[i];
+    std::vector<int> f;
+    if (x.L < 2 || x.L > 45) { err = "L must be in [2, 45]"; return DQMC_EUNSUPPORTED; }
+    if (!factor_L(x.L, f)) { err = "L must factor into 2, 3, 5, 7, 11, 13"; return DQMC_EUNSUPPORTED; }
+    if (!(x.dtau > 0) || !(x.beta > 0) || !std::isfinite(x.t) || !(x.U >= 0)) { err = "need dtau > 0, beta > 0, U >= 0"; return DQMC_EINVAL; }
+    double M = x.beta / x.dtau;
+    if (std::fabs(M - std::round(M)) > 1e-9 || M < 1) { err = "beta/dtau must be a positive integer"; return DQMC_EINVAL; }
+    if (x.n_stab < 1 || ((int)std::lround(M)) % x.n_stab != 0) { err = "n_stab must divide beta/dtau"; return DQMC_EINVAL; }
+    if (x.n_stab != d[0].n_stab) { err = "all instances must share n_stab"; return DQMC_EINVAL; }
+    if (x.n_delay < 1 || x.n_delay > MAX_DELAY) { err = "n_delay must be in [1, 192]"; return DQMC_EINVAL; }
+    if (x.precision != DQMC_FP64) { err = "only DQMC_FP64 is supported"; return DQMC_EUNSUPPORTED; }
+  }
+  return DQMC_OK;
+}
+
+Plan make_plan(const dqmc_instance_desc* d, int n) {
+  Plan p;
+  for (int i = 0; i < n; ++i) p.cplx = p.cplx || is_twisted(d[i]);
+  const size_t ss = p.cplx ? 16 : 8;
+  size_t o = 0;
+  p.insts_off = o;
+  o = al(o + sizeof(InstDev) * n);
+  p.n_stab = d[0].n_stab;
+  for (int i = 0; i < n; ++i) {
+    const int L = d[i].L, N = 2 * L * L, Nc = L * L;
+    const int M = (int)std::lround(d[i].beta / d[i].dtau);
+    const int C = M / d[i].n_stab;
+    const int kcap = d[i].n_delay + WINDOW;
+    p.Nmax = std::max(p.Nmax, N);
+    p.Mmax = std::max(p.Mmax, M);
+    Offs f;
+    f.st = o; o = al(o + sizeof(InstState));
+    f.obs = o; o = al(o + sizeof(double) * (2 * OBS_COUNT + 1));
+    f.series = o; o = al(o + sizeof(double) * OBS_COUNT * MAX_SERIES);
+    f.fields = o; o = al(o + (size_t)M * N);
+    f.tab = o; o = al(o + sizeof(cplx) * 16 * Nc);
+    f.roots = o; o = al(o + sizeof(cplx) * 64);
+    f.factors = o; o = al(o + sizeof(int32_t) * 16);
+    f.perm = o; o = al(o + sizeof(int32_t) * N);
+    f.acc = o; o = al(o + sizeof(int32_t) * WINDOW);
+    f.wcoef = o; o = al(o + ss * (WINDOW + 2 * WINDOW * WINDOW));
+    for (int v = 0; v < VEC_COUNT; ++v) { f.vec[v] = o; o = al(o + sizeof(double) * 2 * N); }
+    const size_t mb = ss * (size_t)N * N;
+    for (int m = 0; m < MAT_COUNT; ++m) {
+      f.mat[m] = o;
+      if (m == MAT_SU || m == MAT_ST) continue;
+      size_t bytes = (m == MAT_X || m == MAT_Y) ? ss * (size_t)N * std::max(N, kcap) : mb;
+      o = al(o + bytes);
+    }
+    f.stackU = o; o = al(o + mb * (C + 1));
+    f.stackT = o; o = al(o + mb * (C + 1));
+    f.stackD = o; o = al(o + sizeof(double) * N * (C + 1));
+    f.end = o;
+    p.offs.push_back(f);
+  }
+  p.total = o;
+  return p;
+}
+
+// exp(c h(k)) / Nc for h = [[0, f], [f*, 0]]: cosh(c|f|) 1 + sinh(c|f|)/|f| h.
+void table_entry(std::complex<double> f, double c, double Nc, std::complex<double> out[4]) {
+  double a = std::abs(f);
+  double ca = c * a;
+  double ch = std::cosh(ca);
+  double sh;
+  if (std::fabs(ca) < 1e-4) {
+    double x2 = ca * ca;
+    sh = c * (1.0 + x2 / 6.0 + x2 * x2 / 120.0);
+  } else {
+    sh = std::sinh(ca) / a;
+  }
+  out[0] = ch / Nc;
+  out[1] = sh * f / Nc;
+  out[2] = sh * std::conj(f) / Nc;
+  out[3] = ch / Nc;
+}
+
+}  // namespace
+
+struct dqmc_ctx {
+  int n = 0;
+  bool cplx = false;
+  int Nmax = 0, Mmax = 0, n_stab = 0;
+  std::vector<dqmc_instance_desc> desc;
+  std::vector<InstDev> hd;
+  Plan plan;
+  InstDev* dinst = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  size_t lds_budget = 65536;
+  std::string err;
+  int64_t sweeps_done = 0;
+};
+
+namespace {
+
+dqmc_status fail(dqmc_ctx* h, dqmc_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+#define HIPCHK(h, x)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return fail(h, DQMC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+hipStream_t pick(dqmc_ctx* h, void* s) { return s ? (hipStream_t)s : h->stream; }
+
+// ---- launch helpers ----------------------------------------------------------------------
+struct Ctx {
+  dqmc_ctx* h;
+  hipStream_t s;
+  hipError_t e = hipSuccess;
+  void chk(hipError_t x) { if (e == hipSuccess && x != hipSuccess) e = x; }
+  void fft(int op, int side, int mat, int j = 0) {
+    FftArgs a{op, side, mat, j, 0, 0, 0, 0};
+    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, s));
+  }
+  void fft_explicit(int side, int mat, int pre, int tab, int post, int slice) {
+    FftArgs a{FOP_EXPLICIT, side, mat, 0, pre, tab, post, slice};
+    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, s));
+  }
+  void gemm(GemmOperand A, GemmOperand B, GemmOperand C, GemmDim M, GemmDim N, GemmDim K,
+            double alpha, double beta, int flags = 0) {
+    chk(launch_gemm(h->dinst, h->n, h->Nmax, h->cplx, A, B, C, M, N, K, alpha, beta, flags, s));
+  }
+  void elem(int op, int a = 0, int b = 0, int c = 0, int v = 0) {
+    ElemArgs x{op, a, b, c, v};
+    chk(launch_elem(h->dinst, h->n, h->Nmax, h->cplx, x, s));
+  }
+};
+
+GemmOperand opnd(int id, int op, int ra = 0, int rb = 0, int ca = 0, int cb = 0) {
+  return GemmOperand{id, op, ra, rb, ca, cb};
+}
+GemmDim dim(int a, int b, int hi = 0) { return GemmDim{a, b, hi}; }
+
+// Blocked Householder QR of MAT_QA (explicit V and T blocks per panel).
+void qr_factor(Ctx& c) {
+  const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
+  for (int p = 0; p < npan; ++p) {
+    const int j0 = p * QR_NB;
+    c.chk(launch_qr_panel(c.h->dinst, c.h->n, c.h->cplx, p, QR_NB, c.s));
+    // W1 = V^H A[j0:, j0+nb:]
+    c.gemm(opnd(MAT_V, 2, 0, j0, 0, j0), opnd(MAT_QA, 0, 0, j0, 0, j0 + QR_NB), opnd(MAT_W1, 0),
+           dim(1, -j0, QR_NB), dim(1, -j0 - QR_NB), dim(1, -j0), 1.0, 0.0);
+    // W2 = T^H W1
+    c.gemm(opnd(MAT_TB, 2, 0, j0, 0, 0), opnd(MAT_W1, 0), opnd(MAT_W2, 0),
+           dim(1, -j0, QR_NB), dim(1, -j0 - QR_NB), dim(1, -j0, QR_NB), 1.0, 0.0);
+    // A[j0:, j0+nb:] -= V W2
+    c.gemm(opnd(MAT_V, 0, 0, j0, 0, j0), opnd(MAT_W2, 0), opnd(MAT_QA, 0, 0, j0, 0, j0 + QR_NB),
+           dim(1, -j0), dim(1, -j0 - QR_NB), dim(1, -j0, QR_NB), -1.0, 1.0);
+  }
+}
+
+// target <- Q target (form Q when target = I), blocks applied last to first.
+void apply_q(Ctx& c, int target) {
+  const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
+  for (int p = npan - 1; p >= 0; --p) {
+    const int j0 = p * QR_NB;
+    c.gemm(opnd(MAT_V, 2, 0, j0, 0, j0), opnd(target, 0, 0, j0, 0, j0), opnd(MAT_W1, 0),
+           dim(1, -j0, QR_NB), dim(1, -j0), dim(1, -j0), 1.0, 0.0);
+    c.gemm(opnd(MAT_TB, 0, 0, j0, 0, 0), opnd(MAT_W1, 0), opnd(MAT_W2, 0),
+           dim(1, -j0, QR_NB), dim(1, -j0), dim(1, -j0, QR_NB), 1.0, 0.0);
+    c.gemm(opnd(MAT_V, 0, 0, j0, 0, j0), opnd(MAT_W2, 0), opnd(target, 0, 0, j0, 0, j0),
+           dim(1, -j0), dim(1, -j0), dim(1, -j0, QR_NB), -1.0, 1.0);
+  }
+}
+
+// target <- Q^H target, blocks applied first to last, all columns.
+void apply_qh(Ctx& c, int target) {
+  const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
+  for (int p = 0; p < npan; ++p) {
+    const int j0 = p * QR_NB;
+    c.gemm(opnd(MAT_V, 2, 0, j0, 0, j0), opnd(target, 0, 0, j0, 0, 0), opnd(MAT_W1, 0),
+           dim(1, -j0, QR_NB), dim(1, 0), dim(1, -j0), 1.0, 0.0);
+    c.gemm(opnd(MAT_TB, 2, 0, j0, 0, 0), opnd(MAT_W1, 0), opnd(MAT_W2, 0),
+           dim(1, -j0, QR_NB), dim(1, 0), dim(1, -j0, QR_NB), 1.0, 0.0);
+    c.gemm(opnd(MAT_V, 0, 0, j0, 0, j0), opnd(MAT_W2, 0), opnd(target, 0, 0, j0, 0, 0),
+           dim(1, -j0), dim(1, 0), dim(1, -j0, QR_NB), -1.0, 1.0);
+  }
+}
+
+// MAT_W3 <- R^{-1} MAT_W3 with R the upper triangle of MAT_QA.
+void upper_solve(Ctx& c) {
+  const int nblk = (c.h->Nmax + TRSM_ROWS - 1) / TRSM_ROWS;
+  for (int b = 0; b < nblk; ++b) {
+    if (b > 0) {
+      // rows [i0, i1), i1 = N - 32 b: W3[i0:i1, :] -= R[i0:i1, i1:] W3[i1:, :]
+      c.gemm(opnd(MAT_QA, 0, 1, -TRSM_ROWS * (b + 1), 1, -TRSM_ROWS * b),
+             opnd(MAT_W3, 0, 1, -TRSM_ROWS * b, 0, 0),
+             opnd(MAT_W3, 0, 1, -TRSM_ROWS * (b + 1), 0, 0),
+             dim(1, -TRSM_ROWS * b, TRSM_ROWS), dim(1, 0), dim(0, TRSM_ROWS * b), -1.0, 1.0);
+    }
+    c.chk(launch_trsm_diag(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, b, c.s));
+  }
+}
+
+// One checkpoint: advance the working UDV chain by n_stab slices, recompute
+// G against the stack partner, record the drift, replace G, store the chain.
+void stabilise(Ctx& c, bool measure) {
+  dqmc_ctx* h = c.h;
+  c.elem(EO_RESET_CHAIN);
+  for (int j = 0; j < h->n_stab; ++j) c.fft(FOP_STAB_B, 0, MAT_UW, j);
+  c.elem(EO_SCALE_COLS, 0, 0, MAT_UW, VEC_DW);
+  c.chk(launch_colnorm_sort(h->dinst, h->n, h->Nmax, h->cplx, MAT_UW, c.s));
+  c.elem(EO_GATHER_COLS, MAT_UW, 0, MAT_QA);
+  c.elem(EO_GATHER_ROWS, MAT_TW, 0, MAT_W3);
+  qr_factor(c);
+  c.chk(launch_diag_abs(h->dinst, h->n, h->Nmax, h->cplx, c.s));
+  c.gemm(opnd(MAT_QA, 0), opnd(MAT_W3, 0), opnd(MAT_TW, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0,
+         GF_A_UPPER);
+  c.elem(EO_SCALE_ROWS_INV, 0, 0, MAT_TW, VEC_DW);
+  c.elem(EO_IDENTITY, 0, 0, MAT_UW);
+  apply_q(c, MAT_UW);
+  // G = U_L D_Lb^-1 Y^-1 D_Rb^-1 U_R^H
+  c.gemm(opnd(MAT_RU, 2), opnd(MAT_LU, 0), opnd(MAT_W1, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.gemm(opnd(MAT_RT, 0), opnd(MAT_LT, 2), opnd(MAT_W2, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.elem(EO_BUILD_Y, MAT_W1, MAT_W2, MAT_QA);
+  c.elem(EO_BUILD_RHS, 0, 0, MAT_W3);
+  qr_factor(c);
+  apply_qh(c, MAT_W3);
+  upper_solve(c);
+  c.elem(EO_SCALE_ROWS_DLB, 0, 0, MAT_W3);
+  c.gemm(opnd(MAT_LU, 0), opnd(MAT_W3, 0), opnd(MAT_GS, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.elem(EO_DRIFT_REPLACE);
+  c.elem(EO_STACK_STORE);
+  if (measure) {
+    bool sym = false;
+    for (auto& d : h->desc) sym = sym || d.sym_measure;
+    if (sym) {
+      c.elem(EO_COPY, MAT_G, 0, MAT_GS);
+      c.fft(FOP_HALF, 0, MAT_GS);
+      c.fft(FOP_HALF, 1, MAT_GS);
+      c.chk(launch_measure(h->dinst, h->n, h->Nmax, h->cplx, MAT_GS, c.s));
+    } else {
+      c.chk(launch_measure(h->dinst, h->n, h->Nmax, h->cplx, MAT_G, c.s));
+    }
+  }
+}
+
+// One step of every instance (one slice of its sweep).
+void step(Ctx& c, int64_t s, bool measure, int replay) {
+  dqmc_ctx* h = c.h;
+  c.fft(FOP_WRAP_PRE, 0, MAT_G);
+  c.fft(FOP_WRAP_PRE, 1, MAT_G);
+  const int nwin = (h->Nmax + WINDOW - 1) / WINDOW;
+  for (int w = 0; w < nwin; ++w) {
+    c.chk(launch_window(h->dinst, h->n, h->cplx, WINDOW, replay, c.s));
+    c.chk(launch_expand(h->dinst, h->n, h->Nmax, h->cplx, WINDOW, c.s));
+    c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
+           GF_K_FILL | GF_IF_FULL);
+    c.chk(launch_flush_done(h->dinst, h->n, 0, c.s));
+  }
+  c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
+         GF_K_FILL | GF_IF_ANY);
+  c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
+  c.fft(FOP_WRAP_POST, 0, MAT_G);
+  c.fft(FOP_WRAP_POST, 1, MAT_G);
+  if ((s + 1) % h->n_stab == 0) stabilise(c, measure);
+  c.chk(launch_advance(h->dinst, h->n, c.s));
+}
+
+dqmc_status upload_insts(dqmc_ctx* h, hipStream_t s) {
+  HIPCHK(h, hipMemcpyAsync(h->dinst, h->hd.data(), sizeof(InstDev) * h->n, hipMemcpyHostToDevice, s));
+  return DQMC_OK;
+}
+
+// Build the UDV stack and G(0) from the current fields: a downward pass
+// without updates (only the chain steps), then the working chain is reset.
+dqmc_status init_green(dqmc_ctx* h, hipStream_t s) {
+  Ctx c{h, s};
+  c.chk(launch_init_state(h->dinst, h->n, 1, s));
+  c.elem(EO_STACK_IDENTITY);
+  c.elem(EO_IDENTITY, 0, 0, MAT_UW);
+  c.elem(EO_IDENTITY, 0, 0, MAT_TW);
+  c.elem(EO_SET_ONES, 0, 0, 0, VEC_DW);
+  for (int64_t st = 0; st < h->Mmax; ++st) {
+    if ((st + 1) % h->n_stab == 0) stabilise(c, false);
+    c.chk(launch_advance(h->dinst, h->n, s));
+  }
+  c.chk(launch_init_state(h->dinst, h->n, 0, s));
+  if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("init: ") + hipGetErrorString(c.e));
+  return DQMC_OK;
+}
+
+}  // namespace
+
+// ================================ C ABI =================================================
+extern "C" {
+
+const char* dqmc_status_string(dqmc_status s) {
+  switch (s) {
+    case DQMC_OK: return "ok";
+    case DQMC_EINVAL: return "invalid argument";
+    case DQMC_ENOMEM: return "workspace too small";
+    case DQMC_EHIP: return "HIP runtime error";
+    case DQMC_ENUMERIC: return "numerical failure (non-finite or zero ratio)";
+    case DQMC_ESTATE: return "invalid state";
+    case DQMC_EUNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+const char* dqmc_last_error(dqmc_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+dqmc_status dqmc_workspace_size(const dqmc_instance_desc* d, int32_t n, size_t* bytes) {
+  std::string err;
+  if (!bytes) return DQMC_EINVAL;
+  dqmc_status st = validate(d, n, err);
+  if (st != DQMC_OK) return st;
+  *bytes = make_plan(d, n).total;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, size_t bytes, void* stream,
+                        dqmc_handle* out) {
+  if (!out || !dev_ws) return DQMC_EINVAL;
+  std::string err;
+  dqmc_status vs = validate(d, n, err);
+  if (vs != DQMC_OK) return vs;
+  if (((uintptr_t)dev_ws) & 255) return DQMC_EINVAL;
+  Plan p = make_plan(d, n);
+  if (bytes < p.total) return DQMC_ENOMEM;
+  dqmc_ctx* h = new dqmc_ctx();
+  h->n = n;
+  h->cplx = p.cplx;
+  h->Nmax = p.Nmax;
+  h->Mmax = p.Mmax;
+  h->n_stab = p.n_stab;
+  h->desc.assign(d, d + n);
+  h->plan = p;
+  h->ws = (char*)dev_ws;
+  h->ws_bytes = bytes;
+  h->stream = (hipStream_t)stream;
+  h->dinst = (InstDev*)(h->ws + p.insts_off);
+  const size_t ss = p.cplx ? 16 : 8;
+  hipStream_t s = h->stream;
+  std::vector<char> host;
+  for (int i = 0; i < n; ++i) {
+    const dqmc_instance_desc& x = d[i];
+    const Offs& f = p.offs[i];
+    InstDev dv;
+    std::memset(&dv, 0, sizeof(dv));
+    dv.L = x.L;
+    dv.Nc = x.L * x.L;
+    dv.N = 2 * dv.Nc;
+    dv.M = (int)std::lround(x.beta / x.dtau);
+    dv.n_stab = x.n_stab;
+    dv.n_ckpt = dv.M / x.n_stab;
+    dv.kflush = x.n_delay;
+    dv.kcap = x.n_delay + WINDOW;
+    dv.is_complex = p.cplx;
+    dv.sym_measure = x.sym_measure;
+    dv.lam = std::acosh(std::exp(x.dtau * x.U / 2.0));
+    dv.U = x.U; dv.dtau = x.dtau; dv.t = x.t;
+    dv.theta1 = x.theta1; dv.theta2 = x.theta2;
+    dv.seed = x.seed;
+    char* b = h->ws;
+    for (int m = 0; m < MAT_COUNT; ++m) dv.mat[m] = b + f.mat[m];
+    for (int v = 0; v < VEC_COUNT; ++v) dv.vec[v] = (double*)(b + f.vec[v]);
+    dv.stackU = b + f.stackU;
+    dv.stackT = b + f.stackT;
+    dv.stackD = (double*)(b + f.stackD);
+    dv.mat_bytes = ss * (size_t)dv.N * dv.N;
+    dv.fields = (int8_t*)(b + f.fields);
+    dv.tab = (const cplx*)(b + f.tab);
+    dv.roots = (const cplx*)(b + f.roots);
+    dv.factors = (const int32_t*)(b + f.factors);
+    dv.perm = (int32_t*)(b + f.perm);
+    dv.acc_site = (int32_t*)(b + f.acc);
+    dv.wcoef = (double*)(b + f.wcoef);
+    dv.st = (InstState*)(b + f.st);
+    dv.obs = (double*)(b + f.obs);
+    dv.series = (double*)(b + f.series);
+    dv.max_series = MAX_SERIES;
+    h->hd.push_back(dv);
+
+    // momentum tables at k = ((l1 + Theta1/2pi)/L) b1 + ((l2 + Theta2/2pi)/L) b2 (eq. kpoints)
+    const int L = x.L, Nc = dv.Nc;
+    std::vector<std::complex<double>> tab((size_t)16 * Nc);
+    const double cs[4] = {-x.dtau, x.dtau, -x.dtau / 2, x.dtau / 2};
+    for (int l2 = 0; l2 < L; ++l2)
+      for (int l1 = 0; l1 < L; ++l1) {
+        double ka1 = (2.0 * M_PI * l1 + x.theta1) / L;  // k . a1
+        double ka2 = (2.0 * M_PI * l2 + x.theta2) / L;  // k . a2
+        std::complex<double> fk = -x.t * (1.0 + std::polar(1.0, ka1 - ka2) + std::polar(1.0, -ka2));
+        int k = l1 + L * l2;
+        for (int t = 0; t < 4; ++t) table_entry(fk, cs[t], Nc, &tab[(size_t)t * Nc * 4 + 4 * k]);
+      }
+    std::vector<std::complex<double>> roots(64);
+    for (int m = 0; m < L; ++m) roots[m] = std::polar(1.0, -2.0 * M_PI * m / L);
+    std::vector<int> fac;
+    factor_L(L, fac);
+    int32_t facs[16] = {0};
+    for (size_t q = 0; q < fac.size(); ++q) facs[q] = fac[q];
+    std::vector<int8_t> fields((size_t)dv.M * dv.N);
+    for (int l = 1; l <= dv.M; ++l)
+      for (int i = 0; i < dv.N; ++i) {
+        philox_out o = philox4x32_10((uint32_t)i, (uint32_t)l, 0u, 2u, (uint32_t)(x.seed & 0xffffffffu),
+                                     (uint32_t)(x.seed >> 32));
+        fields[(size_t)(l - 1) * dv.N + i] = (o.w[0] & 1u) ? 1 : -1;
+      }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b + f.tab, tab.data(), sizeof(cplx) * tab.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(b + f.roots, roots.data(), sizeof(cplx) * 64, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(b + f.factors, facs, sizeof(facs), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(b + f.fields, fields.data(), fields.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.st, 0, sizeof(InstState), s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.series, 0, sizeof(double) * OBS_COUNT * MAX_SERIES, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      std::string m = std::string("create upload: ") + hipGetErrorString(e);
+      delete h;
+      (void)m;
+      return DQMC_EHIP;
+    }
+  }
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    h->lds_budget = std::min<size_t>(65536, (size_t)lds);
+  dqmc_status st = upload_insts(h, s);
+  if (st == DQMC_OK) st = init_green(h, s);
+  if (st == DQMC_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(h, DQMC_EHIP, "create: stream sync failed");
+  if (st != DQMC_OK) { delete h; return st; }
+  *out = h;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_destroy(dqmc_handle h) {
+  if (!h) return DQMC_EINVAL;
+  hipStreamSynchronize(h->stream);
+  delete h;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_shape(dqmc_handle h, int32_t inst, int32_t* N, int32_t* M, int32_t* is_complex) {
+  if (!h || inst < 0 || inst >= h->n) return DQMC_EINVAL;
+  if (N) *N = h->hd[inst].N;
+  if (M) *M = h->hd[inst].M;
+  if (is_complex) *is_complex = h->cplx ? 1 : 0;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_fields(dqmc_handle h, int32_t inst, const int8_t* host_x) {
+  if (!h || inst < 0 || inst >= h->n || !host_x) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  size_t n = (size_t)d.M * d.N;
+  for (size_t i = 0; i < n; ++i)
+    if (host_x[i] != 1 && host_x[i] != -1) return fail(h, DQMC_EINVAL, "fields must be +-1");
+  HIPCHK(h, hipMemcpyAsync(d.fields, host_x, n, hipMemcpyHostToDevice, h->stream));
+  dqmc_status st = init_green(h, h->stream);
+  if (st != DQMC_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_fields(dqmc_handle h, int32_t inst, int8_t* host_x) {
+  if (!h || inst < 0 || inst >= h->n || !host_x) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  HIPCHK(h, hipMemcpyAsync(host_x, d.fields, (size_t)d.M * d.N, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+static dqmc_status run_sweeps(dqmc_handle h, int32_t n_sweeps, int32_t measure, hipStream_t s, int replay) {
+  Ctx c{h, s};
+  const int64_t steps = (int64_t)n_sweeps * 2 * h->Mmax;
+  for (int64_t k = 0; k < steps; ++k) {
+    step(c, k, measure != 0, replay);
+    if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c.e));
+  }
+  h->sweeps_done += n_sweeps;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_sweep(dqmc_handle h, int32_t n_sweeps, int32_t measure, void* stream) {
+  if (!h || n_sweeps < 0) return DQMC_EINVAL;
+  return run_sweeps(h, n_sweeps, measure, pick(h, stream), 0);
+}
+
+dqmc_status dqmc_replay(dqmc_handle h, const uint8_t* dev_bits, int64_t bits_per_inst, double* dev_ratios,
+                        int32_t n_sweeps, int32_t measure, void* stream) {
+  if (!h || !dev_bits || n_sweeps < 0) return DQMC_EINVAL;
+  int64_t need = 0;
+  for (auto& d : h->hd) need = std::max<int64_t>(need, (int64_t)n_sweeps * 2 * h->Mmax * d.N);
+  if (bits_per_inst < need) return fail(h, DQMC_EINVAL, "replay stream too short");
+  hipStream_t s = pick(h, stream);
+  for (int i = 0; i < h->n; ++i) {
+    h->hd[i].replay_bits = dev_bits + (size_t)i * bits_per_inst;
+    h->hd[i].replay_ratio = dev_ratios ? dev_ratios + (size_t)i * bits_per_inst : nullptr;
+    h->hd[i].replay_len = bits_per_inst;
+  }
+  dqmc_status st = upload_insts(h, s);
+  if (st == DQMC_OK) {
+    Ctx c{h, s};
+    c.chk(launch_replay_reset(h->dinst, h->n, s));
+    st = c.e == hipSuccess ? run_sweeps(h, n_sweeps, measure, s, 1) : fail(h, DQMC_EHIP, "replay reset");
+  }
+  for (int i = 0; i < h->n; ++i) {
+    h->hd[i].replay_bits = nullptr;
+    h->hd[i].replay_ratio = nullptr;
+    h->hd[i].replay_len = 0;
+  }
+  dqmc_status st2 = upload_insts(h, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(h, DQMC_EHIP, "replay: stream sync failed");
+  return st != DQMC_OK ? st : st2;
+}
+
+dqmc_status dqmc_get_green(dqmc_handle h, int32_t inst, int32_t spin, double* host_out) {
+  if (!h || inst < 0 || inst >= h->n || !host_out || (spin != 0 && spin != 1)) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  const int N = d.N;
+  const int w = h->cplx ? 2 : 1;
+  std::vector<double> g((size_t)N * N * w);
+  HIPCHK(h, hipMemcpyAsync(g.data(), d.mat[MAT_G], sizeof(double) * g.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      if (spin == 0) {
+        for (int c = 0; c < w; ++c) host_out[((size_t)i * N + j) * w + c] = g[((size_t)j * N + i) * w + c];
+      } else {
+        // P (1 - G^dagger) P: element (i, j) = s_i s_j (delta_ij - conj(G_ji))
+        double sgn = ((i < d.Nc) == (j < d.Nc)) ? 1.0 : -1.0;
+        double re = g[((size_t)i * N + j) * w];  // G_ji (column-major: row j, column i)
+        double im = w == 2 ? g[((size_t)i * N + j) * w + 1] : 0.0;
+        host_out[((size_t)i * N + j) * w] = sgn * ((i == j ? 1.0 : 0.0) - re);
+        if (w == 2) host_out[((size_t)i * N + j) * w + 1] = sgn * im;
+      }
+    }
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_green(dqmc_handle h, int32_t inst, const double* host_in) {
+  if (!h || inst < 0 || inst >= h->n || !host_in) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  const int N = d.N;
+  const int w = h->cplx ? 2 : 1;
+  std::vector<double> g((size_t)N * N * w);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      for (int c = 0; c < w; ++c) g[((size_t)j * N + i) * w + c] = host_in[((size_t)i * N + j) * w + c];
+  HIPCHK(h, hipMemcpyAsync(d.mat[MAT_G], g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_wrap(dqmc_handle h, int32_t dir, int32_t slice, void* stream) {
+  if (!h || (dir != 0 && dir != 1)) return DQMC_EINVAL;
+  for (auto& d : h->hd)
+    if (slice < 1 || slice > d.M) return fail(h, DQMC_EINVAL, "slice out of range");
+  Ctx c{h, pick(h, stream)};
+  if (dir == 0) {
+    c.fft_explicit(0, MAT_G, 0, TAB_P, +1, slice);
+    c.fft_explicit(1, MAT_G, 0, TAB_M, -1, slice);
+  } else {
+    c.fft_explicit(0, MAT_G, -1, TAB_M, 0, slice);
+    c.fft_explicit(1, MAT_G, +1, TAB_P, 0, slice);
+  }
+  if (c.e != hipSuccess) return fail(h, DQMC_EHIP, hipGetErrorString(c.e));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X, const double* host_Y, int32_t k) {
+  if (!h || inst < 0 || inst >= h->n || !host_X || !host_Y || k < 1) return DQMC_EINVAL;
+  InstDev& d = h->hd[inst];
+  if (k > std::max(d.N, d.kcap)) return fail(h, DQMC_EINVAL, "k exceeds the delayed-update capacity");
+  const int w = h->cplx ? 2 : 1;
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(d.mat[MAT_X], host_X, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d.mat[MAT_Y], host_Y, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync((char*)d.st + offsetof(InstState, fill), &k, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  Ctx c{h, s};
+  c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
+         GF_K_FILL | GF_IF_ANY);
+  c.chk(launch_flush_done(h->dinst, h->n, 1, s));
+  if (c.e != hipSuccess) return fail(h, DQMC_EHIP, hipGetErrorString(c.e));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out) {
+  if (!h || inst < 0 || inst >= h->n || !out) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  double obs[2 * OBS_COUNT + 1];
+  InstState st;
+  HIPCHK(h, hipMemcpyAsync(obs, d.obs, sizeof(obs), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&st, d.st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double n = (double)st.n_meas;
+  std::memset(out, 0, sizeof(*out));
+  out->n_meas = st.n_meas;
+  if (n > 0) {
+    out->n = obs[OBS_N] / n;
+    out->D = obs[OBS_D] / n;
+    out->ekin = obs[OBS_EKIN] / n;
+    out->e = obs[OBS_E] / n;
+    out->Szz_G = obs[OBS_SZZ_G] / n;
+    out->Szz_dk = obs[OBS_SZZ_DK] / n;
+    out->m2 = obs[OBS_M2] / n;
+    out->Rm2 = out->Szz_G != 0.0 ? 1.0 - out->Szz_dk / out->Szz_G : 0.0;
+    out->phase_cos = obs[OBS_PHASE_RE] / n;
+    out->phase_sin = obs[OBS_PHASE_IM] / n;
+  }
+  if (st.numeric_err) return fail(h, DQMC_ENUMERIC, "non-finite or zero ratio encountered");
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_reset_obs(dqmc_handle h) {
+  if (!h) return DQMC_EINVAL;
+  for (auto& d : h->hd) HIPCHK(h, hipMemsetAsync(d.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), h->stream));
+  Ctx c{h, h->stream};
+  c.chk(launch_reset_counters(h->dinst, h->n, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32_t max_sweeps, int32_t* n_out) {
+  if (!h || inst < 0 || inst >= h->n || !host_out || !n_out || max_sweeps < 0) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  InstState st;
+  HIPCHK(h, hipMemcpyAsync(&st, d.st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> ser((size_t)OBS_COUNT * MAX_SERIES);
+  HIPCHK(h, hipMemcpyAsync(ser.data(), d.series, sizeof(double) * ser.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int64_t have = std::min<int64_t>(st.sweep - st.series_base, MAX_SERIES);
+  int64_t cnt = std::min<int64_t>(have, max_sweeps);
+  for (int64_t q = 0; q < cnt; ++q) {
+    int64_t sw = st.sweep - cnt + q;
+    const double* row = &ser[(size_t)(sw % MAX_SERIES) * OBS_COUNT];
+    double* o = host_out + q * OBS_COUNT;
+    o[0] = row[OBS_N]; o[1] = row[OBS_D]; o[2] = row[OBS_EKIN]; o[3] = row[OBS_E];
+    o[4] = row[OBS_SZZ_G]; o[5] = row[OBS_SZZ_DK]; o[6] = row[OBS_M2];
+    o[7] = row[OBS_SZZ_G] != 0.0 ? 1.0 - row[OBS_SZZ_DK] / row[OBS_SZZ_G] : 0.0;
+    o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM];
+  }
+  *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out) {
+  if (!h || inst < 0 || inst >= h->n || !out) return DQMC_EINVAL;
+  InstState st;
+  HIPCHK(h, hipMemcpyAsync(&st, h->hd[inst].st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  out->proposals = st.proposals;
+  out->accepted = st.accepted;
+  out->flushes = st.flushes;
+  out->sweeps = st.sweep;
+  out->drift_max = st.drift_max;
+  out->drift_last = st.drift_last;
+  out->numeric_err = st.numeric_err;
+  return DQMC_OK;
+}
+
+}  // extern "C"

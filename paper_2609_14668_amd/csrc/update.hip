@@ -1,0 +1,350 @@
+// Delayed-update Metropolis sweep of one time slice (Sec. III B, eqs.
+// DetailBalance, DRatio, rRatioLocal, DelayG0, DelayRatio, DelayRgenk,
+// FinalDelay).
+//
+// The chain of accept/reject decisions is sequential: every accepted flip
+// changes the diagonal of G seen by later sites.  It is split in windows of up
+// to 64 consecutive sites.  The window kernel (one workgroup per instance)
+// holds the current G restricted to the window,
+//     C = G_[0][w, w] - X[w, :fill] Y[:fill, w],
+// which is (G_[k-1])_{ww} of eq. DelayG0.  Proposals are scanned with a
+// wave-wide ballot: the ratios of all not-yet-decided sites are evaluated from
+// the current diagonal, and the first accepted site is taken, which is the
+// same decision sequence as visiting the sites one by one, because a rejection
+// changes nothing.  On acceptance the window parts of x_k = (Delta/r)
+// G_[k-1][:, i_k] and y_k = (1 - G_[k-1])[i_k, :] (eq. DelayRgenk) are
+// recorded and C is updated on the trailing block only (earlier sites of the
+// window are never read again).
+//
+// The expand kernel then forms the full-length x_k, y_k for the accepted
+// sites with the recursion of eq. DelayRgenk, in parallel over matrix rows
+// (for x) and columns (for y), appending them to X and Y.  When the fill
+// reaches the flush rank the MFMA GEMM applies G <- G - X Y (eq. FinalDelay).
+#include "common.hpp"
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace {
+
+constexpr int WMAX = 64;
+constexpr int WIN_THREADS = 256;
+
+// window coefficient layout (in units of S): [0, WMAX) c_k; then xw[k][a]; then yw[k][b]
+constexpr int WC_X = WMAX;
+constexpr int WC_Y = WMAX + WMAX * WMAX;
+
+template <typename S>
+__global__ void __launch_bounds__(WIN_THREADS)
+k_window(const InstDev* __restrict__ insts, int W, int replay) {
+  constexpr bool CX = ST<S>::is_complex;
+  const InstDev& d = insts[blockIdx.y];
+  InstState* st = d.st;
+  if (st->init_mode || st->idle) return;
+  const int N = d.N, M = d.M;
+  const int phase = st->phase;
+  const int up = sched_is_up(phase, M);
+  const int l = sched_slice(phase, M);
+  const int pass = up ? 0 : 1;
+  const int w0 = st->cursor;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (w0 >= N) {
+    if (tid == 0) { st->m_w = 0; st->wstart = N; st->wlen = 0; }
+    return;
+  }
+  const int wn = min(W, N - w0);
+  const int fill0 = st->fill;
+  const S* G = matp<S>(d, MAT_G);
+  const S* X = matp<S>(d, MAT_X);
+  const S* Y = matp<S>(d, MAT_Y);
+  S* wc = reinterpret_cast<S*>(d.wcoef);
+
+  __shared__ S C[WMAX][WMAX + 1];
+  __shared__ S Xw[16][WMAX];
+  __shared__ S Yw[16][WMAX];
+  __shared__ S xcol[WMAX], yrow[WMAX];
+  __shared__ int xs[WMAX];
+  __shared__ int sh_q, sh_mw;
+  __shared__ S sh_c;
+
+  // ---- C = G[w,w] - X[w,:fill0] Y[:fill0,w]
+  S acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    int a = lane, b = wave + 4 * q;
+    acc[q] = (a < wn && b < wn) ? G[(w0 + a) + (size_t)(w0 + b) * N] : ST<S>::zero();
+  }
+  for (int m0 = 0; m0 < fill0; m0 += 16) {
+    for (int e = tid; e < 16 * WMAX; e += WIN_THREADS) {
+      int mm = e / WMAX, a = e % WMAX;
+      bool ok = (m0 + mm < fill0) && a < wn;
+      Xw[mm][a] = ok ? X[(w0 + a) + (size_t)(m0 + mm) * N] : ST<S>::zero();
+      Yw[mm][a] = ok ? Y[(size_t)(m0 + mm) * N + w0 + a] : ST<S>::zero();
+    }
+    __syncthreads();
+    int mlim = min(16, fill0 - m0);
+    for (int mm = 0; mm < mlim; ++mm) {
+      S xv = Xw[mm][lane];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = acc[q] - xv * Yw[mm][wave + 4 * q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) C[lane][wave + 4 * q] = acc[q];
+  if (tid < WMAX) xs[tid] = tid < wn ? (int)d.fields[(size_t)(l - 1) * N + w0 + tid] : 1;
+  if (tid == 0) sh_mw = 0;
+  __syncthreads();
+
+  const double lam = d.lam;
+  const int64_t rpos = st->replay_pos;
+  int p = 0;
+  while (true) {
+    if (wave == 0) {
+      int q = lane;
+      bool cand = q < wn && q >= p;
+      bool acc_q = false;
+      double R = 0.0;
+      S r = ST<S>::one(), dl = ST<S>::zero();
+      if (cand) {
+        double x = (double)xs[q];
+        double delta = exp(-2.0 * lam * x) - 1.0;
+        dl = ST<S>::from_re(delta);
+        r = ST<S>::one() + dl * (ST<S>::one() - C[q][q]);
+        R = exp(2.0 * lam * x) * absq(r);
+        if (replay) acc_q = d.replay_bits[rpos + q] != 0;
+        else acc_q = site_uniform(d.seed, (uint64_t)st->sweep, pass, l, w0 + q) < R;
+        if (!(R == R) || R == 0.0 || R > 1e300) st->numeric_err = 1;
+      }
+      unsigned long long mask = __ballot(cand && acc_q);
+      int qstar = mask ? (__ffsll((long long)mask) - 1) : wn;
+      if (cand && q <= qstar && d.replay_ratio) d.replay_ratio[rpos + q] = R;
+      if (q == qstar && cand) {
+        sh_c = cdiv(dl, r);
+      }
+      if (lane == 0) sh_q = qstar;
+    }
+    __syncthreads();
+    const int qs = sh_q;
+    if (qs >= wn) break;
+    const int k = sh_mw;
+    const S cfac = sh_c;
+    if (tid < WMAX) {
+      int a = tid;
+      S xv = (a > qs && a < wn) ? C[a][qs] * cfac : ST<S>::zero();
+      S yv = (a > qs && a < wn) ? -C[qs][a] : ST<S>::zero();
+      xcol[a] = xv;
+      yrow[a] = yv;
+      wc[WC_X + k * WMAX + a] = xv;
+      wc[WC_Y + k * WMAX + a] = yv;
+    }
+    if (tid == 0) {
+      wc[k] = cfac;
+      d.acc_site[k] = qs;
+    }
+    __syncthreads();
+    // trailing-block rank-1 update C -= x y^T
+    const int span = wn - qs - 1;
+    for (int e = tid; e < span * span; e += WIN_THREADS) {
+      int a = qs + 1 + e % span, b = qs + 1 + e / span;
+      C[a][b] = C[a][b] - xcol[a] * yrow[b];
+    }
+    if (tid == 0) { xs[qs] = -xs[qs]; sh_mw = k + 1; }
+    p = qs + 1;
+    __syncthreads();
+  }
+  // write back flipped fields and counters
+  const int mw = sh_mw;
+  if (tid < wn) d.fields[(size_t)(l - 1) * N + w0 + tid] = (int8_t)xs[tid];
+  if (tid == 0) {
+    st->m_w = mw;
+    st->wstart = w0;
+    st->wlen = wn;
+    st->cursor = w0 + wn;
+    st->proposals += wn;
+    st->accepted += mw;
+    if (replay) st->replay_pos = rpos + wn;
+  }
+}
+
+// Full-length x_k, y_k for the accepted sites of the last window.
+template <typename S>
+__global__ void __launch_bounds__(64)
+k_expand(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  const InstState* st = d.st;
+  if (st->init_mode || st->idle) return;
+  const int mw = st->m_w;
+  if (mw == 0) return;
+  const int N = d.N;
+  const int j0 = blockIdx.x * 64;
+  if (j0 >= N) return;
+  const int lane = threadIdx.x;
+  const int j = j0 + lane;
+  const bool ok = j < N;
+  const int fill0 = st->fill, w0 = st->wstart, wn = st->wlen;
+  const S* G = matp<S>(d, MAT_G);
+  S* X = matp<S>(d, MAT_X);
+  S* Y = matp<S>(d, MAT_Y);
+  const S* wc = reinterpret_cast<const S*>(d.wcoef);
+
+  __shared__ S Gblk[WMAX][65];
+  __shared__ S ycf[256], xcf[256];
+  __shared__ int sites[WMAX];
+  for (int jj = 0; jj < 64; ++jj) {
+    int col = j0 + jj;
+    Gblk[lane][jj] = (lane < wn && col < N) ? G[(w0 + lane) + (size_t)col * N] : ST<S>::zero();
+  }
+  sites[lane] = lane < mw ? d.acc_site[lane] : 0;
+  __syncthreads();
+
+  for (int k = 0; k < mw; ++k) {
+    const int ik = sites[k];
+    const int gi = w0 + ik;
+    const int nm = fill0 + k;
+    // coefficients y_m[i_k] (for x) and x_m[i_k] (for y), m < fill0 + k
+    for (int m = lane; m < nm; m += 64) {
+      if (m < fill0) {
+        ycf[m] = Y[(size_t)m * N + gi];
+        xcf[m] = X[gi + (size_t)m * N];
+      } else {
+        int mp = m - fill0;
+        ycf[m] = wc[WC_Y + mp * WMAX + ik];
+        xcf[m] = wc[WC_X + mp * WMAX + ik];
+      }
+    }
+    __syncthreads();
+    if (ok) {
+      S s = G[j + (size_t)gi * N];
+      S t = -Gblk[ik][lane];
+      if (j == gi) t = t + ST<S>::one();
+      for (int m = 0; m < nm; ++m) {
+        s = s - X[j + (size_t)m * N] * ycf[m];
+        t = t + xcf[m] * Y[(size_t)m * N + j];
+      }
+      X[j + (size_t)nm * N] = wc[k] * s;
+      Y[(size_t)nm * N + j] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_bump(const InstDev* __restrict__ insts, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  InstState* st = insts[i].st;
+  if (st->init_mode || st->idle) return;
+  st->fill += st->m_w;
+  st->m_w = 0;
+}
+
+__global__ void k_flush_done(const InstDev* __restrict__ insts, int n, int any) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const InstDev& d = insts[i];
+  InstState* st = d.st;
+  if (st->init_mode || st->idle) return;
+  if (any ? st->fill > 0 : st->fill >= d.kflush) {
+    st->fill = 0;
+    st->flushes += 1;
+  }
+}
+
+__global__ void k_advance(const InstDev* __restrict__ insts, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const InstDev& d = insts[i];
+  InstState* st = d.st;
+  if (st->idle) return;
+  st->cursor = 0;
+  st->phase += 1;
+  if (st->phase >= 2 * d.M) {
+    st->phase = 0;
+    if (st->init_mode) st->idle = 1;
+    else {
+      double cnt = d.obs[2 * OBS_COUNT];
+      if (cnt > 0.0 && d.max_series > 0) {
+        double* row = d.series + (size_t)(st->sweep % d.max_series) * OBS_COUNT;
+        for (int k = 0; k < OBS_COUNT; ++k) row[k] = d.obs[OBS_COUNT + k] / cnt;
+      }
+      for (int k = 0; k < OBS_COUNT; ++k) d.obs[OBS_COUNT + k] = 0.0;
+      d.obs[2 * OBS_COUNT] = 0.0;
+      st->sweep += 1;
+    }
+  }
+}
+
+__global__ void k_init_state(const InstDev* __restrict__ insts, int n, int mode) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const InstDev& d = insts[i];
+  InstState* st = d.st;
+  st->cursor = 0;
+  st->fill = 0;
+  st->m_w = 0;
+  st->idle = 0;
+  st->init_mode = mode;
+  st->phase = mode ? d.M : 0;
+}
+
+__global__ void k_replay_reset(const InstDev* __restrict__ insts, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) insts[i].st->replay_pos = 0;
+}
+
+__global__ void k_reset_counters(const InstDev* __restrict__ insts, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  InstState* st = insts[i].st;
+  st->proposals = 0;
+  st->accepted = 0;
+  st->flushes = 0;
+  st->n_meas = 0;
+  st->drift_max = 0.0;
+  st->drift_last = 0.0;
+  st->series_base = st->sweep;
+}
+
+}  // namespace
+
+hipError_t launch_init_state(const InstDev* insts, int n_inst, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_reset(const InstDev* insts, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_reset, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(const InstDev* insts, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counters, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, int replay, hipStream_t s) {
+  if (W > WMAX) W = WMAX;
+  if (cplx_) hipLaunchKernelGGL(k_window<cplx>, dim3(1, n_inst), dim3(WIN_THREADS), 0, s, insts, W, replay);
+  else hipLaunchKernelGGL(k_window<double>, dim3(1, n_inst), dim3(WIN_THREADS), 0, s, insts, W, replay);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int W, hipStream_t s) {
+  (void)W;
+  dim3 grid((Nmax + 63) / 64, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_expand<cplx>, grid, dim3(64), 0, s, insts);
+  else hipLaunchKernelGGL(k_expand<double>, grid, dim3(64), 0, s, insts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bump, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush_done(const InstDev* insts, int n_inst, int any, hipStream_t s) {
+  hipLaunchKernelGGL(k_flush_done, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst, any);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const InstDev* insts, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);
+  return hipGetLastError();
+}

@@ -1,0 +1,139 @@
+"""GPU (HIP path, through the C ABI) against the CPU oracle on the same
+seeded inputs.  FP64 tolerances: single kernels 1e-13 (relative to the
+largest entry), whole sweeps in replay mode 1e-10 (max |dG|)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.dqmc import BitSource, Chain, Model, PhiloxSource, observables
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(descs):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_14668_amd import Simulation
+    return Simulation(descs)
+
+
+def _model(d):
+    return Model(d["L"], d["U"], d["beta"], d["dtau"], t=d["t"], theta1=d["theta1"], theta2=d["theta2"],
+                 n_stab=d["n_stab"])
+
+
+def _rand_g(N, cx, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((N, N))
+    if cx:
+        G = G + 1j * rng.standard_normal((N, N))
+    return G
+
+
+@pytest.mark.parametrize("L,th", [(3, (0, 0)), (4, (0, 0)), (6, (0.0, 0.0)), (12, (0, 0)), (4, (0.7, 2.1)),
+                                  (6, (np.pi / 2, np.pi)), (5, (0.3, 0.0)), (14, (0.0, 0.0))])
+def test_wrap_matches_dense_propagation(L, th):
+    d = workloads.desc(L, 3.7, 1.0, theta=th, n_stab=5)
+    sim = _sim([d])
+    m = _model(d)
+    N, M, cx = sim.shapes[0]
+    f = sim.fields(0)
+    for direction, sl in ((0, 1), (1, 3), (0, M)):
+        G = _rand_g(N, cx, L + sl)
+        sim.set_green(0, G)
+        sim.wrap(direction, sl)
+        out = sim.green(0)
+        B, Bi = m.B(0, f[sl - 1]), m.Binv(0, f[sl - 1])
+        ref = B @ G @ Bi if direction == 0 else Bi @ G @ B
+        assert np.abs(out - ref).max() / np.abs(ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("L,th,k", [(3, (0, 0), 8), (12, (0, 0), 32), (12, (0, 0), 96), (4, (0.5, 1.0), 16),
+                                    (9, (0.2, 0.9), 64)])
+def test_flush_matches_numpy(L, th, k):
+    d = workloads.desc(L, 3.7, 1.0, theta=th, n_stab=5, k=min(k, 192))
+    sim = _sim([d])
+    N, _, cx = sim.shapes[0]
+    G = _rand_g(N, cx, 1)
+    X = _rand_g(N, cx, 2)[:, :k] if k <= N else np.vstack([_rand_g(N, cx, 2)] * 1)[:, :k]
+    Y = _rand_g(N, cx, 3)[:k, :]
+    kk = X.shape[1]
+    Y = Y[:kk]
+    sim.set_green(0, G)
+    sim.flush_test(0, X, Y)
+    ref = G - X @ Y
+    assert np.abs(sim.green(0) - ref).max() / np.abs(ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("L,th,beta", [(3, (0, 0), 3.0), (4, (0.6, 1.3), 2.0), (6, (0, 0), 2.0)])
+def test_initial_green_matches_oracle(L, th, beta):
+    d = workloads.desc(L, 3.8, beta, theta=th, n_stab=10)
+    sim = _sim([d])
+    f = sim.fields(0)
+    m = _model(d)
+    ref = m.green_scratch(f, 0, 0)
+    assert np.abs(sim.green(0) - ref).max() < 1e-10
+    refd = m.green_scratch(f, 0, 1)
+    assert np.abs(sim.green(0, spin=1) - refd).max() < 1e-10
+
+
+def _replay_case(d, seed, p=0.4, sweeps=1, measure=False):
+    import torch
+    sim = _sim([d])
+    m = _model(d)
+    N, M, cx = sim.shapes[0]
+    f0 = workloads.random_fields(seed, M, N)
+    sim.set_fields(0, f0)
+    bits = workloads.accept_bits(seed + 1, sweeps * 2 * M * N, p)
+    tb = torch.from_numpy(bits).reshape(1, -1).cuda()
+    ratios = torch.zeros((1, bits.size), dtype=torch.float64, device="cuda")
+    sim.replay(tb, ratios, n_sweeps=sweeps, measure=measure)
+    ch = Chain(m, f0, sym_measure=bool(d["sym_measure"]))
+    src = BitSource(bits)
+    for _ in range(sweeps):
+        ch.sweep(src, measure=measure)
+    return sim, ch, ratios.cpu().numpy().ravel()
+
+
+@pytest.mark.parametrize("L,th,beta,k", [(3, (0, 0), 3.0, 8), (4, (0.7, 2.2), 2.0, 16), (6, (0, 0), 2.0, 24)])
+def test_replay_sweep_matches_oracle(L, th, beta, k):
+    d = workloads.desc(L, 3.8, beta, theta=th, k=k, n_stab=10)
+    sim, ch, ratios = _replay_case(d, 11)
+    assert np.array_equal(sim.fields(0), ch.fields)
+    assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
+    assert np.abs(sim.green(0, spin=1) - ch.G[1]).max() < 1e-10
+    assert np.abs(ratios - np.array(ch.ratios)).max() / np.abs(ch.ratios).max() < 1e-10
+    st = sim.stats(0)
+    assert st["accepted"] == ch.accepted and st["proposals"] == ch.proposals
+    assert st["drift_max"] < 1e-8
+
+
+def test_replay_measurements_match_oracle():
+    d = workloads.desc(3, 3.8, 3.0, k=8, n_stab=10, sym_measure=1)
+    sim, ch, _ = _replay_case(d, 21, measure=True, sweeps=2)
+    o = sim.measure(0)
+    assert o["n_meas"] == len(ch.samples)
+    for key, okey in (("D", "D"), ("ekin", "ekin"), ("e", "e"), ("Szz_G", "Szz_G"), ("Szz_dk", "Szz_dk"),
+                      ("m2", "m2"), ("n", "n")):
+        ref = np.mean([s[okey] for s in ch.samples])
+        assert abs(o[key] - ref) < 1e-10, key
+
+
+def test_philox_chain_matches_oracle():
+    d = workloads.desc(3, 3.8, 3.0, k=8, n_stab=10, seed=77)
+    sim = _sim([d])
+    m = _model(d)
+    f0 = sim.fields(0)
+    sim.sweep(1, measure=False)
+    ch = Chain(m, f0)
+    ch.sweep(PhiloxSource(77), measure=False)
+    assert np.array_equal(sim.fields(0), ch.fields)
+    assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
+
+
+def test_replay_larger_lattice():
+    d = workloads.desc(12, 3.7, 1.0, k=32, n_stab=10)
+    sim, ch, _ = _replay_case(d, 31, p=0.3)
+    assert np.array_equal(sim.fields(0), ch.fields)
+    assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
