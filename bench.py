@@ -1,0 +1,183 @@
+"""Throughput benchmark of the DQMC sweep on one MI355X.
+
+Workload (default): the L=18, beta t = 18 batch -- 64 twisted complex128
+chains (4 x 4 twist grid x 4 chains) plus 16 L=12 chains, U/t = 3.73,
+dtau = 0.1, all in one handle.  A step is one full sweep of every L=18 chain
+(the L=12 chains keep sweeping in the same launches).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload twist_L18]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads  # noqa: E402
+
+PEAK_FP64 = 78.6e12     # MI355X dense FP64 (vector and matrix), FLOP/s
+PEAK_HBM = 8.0e12       # MI355X HBM3E, B/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="twist_L18")
+    ap.add_argument("--k", type=int, default=None, help="flush rank override")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def make_descs(name, k=None):
+    if name == "twist_L18":
+        return workloads.twist_L18(k=k)
+    if name == "plain_L12":
+        return workloads.plain_L12()
+    if name == "plain_L3":
+        return workloads.plain_L3()
+    if name == "plain_L42":
+        return workloads.plain_L42()
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(descs, seconds):
+    """The CPU oracle as it stands, on one L=18 chain of the workload: time as
+    many slice-steps (wrap + sequential updates of one slice, plus the QR
+    recomputation every n_stab slices) as fit in about `seconds`, and scale to
+    proposals per second."""
+    from oracle.dqmc import Chain, Model, RandomSource
+    d = descs[0]
+    m = Model(d["L"], d["U"], d["beta"], d["dtau"], t=d["t"], theta1=d["theta1"], theta2=d["theta2"],
+              n_stab=d["n_stab"])
+    ch = Chain(m, workloads.random_fields(d["seed"], m.M, m.N))
+    src = RandomSource(d["seed"])
+    t0 = time.perf_counter()
+    slices = 0
+    props0 = ch.proposals
+    for l in range(1, m.M + 1):
+        ch.wrap_up(l)
+        ch.update_slice(l, 0, src)
+        if l % m.n_stab == 0:
+            ch.stabilise(l, measure=True)
+        slices += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    props = ch.proposals - props0
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": props / dt, "unit": "HS field updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d upward slice-steps of one L=%d chain (%d proposals, %.1f s), both spins dense"
+                      % (slices, d["L"], props, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the chains are independent and would be sharded "
+              "across GPUs with no communication; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2609_14668_amd import Simulation
+    descs = make_descs(a.workload, a.k)
+    sim = Simulation(descs)
+    n = len(descs)
+    Nmax = max(s[0] for s in sim.shapes)
+    Mmax = max(s[1] for s in sim.shapes)
+    print("workload %s: %d instances, Nmax %d, Mmax %d, complex %s" % (a.workload, n, Nmax, Mmax,
+                                                                      sim.shapes[0][2]), file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        sim.sweep(1, measure=True)
+        torch.cuda.synchronize()
+        print("warmup sweep %d done" % (w + 1), file=sys.stderr, flush=True)
+    sim.reset_obs()
+    st0 = [sim.stats(i) for i in range(n)]
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        sim.sweep(1, measure=True)
+        torch.cuda.synchronize()
+        print("timed sweep %d done (%.2f s)" % (s + 1, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = sim.timing()
+    sim.set_timing(False)
+    st1 = [sim.stats(i) for i in range(n)]
+    props = sum(st1[i]["proposals"] - st0[i]["proposals"] for i in range(n))
+    acc = sum(st1[i]["accepted"] - st0[i]["accepted"] for i in range(n))
+    sweeps = sum(st1[i]["sweeps"] - st0[i]["sweeps"] for i in range(n))
+    drift = max(s["drift_max"] for s in st1)
+    value = props / dt
+    # effective samples: pooled autocorrelation of the per-sweep m^2 series
+    ess_rate = None
+    try:
+        from oracle import stats as ostats  # the oracle's statistics helpers only
+        ser = [sim.series(i)["m2"] for i in range(n)]
+        ser = [x for x in ser if len(x) >= 4]
+        if ser:
+            L = min(len(x) for x in ser)
+            rho = np.mean([ostats.autocorr(x[-L:]) for x in ser], axis=0)
+            tau = 0.5
+            for W in range(1, L):
+                tau += rho[W]
+                if W >= 5 * tau:
+                    break
+            tau = max(tau, 0.5)
+            ess_rate = sweeps / dt / (2 * tau)
+    except Exception:
+        ess_rate = None
+    line = {
+        "metric": "HS field updates/s + effective samples/s at L=18,βt=18 (learned vs plain)",
+        "value": value,
+        "unit": "HS field updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / max(a.steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if sim.shapes[0][2] else "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
+                   "dtau": descs[0]["dtau"], "proposal": "plain"},
+        "ess_per_s": ess_rate,
+        "acceptance": acc / max(props, 1),
+        "drift_max": drift,
+    }
+    # roofline of the rank-k flush (FP64 MFMA GEMM, complex128 as 4 real products)
+    fl = tim["flush"]
+    if fl["ms"] > 0:
+        ach = tim["flush_flops"] / (fl["ms"] * 1e-3)
+        line["roofline"] = {"bound": "mfma", "kernel": "k_gemm (flush G -= X Y)", "achieved": ach / 1e12,
+                            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
+                            "traffic": None, "launches": fl["launches"],
+                            "avg_launch_us": 1e3 * fl["ms"] / max(fl["launches"], 1)}
+    wr = tim["wrap"]
+    if wr["ms"] > 0:
+        ach = tim["wrap_bytes"] / (wr["ms"] * 1e-3)
+        line["roofline_wrap"] = {"bound": "hbm", "kernel": "k_fft_apply (wrap)", "achieved": ach / 1e9,
+                                 "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                                 "traffic": None, "launches": wr["launches"],
+                                 "avg_launch_us": 1e3 * wr["ms"] / max(wr["launches"], 1)}
+    line["time_split_ms"] = {k: round(tim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab")}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(descs, a.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,23 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
                             int32_t* n_out);
 dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out);  /* synchronises */
 
+/* Live kernel timing with HIP events on the handle's stream.  While enabled,
+ * every launch of the classes below is bracketed by an event pair; times are
+ * summed when dqmc_get_timing synchronises.  Algorithmic work per class:
+ * flush = sum over flushes of c N^2 k (c = 2 real, 8 complex; k = rank),
+ * wrap = 2 N^2 s bytes per instance per side-pass (one read and one write of
+ * G, s = bytes per element). */
+typedef enum { DQMC_T_WRAP = 0, DQMC_T_WINDOW, DQMC_T_EXPAND, DQMC_T_FLUSH, DQMC_T_STAB, DQMC_T_MEASURE,
+               DQMC_T_COUNT } dqmc_timing_class;
+typedef struct {
+  int64_t launches[DQMC_T_COUNT];
+  double ms[DQMC_T_COUNT];
+  double flush_flops;   /* algorithmic FP64 flops of all timed flushes */
+  double wrap_bytes;    /* algorithmic HBM bytes of all timed wrap passes */
+} dqmc_timing;
+dqmc_status dqmc_set_timing(dqmc_handle h, int32_t on);   /* on: 1 enable (and reset), 0 disable */
+dqmc_status dqmc_get_timing(dqmc_handle h, dqmc_timing* out);  /* synchronises */
+
 /* Matrix dimension N, slices M and whether G is complex, for instance inst. */
 dqmc_status dqmc_shape(dqmc_handle h, int32_t inst, int32_t* N, int32_t* M, int32_t* is_complex);
 

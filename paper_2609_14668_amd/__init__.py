@@ -44,6 +44,14 @@ class Stats(ctypes.Structure):
                 ("numeric_err", ctypes.c_int32)]
 
 
+TIMING_CLASSES = ("wrap", "window", "expand", "flush", "stab", "measure")
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 6), ("ms", ctypes.c_double * 6),
+                ("flush_flops", ctypes.c_double), ("wrap_bytes", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "dqmc_workspace_size": [ctypes.POINTER(InstanceDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
@@ -63,6 +71,8 @@ _SIGS = {
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
     "dqmc_shape": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                    ctypes.POINTER(ctypes.c_int32)],
+    "dqmc_set_timing": [_P, ctypes.c_int32],
+    "dqmc_get_timing": [_P, ctypes.POINTER(Timing)],
     "dqmc_status_string": [ctypes.c_int32],
     "dqmc_last_error": [_P],
 }
@@ -245,3 +255,18 @@ class Simulation:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     stats = dqmc_get_stats
+
+    def dqmc_set_timing(self, on=True):
+        self._chk(self.lib.dqmc_set_timing(self.h, int(bool(on))), "set_timing")
+
+    set_timing = dqmc_set_timing
+
+    def dqmc_get_timing(self):
+        t = Timing()
+        self._chk(self.lib.dqmc_get_timing(self.h, ctypes.byref(t)), "get_timing")
+        out = {c: {"launches": t.launches[i], "ms": t.ms[i]} for i, c in enumerate(TIMING_CLASSES)}
+        out["flush_flops"] = t.flush_flops
+        out["wrap_bytes"] = t.wrap_bytes
+        return out
+
+    timing = dqmc_get_timing

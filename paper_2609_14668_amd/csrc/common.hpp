@@ -102,6 +102,7 @@ struct InstState {
   int32_t wstart, wlen;  // site range of the last window
   int32_t idle;          // 1: instance has finished its part of the initial stack build
   int32_t pad0;
+  int64_t flush_rank_sum;  // sum of the ranks of all flushes
   int64_t series_base;   // sweep index at the last reset of the estimators
 };
 
@@ -119,6 +120,8 @@ struct InstDev {
   int32_t kcap;             // capacity of X, Y (kflush + window)
   int32_t is_complex;
   int32_t sym_measure;
+  int32_t fft_fixed;        // 1: a compile-time FFT plan exists for L
+  int32_t pad_fft;
   double lam;               // HS coupling lambda
   double U, dtau, t;
   double theta1, theta2;

@@ -25,7 +25,7 @@
 namespace {
 
 constexpr int WINDOW = 64;
-constexpr int QR_NB = 32;
+constexpr int QR_NB = 16;
 constexpr int TRSM_ROWS = 32;
 constexpr int MAX_SERIES = 4096;
 constexpr int MAX_DELAY = 192;
@@ -157,7 +157,20 @@ struct dqmc_ctx {
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
   size_t lds_budget = 65536;
+  int rmax = 4;  // largest FFT radix over the instances
+  int kcap_max = 0;
+  std::vector<int> fixedL;   // distinct L with a compile-time FFT plan
+  bool any_generic = false;  // some L uses the runtime-plan FFT
   std::string err;
+  // live timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (class, index of start event)
+  int64_t t_launch[DQMC_T_COUNT] = {0};
+  double t_ms[DQMC_T_COUNT] = {0};
+  double wrap_bytes = 0;
+  std::vector<int64_t> rank_base;   // flush_rank_sum at timing reset
   int64_t sweeps_done = 0;
 };
 
@@ -177,6 +190,49 @@ dqmc_status fail(dqmc_ctx* h, dqmc_status s, const std::string& msg) {
 
 hipStream_t pick(dqmc_ctx* h, void* s) { return s ? (hipStream_t)s : h->stream; }
 
+// ---- live timing ---------------------------------------------------------------------------
+hipEvent_t next_event(dqmc_ctx* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+struct TimedScope {
+  dqmc_ctx* h;
+  hipStream_t s;
+  int cls;
+  size_t idx = 0;
+  bool on = false;
+  TimedScope(dqmc_ctx* h_, hipStream_t s_, int c) : h(h_), s(s_), cls(c) {
+    if (!h->timing) return;
+    idx = h->ev_used;
+    hipEvent_t a = next_event(h), b = next_event(h);
+    if (!a || !b) return;
+    on = hipEventRecord(a, s) == hipSuccess;
+  }
+  ~TimedScope() {
+    if (!on) return;
+    if (hipEventRecord(h->ev_pool[idx + 1], s) == hipSuccess) {
+      h->ev_marks.push_back({cls, idx});
+      h->t_launch[cls] += 1;
+    }
+  }
+};
+
+// Resolve recorded event pairs into summed times (caller synchronised).
+void drain_timing(dqmc_ctx* h) {
+  for (auto& m : h->ev_marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev_pool[m.second], h->ev_pool[m.second + 1]) == hipSuccess)
+      h->t_ms[m.first] += ms;
+  }
+  h->ev_marks.clear();
+  h->ev_used = 0;
+}
+
 // ---- launch helpers ----------------------------------------------------------------------
 struct Ctx {
   dqmc_ctx* h;
@@ -185,11 +241,13 @@ struct Ctx {
   void chk(hipError_t x) { if (e == hipSuccess && x != hipSuccess) e = x; }
   void fft(int op, int side, int mat, int j = 0) {
     FftArgs a{op, side, mat, j, 0, 0, 0, 0};
-    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, s));
+    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
+                   (int)h->fixedL.size(), h->any_generic, s));
   }
   void fft_explicit(int side, int mat, int pre, int tab, int post, int slice) {
     FftArgs a{FOP_EXPLICIT, side, mat, 0, pre, tab, post, slice};
-    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, s));
+    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
+                   (int)h->fixedL.size(), h->any_generic, s));
   }
   void gemm(GemmOperand A, GemmOperand B, GemmOperand C, GemmDim M, GemmDim N, GemmDim K,
             double alpha, double beta, int flags = 0) {
@@ -206,50 +264,28 @@ GemmOperand opnd(int id, int op, int ra = 0, int rb = 0, int ca = 0, int cb = 0)
 }
 GemmDim dim(int a, int b, int hi = 0) { return GemmDim{a, b, hi}; }
 
-// Blocked Householder QR of MAT_QA (explicit V and T blocks per panel).
+// Blocked Householder QR of MAT_QA: 16-column panels factored in registers,
+// each followed by the fused block-reflector update of the trailing columns.
 void qr_factor(Ctx& c) {
   const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
   for (int p = 0; p < npan; ++p) {
-    const int j0 = p * QR_NB;
-    c.chk(launch_qr_panel(c.h->dinst, c.h->n, c.h->cplx, p, QR_NB, c.s));
-    // W1 = V^H A[j0:, j0+nb:]
-    c.gemm(opnd(MAT_V, 2, 0, j0, 0, j0), opnd(MAT_QA, 0, 0, j0, 0, j0 + QR_NB), opnd(MAT_W1, 0),
-           dim(1, -j0, QR_NB), dim(1, -j0 - QR_NB), dim(1, -j0), 1.0, 0.0);
-    // W2 = T^H W1
-    c.gemm(opnd(MAT_TB, 2, 0, j0, 0, 0), opnd(MAT_W1, 0), opnd(MAT_W2, 0),
-           dim(1, -j0, QR_NB), dim(1, -j0 - QR_NB), dim(1, -j0, QR_NB), 1.0, 0.0);
-    // A[j0:, j0+nb:] -= V W2
-    c.gemm(opnd(MAT_V, 0, 0, j0, 0, j0), opnd(MAT_W2, 0), opnd(MAT_QA, 0, 0, j0, 0, j0 + QR_NB),
-           dim(1, -j0), dim(1, -j0 - QR_NB), dim(1, -j0, QR_NB), -1.0, 1.0);
+    c.chk(launch_qr_panel_reg(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, c.s));
+    c.chk(launch_apply_refl(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, MAT_QA, 0, 1, c.s));
   }
 }
 
 // target <- Q target (form Q when target = I), blocks applied last to first.
 void apply_q(Ctx& c, int target) {
   const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
-  for (int p = npan - 1; p >= 0; --p) {
-    const int j0 = p * QR_NB;
-    c.gemm(opnd(MAT_V, 2, 0, j0, 0, j0), opnd(target, 0, 0, j0, 0, j0), opnd(MAT_W1, 0),
-           dim(1, -j0, QR_NB), dim(1, -j0), dim(1, -j0), 1.0, 0.0);
-    c.gemm(opnd(MAT_TB, 0, 0, j0, 0, 0), opnd(MAT_W1, 0), opnd(MAT_W2, 0),
-           dim(1, -j0, QR_NB), dim(1, -j0), dim(1, -j0, QR_NB), 1.0, 0.0);
-    c.gemm(opnd(MAT_V, 0, 0, j0, 0, j0), opnd(MAT_W2, 0), opnd(target, 0, 0, j0, 0, j0),
-           dim(1, -j0), dim(1, -j0), dim(1, -j0, QR_NB), -1.0, 1.0);
-  }
+  for (int p = npan - 1; p >= 0; --p)
+    c.chk(launch_apply_refl(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, target, 1, 0, c.s));
 }
 
 // target <- Q^H target, blocks applied first to last, all columns.
 void apply_qh(Ctx& c, int target) {
   const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
-  for (int p = 0; p < npan; ++p) {
-    const int j0 = p * QR_NB;
-    c.gemm(opnd(MAT_V, 2, 0, j0, 0, j0), opnd(target, 0, 0, j0, 0, 0), opnd(MAT_W1, 0),
-           dim(1, -j0, QR_NB), dim(1, 0), dim(1, -j0), 1.0, 0.0);
-    c.gemm(opnd(MAT_TB, 2, 0, j0, 0, 0), opnd(MAT_W1, 0), opnd(MAT_W2, 0),
-           dim(1, -j0, QR_NB), dim(1, 0), dim(1, -j0, QR_NB), 1.0, 0.0);
-    c.gemm(opnd(MAT_V, 0, 0, j0, 0, j0), opnd(MAT_W2, 0), opnd(target, 0, 0, j0, 0, 0),
-           dim(1, -j0), dim(1, 0), dim(1, -j0, QR_NB), -1.0, 1.0);
-  }
+  for (int p = 0; p < npan; ++p)
+    c.chk(launch_apply_refl(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, target, 2, 1, c.s));
 }
 
 // MAT_W3 <- R^{-1} MAT_W3 with R the upper triangle of MAT_QA.
@@ -311,24 +347,62 @@ void stabilise(Ctx& c, bool measure) {
 }
 
 // One step of every instance (one slice of its sweep).
+// Bytes of one wrap side-pass over every instance that is in the given pass.
+double wrap_pass_bytes(dqmc_ctx* h, int64_t s, bool up) {
+  double b = 0;
+  const double ss = h->cplx ? 16.0 : 8.0;
+  for (auto& d : h->hd) {
+    int phase = (int)(s % (2 * d.M));
+    if ((phase < d.M) == up) b += 2.0 * ss * (double)d.N * d.N;
+  }
+  return b;
+}
+
 void step(Ctx& c, int64_t s, bool measure, int replay) {
   dqmc_ctx* h = c.h;
-  c.fft(FOP_WRAP_PRE, 0, MAT_G);
-  c.fft(FOP_WRAP_PRE, 1, MAT_G);
+  {
+    TimedScope t(h, c.s, DQMC_T_WRAP);
+    c.fft(FOP_WRAP_PRE, 0, MAT_G);
+  }
+  {
+    TimedScope t(h, c.s, DQMC_T_WRAP);
+    c.fft(FOP_WRAP_PRE, 1, MAT_G);
+  }
+  if (h->timing) h->wrap_bytes += 2 * wrap_pass_bytes(h, s, true);
   const int nwin = (h->Nmax + WINDOW - 1) / WINDOW;
   for (int w = 0; w < nwin; ++w) {
-    c.chk(launch_window(h->dinst, h->n, h->cplx, WINDOW, replay, c.s));
-    c.chk(launch_expand(h->dinst, h->n, h->Nmax, h->cplx, WINDOW, c.s));
-    c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
-           GF_K_FILL | GF_IF_FULL);
+    {
+      TimedScope t(h, c.s, DQMC_T_WINDOW);
+      c.chk(launch_window(h->dinst, h->n, h->cplx, WINDOW, replay, c.s));
+    }
+    {
+      TimedScope t(h, c.s, DQMC_T_EXPAND);
+      c.chk(launch_expand(h->dinst, h->n, h->Nmax, h->cplx, h->kcap_max, c.s));
+    }
+    {
+      TimedScope t(h, c.s, DQMC_T_FLUSH);
+      c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, GF_IF_FULL, c.s));
+    }
     c.chk(launch_flush_done(h->dinst, h->n, 0, c.s));
   }
-  c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
-         GF_K_FILL | GF_IF_ANY);
+  {
+    TimedScope t(h, c.s, DQMC_T_FLUSH);
+    c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, GF_IF_ANY, c.s));
+  }
   c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
-  c.fft(FOP_WRAP_POST, 0, MAT_G);
-  c.fft(FOP_WRAP_POST, 1, MAT_G);
-  if ((s + 1) % h->n_stab == 0) stabilise(c, measure);
+  {
+    TimedScope t(h, c.s, DQMC_T_WRAP);
+    c.fft(FOP_WRAP_POST, 0, MAT_G);
+  }
+  {
+    TimedScope t(h, c.s, DQMC_T_WRAP);
+    c.fft(FOP_WRAP_POST, 1, MAT_G);
+  }
+  if (h->timing) h->wrap_bytes += 2 * wrap_pass_bytes(h, s, false);
+  if ((s + 1) % h->n_stab == 0) {
+    TimedScope t(h, c.s, DQMC_T_STAB);
+    stabilise(c, measure);
+  }
   c.chk(launch_advance(h->dinst, h->n, c.s));
 }
 
@@ -401,6 +475,17 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
   h->n_stab = p.n_stab;
   h->desc.assign(d, d + n);
   h->plan = p;
+  for (int i = 0; i < n; ++i) {
+    std::vector<int> fac;
+    factor_L(d[i].L, fac);
+    for (int r : fac) h->rmax = std::max(h->rmax, r);
+    h->kcap_max = std::max(h->kcap_max, d[i].n_delay + WINDOW);
+    if (fft_has_fixed(d[i].L)) {
+      if (std::find(h->fixedL.begin(), h->fixedL.end(), d[i].L) == h->fixedL.end()) h->fixedL.push_back(d[i].L);
+    } else {
+      h->any_generic = true;
+    }
+  }
   h->ws = (char*)dev_ws;
   h->ws_bytes = bytes;
   h->stream = (hipStream_t)stream;
@@ -423,6 +508,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.kcap = x.n_delay + WINDOW;
     dv.is_complex = p.cplx;
     dv.sym_measure = x.sym_measure;
+    dv.fft_fixed = fft_has_fixed(x.L) ? 1 : 0;
     dv.lam = std::acosh(std::exp(x.dtau * x.U / 2.0));
     dv.U = x.U; dv.dtau = x.dtau; dv.t = x.t;
     dv.theta1 = x.theta1; dv.theta2 = x.theta2;
@@ -502,6 +588,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
 dqmc_status dqmc_destroy(dqmc_handle h) {
   if (!h) return DQMC_EINVAL;
   hipStreamSynchronize(h->stream);
+  for (auto e : h->ev_pool) hipEventDestroy(e);
   delete h;
   return DQMC_OK;
 }
@@ -643,8 +730,7 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X, c
   HIPCHK(h, hipMemcpyAsync(d.mat[MAT_Y], host_Y, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync((char*)d.st + offsetof(InstState, fill), &k, sizeof(int32_t), hipMemcpyHostToDevice, s));
   Ctx c{h, s};
-  c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
-         GF_K_FILL | GF_IF_ANY);
+  c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, GF_IF_ANY, s));
   c.chk(launch_flush_done(h->dinst, h->n, 1, s));
   if (c.e != hipSuccess) return fail(h, DQMC_EHIP, hipGetErrorString(c.e));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -707,6 +793,41 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
     o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM];
   }
   *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_timing(dqmc_handle h, int32_t on) {
+  if (!h) return DQMC_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->ev_marks.clear();
+  h->ev_used = 0;
+  for (int c = 0; c < DQMC_T_COUNT; ++c) { h->t_launch[c] = 0; h->t_ms[c] = 0; }
+  h->wrap_bytes = 0;
+  h->rank_base.assign(h->n, 0);
+  for (int i = 0; i < h->n; ++i) {
+    InstState st;
+    HIPCHK(h, hipMemcpy(&st, h->hd[i].st, sizeof(st), hipMemcpyDeviceToHost));
+    h->rank_base[i] = st.flush_rank_sum;
+  }
+  h->timing = on != 0;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_timing(dqmc_handle h, dqmc_timing* out) {
+  if (!h || !out) return DQMC_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  drain_timing(h);
+  std::memset(out, 0, sizeof(*out));
+  for (int c = 0; c < DQMC_T_COUNT; ++c) { out->launches[c] = h->t_launch[c]; out->ms[c] = h->t_ms[c]; }
+  double flops = 0;
+  for (int i = 0; i < h->n && i < (int)h->rank_base.size(); ++i) {
+    InstState st;
+    HIPCHK(h, hipMemcpy(&st, h->hd[i].st, sizeof(st), hipMemcpyDeviceToHost));
+    double N = h->hd[i].N;
+    flops += (h->cplx ? 8.0 : 2.0) * N * N * (double)(st.flush_rank_sum - h->rank_base[i]);
+  }
+  out->flush_flops = flops;
+  out->wrap_bytes = h->wrap_bytes;
   return DQMC_OK;
 }
 

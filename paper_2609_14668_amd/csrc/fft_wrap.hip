@@ -9,7 +9,7 @@
 //
 // One workgroup transforms nv vectors (columns, or rows) of one instance held
 // in LDS: optional diagonal, forward 2-D FFT on both sublattices (mixed-radix
-// Stockham, one radix per stage, in place with register staging), 2x2 block
+// Stockham, one radix per stage, ping-pong between two LDS buffers), 2x2 block
 // multiply per momentum, inverse 2-D FFT, optional diagonal, store.  Real
 // matrices pack two real vectors as one complex vector (the operator is real).
 // Rows are transformed with the transpose: E^T = conj(E) for Hermitian K, so a
@@ -20,7 +20,6 @@
 namespace {
 
 constexpr int FFT_THREADS = 256;
-constexpr int FFT_REGS = 16;  // complex values staged per thread per stage
 
 struct Resolved {
   int active, slice, pre, post, tab;
@@ -75,96 +74,159 @@ __device__ __forceinline__ cplx root_pow(const cplx* roots, int L, int m, int si
   return sign < 0 ? w : conjg(w);
 }
 
-// One Stockham stage of radix R on all lines of the nv vectors in LDS.
+// Radix-R DFT of v in place: y_s = sum_r v_r w^{rs}, w = exp(sign 2 pi i / R).
 template <int R>
-__device__ void fft_stage(cplx* buf, const cplx* roots, int L, int Nc, int N, int nv,
-                          int axis, int Ns, int sign) {
-  constexpr int MAXB = (FFT_REGS + R - 1) / R;
+__device__ __forceinline__ void small_dft(cplx* v, const cplx* roots, int L, int sign) {
+  if constexpr (R == 2) {
+    cplx a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R == 4) {
+    cplx x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
+    cplx s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
+    // w = sign * i: w * z = (-sign * z.y, sign * z.x)
+    cplx wd13 = cmake(-sign * d13.y, sign * d13.x);
+    v[0] = s02 + s13;
+    v[1] = d02 + wd13;
+    v[2] = s02 - s13;
+    v[3] = d02 - wd13;
+  } else if constexpr (R == 3) {
+    const double c = -0.5, sn = 0.86602540378443864676 * sign;  // w = (c, sn)
+    cplx x0 = v[0], x1 = v[1], x2 = v[2];
+    cplx t = x1 + x2, u = x1 - x2;
+    cplx m = x0 + c * t;
+    cplx ju = cmake(-sn * u.y, sn * u.x);  // i * sn * u
+    v[0] = x0 + t;
+    v[1] = m + ju;
+    v[2] = m - ju;
+  }
+}
+
+// One Stockham stage of radix R on all lines of the nv vectors: src -> dst.
+template <int R>
+__device__ void fft_stage(const cplx* __restrict__ src, cplx* __restrict__ dst, const cplx* roots, int L,
+                          int Nc, int N, int nv, int axis, int Ns, int sign) {
   const int per_line = L / R;
-  const int nlines = nv * 2 * L;
-  const int nb = nlines * per_line;
+  const int nb = nv * 2 * L * per_line;
   const int estride = axis == 0 ? 1 : L;
   const int ostride = axis == 0 ? L : 1;
-  cplx v[MAXB][R];
-  int dst[MAXB];
+  const int twstep = L / (Ns * R);
+  for (int b = threadIdx.x; b < nb; b += FFT_THREADS) {
+    int line = b / per_line, j = b - line * per_line;
+    int vv = line / (2 * L);
+    int rem = line - vv * 2 * L;
+    int s = rem / L, o = rem - s * L;
+    int base = vv * N + s * Nc + o * ostride;
+    int jm = j % Ns;
+    int tw = twstep * jm;
+    cplx v[R];
 #pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    int b = threadIdx.x + q * FFT_THREADS;
-    dst[q] = -1;
-    if (b < nb) {
-      int line = b / per_line, j = b - line * per_line;
-      int vv = line / (2 * L);
-      int rem = line - vv * 2 * L;
-      int s = rem / L, o = rem - s * L;
-      int base = vv * N + s * Nc + o * ostride;
-      int jm = j % Ns;
-      int tw = (L / (Ns * R)) * jm;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        cplx x = buf[base + (j + r * per_line) * estride];
-        v[q][r] = r ? x * root_pow(roots, L, tw * r, sign) : x;
-      }
-      // R-point DFT
-      cplx out[R];
-#pragma unroll
-      for (int s2 = 0; s2 < R; ++s2) {
-        cplx acc = v[q][0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) acc = acc + v[q][r] * root_pow(roots, L, (L / R) * ((r * s2) % R), sign);
-        out[s2] = acc;
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = out[r];
-      dst[q] = base + ((j / Ns) * Ns * R + jm) * estride;
+    for (int r = 0; r < R; ++r) {
+      cplx x = src[base + (j + r * per_line) * estride];
+      v[r] = (r && tw) ? x * root_pow(roots, L, tw * r, sign) : x;
     }
-  }
-  __syncthreads();
+    int d0 = base + ((j / Ns) * Ns * R + jm) * estride;
+    if constexpr (R <= 4) {
+      small_dft<R>(v, roots, L, sign);
 #pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    if (dst[q] >= 0) {
-      int ostep = (axis == 0 ? 1 : L);
-      // outputs of one butterfly are Ns apart along the line
+      for (int r = 0; r < R; ++r) dst[d0 + r * Ns * estride] = v[r];
+    } else {
+      // y_s = sum_r v_r w^{rs}, one output at a time (w^s from the root table)
+#pragma unroll 1
+      for (int s2 = 0; s2 < R; ++s2) {
+        const cplx step = s2 ? root_pow(roots, L, (L / R) * s2, sign) : cmake(1.0, 0.0);
+        cplx w = step, acc = v[0];
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[q] + r * Ns * ostep] = v[q][r];
+        for (int r = 1; r < R; ++r) {
+          acc = acc + v[r] * w;
+          w = w * step;
+        }
+        dst[d0 + s2 * Ns * estride] = acc;
+      }
     }
   }
   __syncthreads();
 }
 
-__device__ void fft_2d(cplx* buf, const cplx* roots, const int* fac, int L, int Nc, int N,
-                       int nv, int sign) {
+// Largest radix a kernel instance supports; the host picks the smallest set
+// that covers the factors of every instance's L.  Ping-pongs between the two
+// LDS buffers; returns the buffer that holds the result.
+template <int RMAX>
+__device__ cplx* fft_2d(cplx* cur, cplx* other, const cplx* roots, const int* fac, int L, int Nc, int N,
+                        int nv, int sign) {
   for (int axis = 0; axis < 2; ++axis) {
     int Ns = 1;
     for (int f = 0; fac[f]; ++f) {
       int R = fac[f];
       switch (R) {
-        case 2: fft_stage<2>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
-        case 3: fft_stage<3>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
-        case 4: fft_stage<4>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
-        case 5: fft_stage<5>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
-        case 7: fft_stage<7>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
-        case 11: fft_stage<11>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
-        case 13: fft_stage<13>(buf, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 2: fft_stage<2>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 3: fft_stage<3>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 4: fft_stage<4>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 5: if constexpr (RMAX >= 5) fft_stage<5>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 7: if constexpr (RMAX >= 7) fft_stage<7>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 11: if constexpr (RMAX >= 11) fft_stage<11>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
+        case 13: if constexpr (RMAX >= 13) fft_stage<13>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
         default: break;  // rejected on the host
       }
+      cplx* t = cur; cur = other; other = t;
       Ns *= R;
     }
   }
+  return cur;
 }
 
-template <typename S>
+// ---- compile-time plans for the common lattice sizes ------------------------------------
+// Same radix order as the host: 4s, then 2, 3, 5, 7, 11, 13.
+constexpr int fac_count(int L) {
+  int c = 0, n = L;
+  while (n % 4 == 0) { n /= 4; ++c; }
+  while (n % 2 == 0) { n /= 2; ++c; }
+  for (int p : {3, 5, 7, 11, 13})
+    while (n % p == 0) { n /= p; ++c; }
+  return c;
+}
+constexpr int fac_at(int L, int i) {
+  int c = 0, n = L;
+  while (n % 4 == 0) { if (c == i) return 4; n /= 4; ++c; }
+  while (n % 2 == 0) { if (c == i) return 2; n /= 2; ++c; }
+  for (int p : {3, 5, 7, 11, 13})
+    while (n % p == 0) { if (c == i) return p; n /= p; ++c; }
+  return 0;
+}
+
+template <int L, int AXIS, int I, int NS>
+__device__ __forceinline__ void fixed_stages(cplx*& cur, cplx*& other, const cplx* roots, int nv, int sign) {
+  if constexpr (I < fac_count(L)) {
+    constexpr int R = fac_at(L, I);
+    fft_stage<R>(cur, other, roots, L, L * L, 2 * L * L, nv, AXIS, NS, sign);
+    cplx* t = cur; cur = other; other = t;
+    fixed_stages<L, AXIS, I + 1, NS * R>(cur, other, roots, nv, sign);
+  }
+}
+
+template <int L>
+__device__ __forceinline__ cplx* fft_2d_fixed(cplx* cur, cplx* other, const cplx* roots, int nv, int sign) {
+  fixed_stages<L, 0, 0, 1>(cur, other, roots, nv, sign);
+  fixed_stages<L, 1, 0, 1>(cur, other, roots, nv, sign);
+  return cur;
+}
+
+template <typename S, int RMAX, int LC>
 __global__ void __launch_bounds__(FFT_THREADS)
-k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv) {
+k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_only) {
   extern __shared__ char smem_raw[];
   const InstDev& d = insts[blockIdx.y];
+  if (LC > 0 ? d.L != LC : (generic_only && d.fft_fixed)) return;
   Resolved rs = resolve(d, a);
   if (!rs.active) return;
-  const int N = d.N, Nc = d.Nc, L = d.L;
+  const int L = LC > 0 ? LC : d.L;
+  const int Nc = L * L, N = 2 * Nc;
   const int nvec = ST<S>::is_complex ? N : N / 2;
   const int v0 = blockIdx.x * nv;
   if (v0 >= nvec) return;
   const int nvl = min(nv, nvec - v0);
   cplx* buf = reinterpret_cast<cplx*>(smem_raw);
+  cplx* buf2 = buf + (size_t)nv * N;
   __shared__ cplx roots[64];
   __shared__ int fac[16];
   __shared__ double dpre[1], dpost[1];
@@ -173,7 +235,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv) {
   if (threadIdx.x < 16) fac[threadIdx.x] = d.factors[threadIdx.x];
   S* Mx = matp<S>(d, a.mat);
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
-  const double lam = d.lam;
+  const double ep = exp(d.lam), em = exp(-d.lam);
   const bool rows = a.side != 0;
   // load (+ pre diagonal)
   const int tot = nvl * N;
@@ -190,30 +252,34 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv) {
       if (!rows) val = cmake(Mx[(size_t)(2 * q) * N + r], Mx[(size_t)(2 * q + 1) * N + r]);
       else val = cmake(Mx[(size_t)r * N + 2 * q], Mx[(size_t)r * N + 2 * q + 1]);
     }
-    if (rs.pre) val = val * exp(rs.pre * lam * (double)xs[r]);
+    if (rs.pre) val = val * ((rs.pre * xs[r]) > 0 ? ep : em);
     buf[vv * N + r] = val;
   }
   __syncthreads();
-  fft_2d(buf, roots, fac, L, Nc, N, nvl, -1);
+  cplx* cur;
+  if constexpr (LC > 0) cur = fft_2d_fixed<LC>(buf, buf2, roots, nvl, -1);
+  else cur = fft_2d<RMAX>(buf, buf2, roots, fac, L, Nc, N, nvl, -1);
+  cplx* oth = cur == buf ? buf2 : buf;
   // 2x2 block per momentum
   const cplx* T = d.tab + (size_t)rs.tab * Nc * 4;
   for (int e = threadIdx.x; e < nvl * Nc; e += FFT_THREADS) {
     int vv = e / Nc, k = e - vv * Nc;
-    cplx qa = buf[vv * N + k], qb = buf[vv * N + Nc + k];
+    cplx qa = cur[vv * N + k], qb = cur[vv * N + Nc + k];
     cplx t00 = T[4 * k], t01 = T[4 * k + 1], t10 = T[4 * k + 2], t11 = T[4 * k + 3];
-    buf[vv * N + k] = t00 * qa + t01 * qb;
-    buf[vv * N + Nc + k] = t10 * qa + t11 * qb;
+    cur[vv * N + k] = t00 * qa + t01 * qb;
+    cur[vv * N + Nc + k] = t10 * qa + t11 * qb;
   }
   __syncthreads();
-  fft_2d(buf, roots, fac, L, Nc, N, nvl, +1);
+  if constexpr (LC > 0) cur = fft_2d_fixed<LC>(cur, oth, roots, nvl, +1);
+  else cur = fft_2d<RMAX>(cur, oth, roots, fac, L, Nc, N, nvl, +1);
   // store (+ post diagonal)
   for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
     int vv, r;
     if (!rows) { vv = e / N; r = e - vv * N; }
     else { vv = e % nvl; r = e / nvl; }
     int q = v0 + vv;
-    cplx val = buf[vv * N + r];
-    if (rs.post) val = val * exp(rs.post * lam * (double)xs[r]);
+    cplx val = cur[vv * N + r];
+    if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
     if constexpr (ST<S>::is_complex) {
       if (rows) Mx[(size_t)r * N + q] = conjg(val);
       else Mx[(size_t)q * N + r] = val;
@@ -227,20 +293,65 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv) {
 }  // namespace
 
 int fft_vectors_per_block(int N, size_t lds_budget) {
-  int nv = (int)(lds_budget / ((size_t)N * sizeof(cplx)));
-  int cap = (FFT_THREADS * FFT_REGS) / N;
-  if (nv > cap) nv = cap;
+  // two ping-pong buffers of nv vectors
+  int nv = (int)(lds_budget / (2 * (size_t)N * sizeof(cplx)));
   if (nv > 16) nv = 16;
   return nv < 1 ? 1 : nv;
 }
 
+// Lattice sizes with a compile-time plan (the paper's sizes and their
+// neighbours); other L run the runtime-plan kernel.
+#define DQMC_FIXED_L(X) X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(15) X(16) X(18) X(21) X(24) X(27) \
+  X(30) X(32) X(33) X(36) X(39) X(42)
+
+bool fft_has_fixed(int L) {
+  switch (L) {
+#define DQMC_CASE(v) case v:
+    DQMC_FIXED_L(DQMC_CASE)
+#undef DQMC_CASE
+    return true;
+    default: return false;
+  }
+}
+
+namespace {
+template <typename S, int LC>
+void launch_fixed(const InstDev* insts, int n_inst, const FftArgs& a, size_t lds_budget, hipStream_t s) {
+  constexpr int N = 2 * LC * LC;
+  int nv = fft_vectors_per_block(N, lds_budget);
+  int nvec = ST<S>::is_complex ? N : N / 2;
+  dim3 grid((nvec + nv - 1) / nv, n_inst);
+  size_t lds = 2 * (size_t)nv * N * sizeof(cplx);
+  constexpr int R = (fac_count(LC) > 0) ? 13 : 13;  // unused by the fixed path
+  hipLaunchKernelGGL((k_fft_apply<S, R, LC>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 0);
+}
+}  // namespace
+
 hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, const FftArgs& a,
-                      size_t lds_budget, hipStream_t s) {
+                      size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, hipStream_t s) {
+  for (int q = 0; q < nL; ++q) {
+    switch (Ls[q]) {
+#define DQMC_CASE(v)                                                          \
+  case v:                                                                     \
+    if (cplx_) launch_fixed<cplx, v>(insts, n_inst, a, lds_budget, s);        \
+    else launch_fixed<double, v>(insts, n_inst, a, lds_budget, s);            \
+    break;
+      DQMC_FIXED_L(DQMC_CASE)
+#undef DQMC_CASE
+      default: break;
+    }
+  }
+  if (!any_generic) return hipGetLastError();
   int nv = fft_vectors_per_block(Nmax, lds_budget);
   int nvec = cplx_ ? Nmax : Nmax / 2;
   dim3 grid((nvec + nv - 1) / nv, n_inst);
-  size_t lds = (size_t)nv * Nmax * sizeof(cplx);
-  if (cplx_) hipLaunchKernelGGL(k_fft_apply<cplx>, grid, dim3(FFT_THREADS), lds, s, insts, a, nv);
-  else hipLaunchKernelGGL(k_fft_apply<double>, grid, dim3(FFT_THREADS), lds, s, insts, a, nv);
+  size_t lds = 2 * (size_t)nv * Nmax * sizeof(cplx);
+#define DQMC_FFT_LAUNCH(R)                                                                                         \
+  if (cplx_) hipLaunchKernelGGL((k_fft_apply<cplx, R, 0>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);   \
+  else hipLaunchKernelGGL((k_fft_apply<double, R, 0>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);
+  if (rmax <= 4) { DQMC_FFT_LAUNCH(4) }
+  else if (rmax <= 7) { DQMC_FFT_LAUNCH(7) }
+  else { DQMC_FFT_LAUNCH(13) }
+#undef DQMC_FFT_LAUNCH
   return hipGetLastError();
 }

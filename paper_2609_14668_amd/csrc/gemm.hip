@@ -69,48 +69,99 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
   const int tm = (M + BM - 1) / BM, tn = (NC + BN - 1) / BN;
   const int ntiles = tm * tn;
 
+  // global -> register staging of one BK chunk (4 values of op(A), 4 of op(B) per thread)
+  double ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+  auto load_chunk = [&](int m0, int n0, int k0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int i, kk;
+      if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
+      else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
+      int gi = m0 + i, gk = k0 + kk;
+      double re = 0.0, im = 0.0;
+      if (gi < M && gk < K && !(a_upper && gi > gk)) {
+        S v = A.op == 0 ? pa[gi + (size_t)gk * ld] : pa[gk + (size_t)gi * ld];
+        split<S>(v, re, im);
+        if (A.op == 2) im = -im;
+      }
+      ra_r[p] = re;
+      ra_i[p] = im;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int j, kk;
+      if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
+      else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
+      int gj = n0 + j, gk = k0 + kk;
+      double re = 0.0, im = 0.0;
+      if (gj < NC && gk < K) {
+        S v = B.op == 0 ? pb[gk + (size_t)gj * ld] : pb[gj + (size_t)gk * ld];
+        split<S>(v, re, im);
+        if (B.op == 2) im = -im;
+      }
+      rb_r[p] = re;
+      rb_i[p] = im;
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int i, kk;
+      if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
+      else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
+      Ar[kk][i] = ra_r[p];
+      if constexpr (CX) Ai[kk][i] = ra_i[p];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int j, kk;
+      if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
+      else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
+      Br[kk][j] = rb_r[p];
+      if constexpr (CX) Bi[kk][j] = rb_i[p];
+    }
+  };
+
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int m0 = (tile % tm) * BM, n0 = (tile / tm) * BN;
+    // accumulators hold transposed 16x16 blocks: operands are fed as (B, A) so
+    // that a lane owns 4 columns of one row and stores coalesce along columns
     d4 acc_r[2][2], acc_i[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) { acc_r[i][j] = d4{0, 0, 0, 0}; acc_i[i][j] = d4{0, 0, 0, 0}; }
 
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      // ---- stage op(A)[m0:m0+64, k0:k0+16] as [k][i]
-      for (int p = 0; p < 4; ++p) {
-        int i, kk;
-        if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
-        else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
-        int gi = m0 + i, gk = k0 + kk;
-        double re = 0.0, im = 0.0;
-        if (gi < M && gk < K && !(a_upper && gi > gk)) {
-          S v = A.op == 0 ? pa[gi + (size_t)gk * ld] : pa[gk + (size_t)gi * ld];
-          split<S>(v, re, im);
-          if (A.op == 2) im = -im;
-        }
-        Ar[kk][i] = re;
-        if constexpr (CX) Ai[kk][i] = im;
-      }
-      // ---- stage op(B)[k0:k0+16, n0:n0+64] as [k][j]
-      for (int p = 0; p < 4; ++p) {
-        int j, kk;
-        if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
-        else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
-        int gj = n0 + j, gk = k0 + kk;
-        double re = 0.0, im = 0.0;
-        if (gj < NC && gk < K) {
-          S v = B.op == 0 ? pb[gk + (size_t)gj * ld] : pb[gj + (size_t)gk * ld];
-          split<S>(v, re, im);
-          if (B.op == 2) im = -im;
-        }
-        Br[kk][j] = re;
-        if constexpr (CX) Bi[kk][j] = im;
-      }
-      __syncthreads();
+    // For C = alpha (op(A) op(B)) + beta C the accumulators start at
+    // (beta/alpha) C, loaded before the K loop so that the read of C overlaps
+    // the products; the result is alpha * acc.
+    const double cscale = (beta != 0.0 && alpha != 0.0) ? beta / alpha : 0.0;
+    if (cscale != 0.0) {
 #pragma unroll
-      for (int ks = 0; ks < BK / 4; ++ks) {
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int gi = m0 + wr + ti * 16 + (lane & 15);
+            int gj = n0 + wc + tj * 16 + (lane >> 4) + 4 * r;
+            if (gi < M && gj < NC) {
+              double re, im;
+              split<S>(pc[gi + (size_t)gj * ld], re, im);
+              acc_r[ti][tj][r] = cscale * re;
+              acc_i[ti][tj][r] = cscale * im;
+            }
+          }
+    }
+    // upper-triangular op(A): chunks with k < m0 contribute nothing
+    const int kbeg = a_upper ? (m0 / BK) * BK : 0;
+    if (kbeg < K) load_chunk(m0, n0, kbeg);
+    for (int k0 = kbeg; k0 < K; k0 += BK) {
+      store_chunk();
+      __syncthreads();
+      if (k0 + BK < K) load_chunk(m0, n0, k0 + BK);
+      const int ksn = min(BK, K - k0 + 3) / 4;
+      for (int ks = 0; ks < ksn; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         double ar[2], br[2], ai[2], bi[2];
 #pragma unroll
@@ -126,37 +177,139 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
         for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
           for (int tj = 0; tj < 2; ++tj) {
-            acc_r[ti][tj] = mfma(ar[ti], br[tj], acc_r[ti][tj]);
+            acc_r[ti][tj] = mfma(br[tj], ar[ti], acc_r[ti][tj]);
             if constexpr (CX) {
-              acc_r[ti][tj] = mfma(-ai[ti], bi[tj], acc_r[ti][tj]);
-              acc_i[ti][tj] = mfma(ar[ti], bi[tj], acc_i[ti][tj]);
-              acc_i[ti][tj] = mfma(ai[ti], br[tj], acc_i[ti][tj]);
+              acc_r[ti][tj] = mfma(-bi[tj], ai[ti], acc_r[ti][tj]);
+              acc_i[ti][tj] = mfma(bi[tj], ar[ti], acc_i[ti][tj]);
+              acc_i[ti][tj] = mfma(br[tj], ai[ti], acc_i[ti][tj]);
             }
           }
       }
       __syncthreads();
     }
-    // ---- epilogue: lane holds rows lane/16 + 4 r, column lane%16 of each 16x16 tile
-    //      (v_mfma_f64_16x16x4f64 output layout, checked on the device)
+    // ---- epilogue.  v_mfma_f64_16x16x4f64 leaves D[l/16 + 4r][l%16] in lane l
+    //      (layout checked on the device); with operands swapped that is
+    //      C[row = l%16][col = l/16 + 4r] of the block.
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          int gi = m0 + wr + ti * 16 + (lane >> 4) + 4 * r;
-          int gj = n0 + wc + tj * 16 + (lane & 15);
+          int gi = m0 + wr + ti * 16 + (lane & 15);
+          int gj = n0 + wc + tj * 16 + (lane >> 4) + 4 * r;
           if (gi < M && gj < NC) {
             S* cp = pc + gi + (size_t)gj * ld;
             if constexpr (CX) {
               cplx v = cmake(alpha * acc_r[ti][tj][r], alpha * acc_i[ti][tj][r]);
-              if (beta != 0.0) v = v + beta * (*cp);
+              if (beta != 0.0 && cscale == 0.0) v = v + beta * (*cp);
               *cp = v;
             } else {
               double v = alpha * acc_r[ti][tj][r];
-              if (beta != 0.0) v += beta * (*cp);
+              if (beta != 0.0 && cscale == 0.0) v += beta * (*cp);
               *cp = v;
             }
+          }
+        }
+  }
+}
+
+// Flush without LDS: G <- G - X Y with X column-major N x K (op N) and Y
+// stored as Y[m, j] at m*N + j (op T on a column-major N x K buffer).  Each
+// wave owns a 32 x 32 block of G and reads its MFMA fragments straight from
+// memory: lane l needs X[i0 + l%16, k + l/16] and Y[k + l/16, j0 + l%16], i.e.
+// 16 consecutive elements per k, so every fragment load is coalesced and no
+// barrier is needed.  The next k-step's fragments are loaded while the
+// current one is multiplied.
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_flush_direct(const InstDev* __restrict__ insts, int flags) {
+  constexpr bool CX = ST<S>::is_complex;
+  const InstDev& d = insts[blockIdx.y];
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return;
+  if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
+  if ((flags & GF_IF_ANY) && st.fill <= 0) return;
+  const int N = d.N;
+  const int K = st.fill;
+  const S* X = reinterpret_cast<const S*>(d.mat[MAT_X]);
+  const S* Y = reinterpret_cast<const S*>(d.mat[MAT_Y]);
+  S* G = reinterpret_cast<S*>(d.mat[MAT_G]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb32 = (N + 31) / 32;
+  const int nblk = nb32 * nb32;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+    const int i0 = (blk % nb32) * 32, j0 = (blk / nb32) * 32;
+    d4 ar_[2][2], ai_[2][2];   // [ti][tj] accumulators (transposed blocks)
+    // start from -G (alpha = -1): acc = X Y - G, G_new = -acc
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int gi = i0 + ti * 16 + lr, gj = j0 + tj * 16 + lk + 4 * r;
+          double re = 0.0, im = 0.0;
+          if (gi < N && gj < N) split<S>(G[gi + (size_t)gj * N], re, im);
+          ar_[ti][tj][r] = -re;
+          ai_[ti][tj][r] = -im;
+        }
+    auto frag = [&](int k, double (&xr)[2], double (&xi)[2], double (&yr)[2], double (&yi)[2]) {
+      const int kk = k + lk;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        int gi = i0 + t * 16 + lr, gj = j0 + t * 16 + lr;
+        double a = 0, b = 0, c = 0, e = 0;
+        if (kk < K) {
+          if (gi < N) split<S>(X[gi + (size_t)kk * N], a, b);
+          if (gj < N) split<S>(Y[(size_t)kk * N + gj], c, e);
+        }
+        xr[t] = a; xi[t] = b; yr[t] = c; yi[t] = e;
+      }
+    };
+    // fragments two k-steps ahead; independent accumulators interleaved so
+    // that no MFMA waits on the one just issued
+    double xr[2], xi[2], yr[2], yi[2], nxr[2], nxi[2], nyr[2], nyi[2];
+    frag(0, xr, xi, yr, yi);
+    frag(4, nxr, nxi, nyr, nyi);
+    for (int k = 0; k < K; k += 4) {
+      double mxr[2], mxi[2], myr[2], myi[2];
+      frag(k + 8, mxr, mxi, myr, myi);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) ar_[ti][tj] = mfma(yr[tj], xr[ti], ar_[ti][tj]);
+      if constexpr (CX) {
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma(yi[tj], xr[ti], ai_[ti][tj]);
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) ar_[ti][tj] = mfma(-yi[tj], xi[ti], ar_[ti][tj]);
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma(yr[tj], xi[ti], ai_[ti][tj]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        xr[t] = nxr[t]; xi[t] = nxi[t]; yr[t] = nyr[t]; yi[t] = nyi[t];
+        nxr[t] = mxr[t]; nxi[t] = mxi[t]; nyr[t] = myr[t]; nyi[t] = myi[t];
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int gi = i0 + ti * 16 + lr, gj = j0 + tj * 16 + lk + 4 * r;
+          if (gi < N && gj < N) {
+            if constexpr (CX) G[gi + (size_t)gj * N] = cmake(-ar_[ti][tj][r], -ai_[ti][tj][r]);
+            else G[gi + (size_t)gj * N] = -ar_[ti][tj][r];
           }
         }
   }
@@ -176,5 +329,16 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
   dim3 grid(gx, n_inst);
   if (cplx_) hipLaunchKernelGGL(k_gemm<cplx>, grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
   else hipLaunchKernelGGL(k_gemm<double>, grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int flags, hipStream_t s) {
+  int nb32 = (Nmax + 31) / 32;
+  int blocks = (nb32 * nb32 + 3) / 4;
+  int cap = 8192 / (n_inst > 0 ? n_inst : 1);
+  if (cap < 16) cap = 16;
+  dim3 grid(blocks < cap ? blocks : cap, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_flush_direct<cplx>, grid, dim3(256), 0, s, insts, flags);
+  else hipLaunchKernelGGL(k_flush_direct<double>, grid, dim3(256), 0, s, insts, flags);
   return hipGetLastError();
 }

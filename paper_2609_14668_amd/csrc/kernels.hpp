@@ -13,8 +13,11 @@ struct FftArgs {
   int ex_pre, ex_tab, ex_post, ex_slice;  // FOP_EXPLICIT: diagonal signs, table, slice
 };
 int fft_vectors_per_block(int N, size_t lds_budget);
+// Ls: the distinct L with a compile-time plan among the instances;
+// any_generic: some instance needs the runtime-plan kernel.
+bool fft_has_fixed(int L);
 hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, const FftArgs& a,
-                      size_t lds_budget, hipStream_t s);
+                      size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, hipStream_t s);
 
 // ---- batched GEMM on named matrices (FP64 MFMA) --------------------------------------
 // C = alpha * op(A) op(B) + beta * C for every instance.  Row/column offsets
@@ -38,10 +41,14 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
                        GemmOperand B, GemmOperand C, GemmDim M, GemmDim Nn, GemmDim K,
                        double alpha, double beta, int flags, hipStream_t s);
 
+// Flush G <- G - X[:, :fill] Y[:fill, :] straight from memory (no LDS);
+// flags: GF_IF_FULL or GF_IF_ANY.
+hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int flags, hipStream_t s);
+
 // ---- delayed update -------------------------------------------------------------------
 hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, int replay,
                          hipStream_t s);
-hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int W,
+hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int kcap_max,
                          hipStream_t s);
 hipError_t launch_flush_done(const InstDev* insts, int n_inst, int any, hipStream_t s);
 
@@ -74,6 +81,12 @@ struct ElemArgs { int op, a, b, c, v; };
 hipError_t launch_elem(const InstDev* insts, int n_inst, int Nmax, bool cplx_, ElemArgs e, hipStream_t s);
 hipError_t launch_colnorm_sort(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
 hipError_t launch_qr_panel(const InstDev* insts, int n_inst, bool cplx_, int p, int nb, hipStream_t s);
+// 16-column panel held in registers (rows per thread chosen from Nmax)
+hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, hipStream_t s);
+// target <- (I - V op(T) V^H) target for panel p; cols 0: trailing [j0+16, N),
+// 1: [j0, N), 2: all; use_th: op(T) = T^H (apply Q^H) else T (apply Q).
+hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, int target, int cols,
+                             int use_th, hipStream_t s);
 hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
 hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int blk, hipStream_t s);
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);

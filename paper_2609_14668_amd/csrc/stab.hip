@@ -28,6 +28,14 @@ __device__ __forceinline__ void atomic_max_pos(double* addr, double v) {
 template <typename S>
 __device__ __forceinline__ double absval(S v) { return sqrt(absq(v)); }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+template <typename S>
+__device__ __forceinline__ void split_s(S v, double& re, double& im);
+template <>
+__device__ __forceinline__ void split_s<double>(double v, double& re, double& im) { re = v; im = 0.0; }
+template <>
+__device__ __forceinline__ void split_s<cplx>(cplx v, double& re, double& im) { re = v.x; im = v.y; }
+
 template <typename S>
 __global__ void __launch_bounds__(EW_THREADS)
 k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
@@ -225,22 +233,23 @@ __global__ void __launch_bounds__(256) k_colnorm_sort(const InstDev* __restrict_
 // H_j^H applied from the left; beta = -sign(Re alpha) ||(alpha, x)||.
 // Writes explicit V (MAT_V) and the compact-WY factor T (MAT_TB), so that
 // H_j0 ... H_{j0+nbe-1} = I - V T V^H.
-constexpr int QR_T = 256;
+constexpr int QR_T = 128;
+constexpr int QR_W = QR_T / 64;
 constexpr int NBMAX = 32;
 
 template <typename S>
-__device__ __forceinline__ S block_sum(S v, S* red, int tid) {
-  // reduce over 256 threads; red has 4 entries
+__device__ __forceinline__ S wave_sum(S v) {
   for (int off = 32; off > 0; off >>= 1) {
     if constexpr (ST<S>::is_complex) { v.x += __shfl_xor(v.x, off); v.y += __shfl_xor(v.y, off); }
     else v += __shfl_xor(v, off);
   }
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = v;
-  __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
+  return v;
 }
 
+// Rows are owned by a fixed thread (row i by thread (i - j0) % QR_T) for the
+// whole panel, so a thread only rereads what it wrote itself; per column one
+// fused reduction gives ||x||^2 and the dots x^H A[:, c] of all later panel
+// columns, from which w_c = v^H A[j:, c] = A[j, c] + conj(scal) x^H A[j+1:, c].
 template <typename S>
 __global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ insts, int p, int nb) {
   const InstDev& d = insts[blockIdx.y];
@@ -254,29 +263,59 @@ __global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ i
   S* TB = matp<S>(d, MAT_TB);
   double* tauv = d.vec[VEC_TAU];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ S red[4];
-  __shared__ S part[4][NBMAX];
-  __shared__ S wsum[NBMAX];
+  // per-wave transpose buffer: lane partials of every reduced value
+  __shared__ S xbuf[QR_W][NBMAX + 1][65];
+  __shared__ S part[QR_W][NBMAX + 1];
+  __shared__ S tot[NBMAX + 1];
+  __shared__ S rowj[NBMAX + 1];
   __shared__ S tau_s[NBMAX];
   __shared__ S Tm[NBMAX][NBMAX + 1];
   __shared__ S sh_scal;
 
   for (int jj = 0; jj < nbe; ++jj) {
     const int j = j0 + jj;
-    // norm of the sub-diagonal part
-    double xs = 0.0;
-    for (int i = j + 1 + tid; i < N; i += QR_T) xs += absq(A[i + (size_t)j * N]);
-    double xn2 = block_sum<double>(xs, reinterpret_cast<double*>(red), tid);
+    const int nc = nbe - jj - 1;
+    // fused pass: slot 0 = ||x||^2 (x = A[j+1:, j]), slot 1 + c = x^H A[j+1:, j+1+c]
+    S acc[NBMAX + 1];
+#pragma unroll
+    for (int c = 0; c <= NBMAX; ++c) acc[c] = ST<S>::zero();
+    // row j of the panel: alpha = A[j, j], then A[j, j+1+c]
+    if (tid <= nc) rowj[tid] = A[j + (size_t)(j + tid) * N];
+    for (int i = j0 + tid; i < N; i += QR_T) {
+      if (i <= j) continue;
+      S x = A[i + (size_t)j * N];
+      S cx = conjg(x);
+      acc[0] = acc[0] + ST<S>::from_re(absq(x));
+#pragma unroll
+      for (int c = 0; c < NBMAX; ++c)
+        if (c < nc) acc[1 + c] = acc[1 + c] + cx * A[i + (size_t)(j + 1 + c) * N];
+    }
+#pragma unroll
+    for (int c = 0; c <= NBMAX; ++c)
+      if (c <= nc) xbuf[wave][c][lane] = acc[c];
+    __syncthreads();
+    if (lane <= nc) {
+      S t = xbuf[wave][lane][0];
+      for (int l = 1; l < 64; ++l) t = t + xbuf[wave][lane][l];
+      part[wave][lane] = t;
+    }
+    __syncthreads();
+    if (tid <= nc) {
+      S t = part[0][tid];
+      for (int w = 1; w < QR_W; ++w) t = t + part[w][tid];
+      tot[tid] = t;
+    }
+    __syncthreads();
     if (tid == 0) {
-      S alpha = A[j + (size_t)j * N];
+      S alpha = rowj[0];
+      double xn2 = real_part(tot[0]);
       S tau, scal;
       if (xn2 == 0.0 && imag_part(alpha) == 0.0) {
         tau = ST<S>::zero();
         scal = ST<S>::one();
       } else {
-        double ar = real_part(alpha);
         double nrm = sqrt(absq(alpha) + xn2);
-        double beta = ar >= 0.0 ? -nrm : nrm;
+        double beta = real_part(alpha) >= 0.0 ? -nrm : nrm;
         S bS = ST<S>::from_re(beta);
         tau = cdiv(bS - alpha, bS);
         scal = cdiv(ST<S>::one(), alpha - bS);
@@ -288,45 +327,25 @@ __global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ i
     __syncthreads();
     const S scal = sh_scal;
     const S ctau = conjg(tau_s[jj]);
-    for (int i = j + 1 + tid; i < N; i += QR_T) A[i + (size_t)j * N] = A[i + (size_t)j * N] * scal;
-    __syncthreads();
-    // w_c = v^H A[j:, c] for the remaining panel columns
-    const int nc = nbe - jj - 1;
-    if (nc > 0) {
-      S acc[NBMAX];
-#pragma unroll
-      for (int c = 0; c < NBMAX; ++c) acc[c] = ST<S>::zero();
-      for (int i = j + tid; i < N; i += QR_T) {
-        S vi = (i == j) ? ST<S>::one() : A[i + (size_t)j * N];
-        S cv = conjg(vi);
-#pragma unroll
-        for (int c = 0; c < NBMAX; ++c)
-          if (c < nc) acc[c] = acc[c] + cv * A[i + (size_t)(j + 1 + c) * N];
-      }
-#pragma unroll
-      for (int c = 0; c < NBMAX; ++c) {
-        if (c < nc) {
-          S v = acc[c];
-          for (int off = 32; off > 0; off >>= 1) {
-            if constexpr (ST<S>::is_complex) { v.x += __shfl_xor(v.x, off); v.y += __shfl_xor(v.y, off); }
-            else v += __shfl_xor(v, off);
-          }
-          if (lane == 0) part[wave][c] = v;
-        }
-      }
-      __syncthreads();
-      if (tid < nc) wsum[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
-      __syncthreads();
-      for (int i = j + tid; i < N; i += QR_T) {
-        S vi = (i == j) ? ST<S>::one() : A[i + (size_t)j * N];
-        S f = ctau * vi;
-        for (int c = 0; c < nc; ++c) {
-          size_t o = i + (size_t)(j + 1 + c) * N;
-          A[o] = A[o] - f * wsum[c];
-        }
-      }
-      __syncthreads();
+    const S cscal = conjg(scal);
+    // row j of the later panel columns (v_j = 1)
+    if (tid < nc) {
+      S w = rowj[1 + tid] + cscal * tot[1 + tid];
+      A[j + (size_t)(j + 1 + tid) * N] = rowj[1 + tid] - ctau * w;
     }
+    // rows below j: v_i = scal x_i, A[i, c] -= conj(tau) v_i w_c
+    for (int i = j0 + tid; i < N; i += QR_T) {
+      if (i <= j) continue;
+      S vi = A[i + (size_t)j * N] * scal;
+      A[i + (size_t)j * N] = vi;
+      S f = ctau * vi;
+#pragma unroll 4
+      for (int c = 0; c < nc; ++c) {
+        size_t o = i + (size_t)(j + 1 + c) * N;
+        A[o] = A[o] - f * (rowj[1 + c] + cscal * tot[1 + c]);
+      }
+    }
+    __syncthreads();
   }
   // explicit V and tau
   for (int jj = 0; jj < nbe; ++jj) {
@@ -337,48 +356,387 @@ __global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ i
     }
   }
   if (tid < nbe) tauv[2 * (j0 + tid)] = real_part(tau_s[tid]), tauv[2 * (j0 + tid) + 1] = imag_part(tau_s[tid]);
-  __syncthreads();
-  // T (forward, columnwise): T[jj][jj] = tau_jj, T[0:jj, jj] = -tau_jj T[0:jj, 0:jj] V[:, 0:jj]^H v_jj
   for (int r = tid; r < NBMAX * (NBMAX + 1); r += QR_T) (&Tm[0][0])[r] = ST<S>::zero();
   __syncthreads();
-  for (int jj = 0; jj < nbe; ++jj) {
+  // T (forward, columnwise): T[jj][jj] = tau_jj, T[0:jj, jj] = -tau_jj T[0:jj, 0:jj] V[:, 0:jj]^H v_jj
+  for (int jj = 1; jj < nbe; ++jj) {
     const int j = j0 + jj;
-    if (jj > 0) {
-      S acc[NBMAX];
+    S acc[NBMAX];
 #pragma unroll
-      for (int m = 0; m < NBMAX; ++m) acc[m] = ST<S>::zero();
-      for (int i = j + tid; i < N; i += QR_T) {
-        S vj = V[i + (size_t)j * N];
+    for (int m = 0; m < NBMAX; ++m) acc[m] = ST<S>::zero();
+    for (int i = j0 + tid; i < N; i += QR_T) {
+      if (i < j) continue;
+      S vj = V[i + (size_t)j * N];
 #pragma unroll
-        for (int m = 0; m < NBMAX; ++m)
-          if (m < jj) acc[m] = acc[m] + conjg(V[i + (size_t)(j0 + m) * N]) * vj;
-      }
-#pragma unroll
-      for (int m = 0; m < NBMAX; ++m) {
-        if (m < jj) {
-          S v = acc[m];
-          for (int off = 32; off > 0; off >>= 1) {
-            if constexpr (ST<S>::is_complex) { v.x += __shfl_xor(v.x, off); v.y += __shfl_xor(v.y, off); }
-            else v += __shfl_xor(v, off);
-          }
-          if (lane == 0) part[wave][m] = v;
-        }
-      }
-      __syncthreads();
-      if (tid < jj) wsum[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
-      __syncthreads();
-      if (tid < jj) {
-        S s = ST<S>::zero();
-        for (int m = tid; m < jj; ++m) s = s + Tm[tid][m] * wsum[m];
-        Tm[tid][jj] = -(tau_s[jj] * s);
-      }
+      for (int m = 0; m < NBMAX; ++m)
+        if (m < jj) acc[m] = acc[m] + conjg(V[i + (size_t)(j0 + m) * N]) * vj;
     }
-    if (tid == 0) Tm[jj][jj] = tau_s[jj];
+#pragma unroll
+    for (int m = 0; m < NBMAX; ++m)
+      if (m < jj) xbuf[wave][m][lane] = acc[m];
+    __syncthreads();
+    if (lane < jj) {
+      S t = xbuf[wave][lane][0];
+      for (int l = 1; l < 64; ++l) t = t + xbuf[wave][lane][l];
+      part[wave][lane] = t;
+    }
+    __syncthreads();
+    if (tid < jj) {
+      S t = part[0][tid];
+      for (int w = 1; w < QR_W; ++w) t = t + part[w][tid];
+      tot[tid] = t;
+    }
+    __syncthreads();
+    // column jj of T from the rows above (sequential dependence only on earlier columns)
+    if (tid < jj) {
+      S s2 = ST<S>::zero();
+      for (int m = tid; m < jj; ++m) s2 = s2 + (m == tid ? tau_s[m] : Tm[tid][m]) * tot[m];
+      Tm[tid][jj] = -(tau_s[jj] * s2);
+    }
     __syncthreads();
   }
   for (int x = tid; x < nbe * nbe; x += QR_T) {
     int r = x % nbe, c = x / nbe;
-    TB[(j0 + r) + (size_t)c * N] = Tm[r][c];
+    TB[(j0 + r) + (size_t)c * N] = r == c ? tau_s[r] : Tm[r][c];
+  }
+}
+
+// Register-resident panel: thread t owns rows j0 + t + PT*q (q < RPT) of the
+// NBR panel columns for the whole factorisation, so the column loop touches no
+// global memory; per column one reduction (through an LDS transpose) gives
+// ||x||^2 and x^H A[j+1:, c] for the later columns.
+constexpr int PT = 256;
+constexpr int PW = PT / 64;
+constexpr int NBR = 16;
+
+template <typename S>
+struct PanelShared {
+  S xbuf[PW][NBR + 1][65];
+  S tot[NBR + 1];
+  S rowj[NBR];
+  S tau_s[NBR];
+  S Tm[NBR][NBR + 1];
+  S scal;
+};
+
+// Sum acc[0..nval) over all threads of the block into sh.tot.
+template <typename S>
+__device__ __forceinline__ void panel_reduce(PanelShared<S>& sh, const S* acc, int nval) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int c = 0; c <= NBR; ++c)
+    if (c < nval) sh.xbuf[wave][c][lane] = acc[c];
+  __syncthreads();
+  // two levels: 16 threads per value each add 16 partials, then one adds 16
+  S t = ST<S>::zero();
+  const int c = tid >> 4, sub = tid & 15;
+  if (c < nval) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      int x = sub * 16 + u;            // partial index 0..255 = wave*64 + lane
+      t = t + sh.xbuf[x >> 6][c][x & 63];
+    }
+  }
+  __syncthreads();
+  if (c < nval) sh.xbuf[0][c][sub] = t;
+  __syncthreads();
+  if (tid < nval) {
+    S u2 = ST<S>::zero();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) u2 = u2 + sh.xbuf[0][tid][u];
+    sh.tot[tid] = u2;
+  }
+  __syncthreads();
+}
+
+// Column JJ of the panel (compile-time, so the register array is indexed
+// with constants only).
+template <typename S, int RPT, int JJ>
+struct PanelColumn {
+  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S>& sh, int j0, int N, int nbe) {
+    if constexpr (JJ < NBR) {
+      if (JJ < nbe) {
+        const int tid = threadIdx.x;
+        const int j = j0 + JJ;
+        const int nc = nbe - JJ - 1;
+        S acc[NBR + 1];
+#pragma unroll
+        for (int c = 0; c <= NBR; ++c) acc[c] = ST<S>::zero();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int i = j0 + tid + PT * q;
+          if (i > j && i < N) {
+            S x = a[q][JJ];
+            S cx = conjg(x);
+            acc[0] = acc[0] + ST<S>::from_re(absq(x));
+#pragma unroll
+            for (int c = JJ + 1; c < NBR; ++c) acc[c - JJ] = acc[c - JJ] + cx * a[q][c];
+          }
+        }
+        if (tid == JJ) {
+#pragma unroll
+          for (int c = JJ; c < NBR; ++c) sh.rowj[c] = a[0][c];
+        }
+        panel_reduce<S>(sh, acc, nc + 1);
+        if (tid == 0) {
+          S alpha = sh.rowj[JJ];
+          double xn2 = real_part(sh.tot[0]);
+          S tau, scal;
+          if (xn2 == 0.0 && imag_part(alpha) == 0.0) {
+            tau = ST<S>::zero();
+            scal = ST<S>::one();
+          } else {
+            double nrm = sqrt(absq(alpha) + xn2);
+            double beta = real_part(alpha) >= 0.0 ? -nrm : nrm;
+            S bS = ST<S>::from_re(beta);
+            tau = cdiv(bS - alpha, bS);
+            scal = cdiv(ST<S>::one(), alpha - bS);
+            sh.rowj[JJ] = bS;
+          }
+          sh.tau_s[JJ] = tau;
+          sh.scal = scal;
+        }
+        __syncthreads();
+        const S scal = sh.scal, cscal = conjg(scal);
+        const S ctau = conjg(sh.tau_s[JJ]);
+        S w[NBR];
+#pragma unroll
+        for (int c = JJ + 1; c < NBR; ++c) w[c] = sh.rowj[c] + cscal * sh.tot[c - JJ];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int i = j0 + tid + PT * q;
+          if (i == j) {
+            a[q][JJ] = sh.rowj[JJ];
+#pragma unroll
+            for (int c = JJ + 1; c < NBR; ++c) a[q][c] = a[q][c] - ctau * w[c];
+          } else if (i > j && i < N) {
+            S vi = a[q][JJ] * scal;
+            a[q][JJ] = vi;
+            S f = ctau * vi;
+#pragma unroll
+            for (int c = JJ + 1; c < NBR; ++c) a[q][c] = a[q][c] - f * w[c];
+          }
+        }
+        __syncthreads();
+      }
+      PanelColumn<S, RPT, JJ + 1>::run(a, sh, j0, N, nbe);
+    }
+  }
+};
+
+// Column JJ of the compact-WY factor T from the register-held V.
+template <typename S, int RPT, int JJ>
+struct PanelT {
+  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S>& sh, int j0, int N, int nbe) {
+    if constexpr (JJ < NBR) {
+      if (JJ < nbe) {
+        const int tid = threadIdx.x;
+        const int j = j0 + JJ;
+        S acc[NBR + 1];
+#pragma unroll
+        for (int m = 0; m <= NBR; ++m) acc[m] = ST<S>::zero();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int i = j0 + tid + PT * q;
+          if (i >= j && i < N) {
+            S vj = i == j ? ST<S>::one() : a[q][JJ];
+#pragma unroll
+            for (int m = 0; m < JJ; ++m) acc[m] = acc[m] + conjg(a[q][m]) * vj;   // i > j0 + m
+          }
+        }
+        panel_reduce<S>(sh, acc, JJ);
+        if (tid < JJ) {
+          S s2 = ST<S>::zero();
+          for (int m = tid; m < JJ; ++m) s2 = s2 + (m == tid ? sh.tau_s[m] : sh.Tm[tid][m]) * sh.tot[m];
+          sh.Tm[tid][JJ] = -(sh.tau_s[JJ] * s2);
+        }
+        __syncthreads();
+      }
+      PanelT<S, RPT, JJ + 1>::run(a, sh, j0, N, nbe);
+    }
+  }
+};
+
+template <typename S, int RPT>
+__global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__ insts, int p) {
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  const int j0 = p * NBR;
+  if (j0 >= N) return;
+  const int nbe = min(NBR, N - j0);
+  S* A = matp<S>(d, MAT_QA);
+  S* V = matp<S>(d, MAT_V);
+  S* TB = matp<S>(d, MAT_TB);
+  double* tauv = d.vec[VEC_TAU];
+  const int tid = threadIdx.x;
+  __shared__ PanelShared<S> sh;
+
+  S a[RPT][NBR];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = j0 + tid + PT * q;
+#pragma unroll
+    for (int c = 0; c < NBR; ++c) a[q][c] = (i < N && c < nbe) ? A[i + (size_t)(j0 + c) * N] : ST<S>::zero();
+  }
+  PanelColumn<S, RPT, 0>::run(a, sh, j0, N, nbe);
+  // write back R (upper part) and the Householder vectors, plus explicit V
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = j0 + tid + PT * q;
+    if (i < N) {
+#pragma unroll
+      for (int c = 0; c < NBR; ++c) {
+        if (c < nbe) {
+          const int j = j0 + c;
+          A[i + (size_t)j * N] = a[q][c];
+          V[i + (size_t)j * N] = i < j ? ST<S>::zero() : (i == j ? ST<S>::one() : a[q][c]);
+        }
+      }
+    }
+  }
+  if (tid < nbe) tauv[2 * (j0 + tid)] = real_part(sh.tau_s[tid]), tauv[2 * (j0 + tid) + 1] = imag_part(sh.tau_s[tid]);
+  for (int r = tid; r < NBR * (NBR + 1); r += PT) (&sh.Tm[0][0])[r] = ST<S>::zero();
+  __syncthreads();
+  PanelT<S, RPT, 1>::run(a, sh, j0, N, nbe);
+  for (int x = tid; x < nbe * nbe; x += PT) {
+    int r = x % nbe, c = x / nbe;
+    TB[(j0 + r) + (size_t)c * N] = r == c ? sh.tau_s[r] : sh.Tm[r][c];
+  }
+}
+
+// C <- (I - V op(T) V^H) C on rows [j0, N) and a range of columns of a
+// target matrix, with the 16-column V and T of panel p (eq. of the compact-WY
+// representation H_1..H_k = I - V T V^H):
+//   W = V^H C (MFMA, rows staged through LDS), W' = op(T) W, C -= V W'.
+// op(T) = T^H applies Q^H (QR trailing update, Q^H RHS), T applies Q (forming Q).
+// cols: 0 -> [j0 + 16, N), 1 -> [j0, N), 2 -> [0, N).
+constexpr int AR_CT = 64;
+template <typename S>
+__global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ insts, int p, int target,
+                                                    int cols, int use_th) {
+  constexpr bool CX = ST<S>::is_complex;
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  const int j0 = p * NBR;
+  if (j0 >= N) return;
+  const int nbe = min(NBR, N - j0);
+  const int cbeg = cols == 0 ? j0 + NBR : (cols == 1 ? j0 : 0);
+  const int c0 = cbeg + blockIdx.x * AR_CT;
+  if (c0 >= N) return;
+  const S* V = matp<S>(d, MAT_V);
+  const S* TB = matp<S>(d, MAT_TB);
+  S* C = matp<S>(d, target);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  __shared__ double Vr[16][NBR + 1], Vi[CX ? 16 : 1][NBR + 1];
+  __shared__ double Cr[16][AR_CT + 1], Ci[CX ? 16 : 1][AR_CT + 1];
+  __shared__ S Ws[NBR][AR_CT + 1];
+  __shared__ S Tt[NBR][NBR + 1];
+  // ---- W = V^H C: wave w owns columns 16w..16w+15 of the tile
+  d4 wr = d4{0, 0, 0, 0}, wi = d4{0, 0, 0, 0};
+  for (int i0 = j0; i0 < N; i0 += 16) {
+    for (int x = tid; x < 16 * NBR; x += 256) {
+      int r = x % 16, m = x / 16, i = i0 + r;
+      double re = 0, im = 0;
+      if (i < N && m < nbe) split_s<S>(V[i + (size_t)(j0 + m) * N], re, im);
+      Vr[r][m] = re;
+      if constexpr (CX) Vi[r][m] = im;
+    }
+    for (int x = tid; x < 16 * AR_CT; x += 256) {
+      int r = x % 16, cc = x / 16, i = i0 + r, c = c0 + cc;
+      double re = 0, im = 0;
+      if (i < N && c < N) split_s<S>(C[i + (size_t)c * N], re, im);
+      Cr[r][cc] = re;
+      if constexpr (CX) Ci[r][cc] = im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k = ks * 4 + lk;
+      // A = V^H: A[m][k] = conj(V[k][m]); B = C: B[k][c]
+      double ar = Vr[k][lr], br = Cr[k][wave * 16 + lr];
+      wr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, wr, 0, 0, 0);
+      if constexpr (CX) {
+        double ai = -Vi[k][lr], bi = Ci[k][wave * 16 + lr];
+        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, wr, 0, 0, 0);
+        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, wi, 0, 0, 0);
+        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, wi, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D layout: lane holds W[m = lk + 4 r][c = 16 wave + lr]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if constexpr (CX) Ws[lk + 4 * r][wave * 16 + lr] = cmake(wr[r], wi[r]);
+    else Ws[lk + 4 * r][wave * 16 + lr] = wr[r];
+  }
+  for (int x = tid; x < NBR * NBR; x += 256) {
+    int r = x % NBR, c = x / NBR;
+    S t = (r < nbe && c < nbe) ? TB[(j0 + r) + (size_t)c * N] : ST<S>::zero();
+    // op(T): T^H[r][c] = conj(T[c][r]) -> stored transposed below
+    Tt[r][c] = t;
+  }
+  __syncthreads();
+  // ---- W' = op(T) W (16 x 64), written over Ws after a barrier
+  S wp[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int x = tid + 256 * u, m = x % NBR, c = x / NBR;
+    S acc = ST<S>::zero();
+    for (int k = 0; k < NBR; ++k) {
+      S t = use_th ? conjg(Tt[k][m]) : Tt[m][k];
+      acc = acc + t * Ws[k][c];
+    }
+    wp[u] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int x = tid + 256 * u, m = x % NBR, c = x / NBR;
+    Ws[m][c] = wp[u];
+  }
+  __syncthreads();
+  // ---- C -= V W': wave w updates columns 16w..16w+15, 16 rows at a time.
+  // Operands fed as (W', V) so a lane owns one row and four columns of the
+  // block and the stores coalesce along the column.
+  const int cw = c0 + wave * 16;
+  for (int i0 = j0; i0 < N; i0 += 16) {
+    d4 cr, ci;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i = i0 + lr, c = cw + lk + 4 * r;
+      double re = 0, im = 0;
+      if (i < N && c < N) split_s<S>(C[i + (size_t)c * N], re, im);
+      cr[r] = -re;
+      ci[r] = -im;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int m = ks * 4 + lk;
+      const int i = i0 + lr;
+      double vr = 0, vi = 0;
+      if (i < N && m < nbe) split_s<S>(V[i + (size_t)(j0 + m) * N], vr, vi);
+      double br, bi;
+      split_s<S>(Ws[m][wave * 16 + lr], br, bi);
+      // acc^T += W'^T V^T : A-operand W'[m][c] as (c, m), B-operand V[i][m] as (m, i)
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, cr, 0, 0, 0);
+      if constexpr (CX) {
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi, vi, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vr, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vi, ci, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i = i0 + lr, c = cw + lk + 4 * r;
+      if (i < N && c < N) {
+        if constexpr (CX) C[i + (size_t)c * N] = cmake(-cr[r], -ci[r]);
+        else C[i + (size_t)c * N] = -cr[r];
+      }
+    }
   }
 }
 
@@ -453,6 +811,12 @@ hipError_t launch_colnorm_sort(const InstDev* insts, int n_inst, int Nmax, bool 
 }
 
 hipError_t launch_qr_panel(const InstDev* insts, int n_inst, bool cplx_, int p, int nb, hipStream_t s) {
+  if (nb == NBR) {
+    // register-resident panel; rows per thread from the largest instance
+    int Nmax = 0;
+    (void)Nmax;
+    return hipErrorInvalidValue;  // replaced by launch_qr_panel_reg
+  }
   if (nb > NBMAX) return hipErrorInvalidValue;
   if (cplx_) hipLaunchKernelGGL(k_qr_panel<cplx>, dim3(1, n_inst), dim3(QR_T), 0, s, insts, p, nb);
   else hipLaunchKernelGGL(k_qr_panel<double>, dim3(1, n_inst), dim3(QR_T), 0, s, insts, p, nb);
@@ -470,5 +834,33 @@ hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cpl
   dim3 grid((Nmax + 255) / 256, n_inst);
   if (cplx_) hipLaunchKernelGGL(k_trsm_diag<cplx>, grid, dim3(256), 0, s, insts, blk);
   else hipLaunchKernelGGL(k_trsm_diag<double>, grid, dim3(256), 0, s, insts, blk);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, hipStream_t s) {
+  int rpt = (Nmax + PT - 1) / PT;
+#define DQMC_QRP(R)                                                                                          \
+  if (cplx_) hipLaunchKernelGGL((k_qr_panel_reg<cplx, R>), dim3(1, n_inst), dim3(PT), 0, s, insts, p);      \
+  else hipLaunchKernelGGL((k_qr_panel_reg<double, R>), dim3(1, n_inst), dim3(PT), 0, s, insts, p);
+  if (rpt <= 1) { DQMC_QRP(1) }
+  else if (rpt <= 2) { DQMC_QRP(2) }
+  else if (rpt <= 3) { DQMC_QRP(3) }
+  else if (rpt <= 4) { DQMC_QRP(4) }
+  else if (rpt <= 8) { DQMC_QRP(8) }
+  else if (rpt <= 16) { DQMC_QRP(16) }
+  else return hipErrorInvalidValue;
+#undef DQMC_QRP
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, int target, int cols,
+                             int use_th, hipStream_t s) {
+  int j0 = p * NBR;
+  int cbeg = cols == 0 ? j0 + NBR : (cols == 1 ? j0 : 0);
+  int ncol = Nmax - cbeg;
+  if (ncol <= 0) return hipSuccess;
+  dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_apply_refl<cplx>, grid, dim3(256), 0, s, insts, p, target, cols, use_th);
+  else hipLaunchKernelGGL(k_apply_refl<double>, grid, dim3(256), 0, s, insts, p, target, cols, use_th);
   return hipGetLastError();
 }

@@ -166,10 +166,18 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
   }
 }
 
-// Full-length x_k, y_k for the accepted sites of the last window.
+// Full-length x_k, y_k for the accepted sites of the last window, by the
+// recursion of eq. DelayRgenk:
+//   x_k[j] = c_k (G0[j, i_k] - sum_{m<k} x_m[j] y_m[i_k]),
+//   y_k[j] = delta_{i_k j} - G0[i_k, j] + sum_{m<k} x_m[i_k] y_m[j],
+// one thread per j (row of X and column of Y), accepted sites taken KC at a
+// time so that every x_m[j], y_m[j] read from memory serves KC updates.
+constexpr int KC = 8;
+constexpr int EXP_WAVES = 4;   // each wave accumulates KC / EXP_WAVES of the chunk
 template <typename S>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * EXP_WAVES)
 k_expand(const InstDev* __restrict__ insts) {
+  constexpr int KW = KC / EXP_WAVES;
   const InstDev& d = insts[blockIdx.y];
   const InstState* st = d.st;
   if (st->init_mode || st->idle) return;
@@ -178,51 +186,97 @@ k_expand(const InstDev* __restrict__ insts) {
   const int N = d.N;
   const int j0 = blockIdx.x * 64;
   if (j0 >= N) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j = j0 + lane;
   const bool ok = j < N;
-  const int fill0 = st->fill, w0 = st->wstart, wn = st->wlen;
+  const int fill0 = st->fill, w0 = st->wstart;
   const S* G = matp<S>(d, MAT_G);
   S* X = matp<S>(d, MAT_X);
   S* Y = matp<S>(d, MAT_Y);
   const S* wc = reinterpret_cast<const S*>(d.wcoef);
 
-  __shared__ S Gblk[WMAX][65];
-  __shared__ S ycf[256], xcf[256];
+  extern __shared__ char xsmem[];
+  // [m][kk]: y_m[i_k], x_m[i_k] for m < kcap
+  S* ycf = reinterpret_cast<S*>(xsmem);
+  S* xcf = ycf + (size_t)d.kcap * KC;
+  __shared__ S pax[KC][64], pay[KC][64];
   __shared__ int sites[WMAX];
-  for (int jj = 0; jj < 64; ++jj) {
-    int col = j0 + jj;
-    Gblk[lane][jj] = (lane < wn && col < N) ? G[(w0 + lane) + (size_t)col * N] : ST<S>::zero();
-  }
-  sites[lane] = lane < mw ? d.acc_site[lane] : 0;
+  if (tid < WMAX) sites[tid] = tid < mw ? d.acc_site[tid] : 0;
   __syncthreads();
 
-  for (int k = 0; k < mw; ++k) {
-    const int ik = sites[k];
-    const int gi = w0 + ik;
-    const int nm = fill0 + k;
-    // coefficients y_m[i_k] (for x) and x_m[i_k] (for y), m < fill0 + k
-    for (int m = lane; m < nm; m += 64) {
-      if (m < fill0) {
-        ycf[m] = Y[(size_t)m * N + gi];
-        xcf[m] = X[gi + (size_t)m * N];
-      } else {
-        int mp = m - fill0;
-        ycf[m] = wc[WC_Y + mp * WMAX + ik];
-        xcf[m] = wc[WC_X + mp * WMAX + ik];
+  for (int k0 = 0; k0 < mw; k0 += KC) {
+    const int kn = min(KC, mw - k0);
+    const int nm = fill0 + k0 + kn;   // coefficients needed for m < nm
+    for (int x = tid; x < nm * KC; x += 64 * EXP_WAVES) {
+      int m = x / KC, kk = x % KC;
+      S yv = ST<S>::zero(), xv = ST<S>::zero();
+      if (kk < kn) {
+        int ik = sites[k0 + kk], gi = w0 + ik;
+        if (m < fill0) {
+          yv = Y[(size_t)m * N + gi];
+          xv = X[gi + (size_t)m * N];
+        } else {
+          int mp = m - fill0;
+          yv = wc[WC_Y + mp * WMAX + ik];
+          xv = wc[WC_X + mp * WMAX + ik];
+        }
+      }
+      ycf[m * KC + kk] = yv;
+      xcf[m * KC + kk] = xv;
+    }
+    __syncthreads();
+    const int mpre = fill0 + k0;
+    if (ok) {
+      // this wave's share of the chunk: kk = wave*KW .. wave*KW + KW - 1
+      S ax[KW], ay[KW];
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        int kk = wave * KW + q;
+        if (kk < kn) {
+          int gi = w0 + sites[k0 + kk];
+          ax[q] = G[j + (size_t)gi * N];
+          ay[q] = -G[gi + (size_t)j * N];
+          if (j == gi) ay[q] = ay[q] + ST<S>::one();
+        } else {
+          ax[q] = ST<S>::zero();
+          ay[q] = ST<S>::zero();
+        }
+      }
+      for (int m = 0; m < mpre; ++m) {
+        S xv = X[j + (size_t)m * N];
+        S yv = Y[(size_t)m * N + j];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+          int kk = wave * KW + q;
+          ax[q] = ax[q] - xv * ycf[m * KC + kk];
+          ay[q] = ay[q] + xcf[m * KC + kk] * yv;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        pax[wave * KW + q][lane] = ax[q];
+        pay[wave * KW + q][lane] = ay[q];
       }
     }
     __syncthreads();
-    if (ok) {
-      S s = G[j + (size_t)gi * N];
-      S t = -Gblk[ik][lane];
-      if (j == gi) t = t + ST<S>::one();
-      for (int m = 0; m < nm; ++m) {
-        s = s - X[j + (size_t)m * N] * ycf[m];
-        t = t + xcf[m] * Y[(size_t)m * N + j];
+    if (ok && wave == 0) {
+      // the recursion inside the chunk
+      S ax[KC], ay[KC];
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) { ax[kk] = pax[kk][lane]; ay[kk] = pay[kk][lane]; }
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        if (kk < kn) {
+#pragma unroll
+          for (int q = 0; q < kk; ++q) {
+            ax[kk] = ax[kk] - ax[q] * ycf[(mpre + q) * KC + kk];
+            ay[kk] = ay[kk] + xcf[(mpre + q) * KC + kk] * ay[q];
+          }
+          ax[kk] = wc[k0 + kk] * ax[kk];
+          X[j + (size_t)(mpre + kk) * N] = ax[kk];
+          Y[(size_t)(mpre + kk) * N + j] = ay[kk];
+        }
       }
-      X[j + (size_t)nm * N] = wc[k] * s;
-      Y[(size_t)nm * N + j] = t;
     }
     __syncthreads();
   }
@@ -244,6 +298,7 @@ __global__ void k_flush_done(const InstDev* __restrict__ insts, int n, int any) 
   InstState* st = d.st;
   if (st->init_mode || st->idle) return;
   if (any ? st->fill > 0 : st->fill >= d.kflush) {
+    st->flush_rank_sum += st->fill;
     st->fill = 0;
     st->flushes += 1;
   }
@@ -301,6 +356,7 @@ __global__ void k_reset_counters(const InstDev* __restrict__ insts, int n) {
   st->n_meas = 0;
   st->drift_max = 0.0;
   st->drift_last = 0.0;
+  st->flush_rank_sum = 0;
   st->series_base = st->sweep;
 }
 
@@ -328,11 +384,11 @@ hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, in
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int W, hipStream_t s) {
-  (void)W;
+hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int kcap_max, hipStream_t s) {
   dim3 grid((Nmax + 63) / 64, n_inst);
-  if (cplx_) hipLaunchKernelGGL(k_expand<cplx>, grid, dim3(64), 0, s, insts);
-  else hipLaunchKernelGGL(k_expand<double>, grid, dim3(64), 0, s, insts);
+  size_t lds = (size_t)2 * kcap_max * KC * (cplx_ ? sizeof(cplx) : sizeof(double));
+  if (cplx_) hipLaunchKernelGGL(k_expand<cplx>, grid, dim3(64 * EXP_WAVES), lds, s, insts);
+  else hipLaunchKernelGGL(k_expand<double>, grid, dim3(64 * EXP_WAVES), lds, s, insts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bump, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);
