@@ -162,7 +162,7 @@ def main():
     fl = tim["flush"]
     if fl["ms"] > 0:
         ach = tim["flush_flops"] / (fl["ms"] * 1e-3)
-        line["roofline"] = {"bound": "mfma", "kernel": "k_gemm (flush G -= X Y)", "achieved": ach / 1e12,
+        line["roofline"] = {"bound": "mfma", "kernel": "k_flush_direct (G -= X Y)", "achieved": ach / 1e12,
                             "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
                             "traffic": None, "launches": fl["launches"],
                             "avg_launch_us": 1e3 * fl["ms"] / max(fl["launches"], 1)}

@@ -630,30 +630,32 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
   S* C = matp<S>(d, target);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  __shared__ double Vr[16][NBR + 1], Vi[CX ? 16 : 1][NBR + 1];
-  __shared__ double Cr[16][AR_CT + 1], Ci[CX ? 16 : 1][AR_CT + 1];
+  constexpr int RB = 64;   // rows of V and C staged per step
+  __shared__ double Vr[RB][NBR + 1], Vi[CX ? RB : 1][NBR + 1];
+  __shared__ double Cr[RB][AR_CT + 1], Ci[CX ? RB : 1][AR_CT + 1];
   __shared__ S Ws[NBR][AR_CT + 1];
   __shared__ S Tt[NBR][NBR + 1];
   // ---- W = V^H C: wave w owns columns 16w..16w+15 of the tile
   d4 wr = d4{0, 0, 0, 0}, wi = d4{0, 0, 0, 0};
-  for (int i0 = j0; i0 < N; i0 += 16) {
-    for (int x = tid; x < 16 * NBR; x += 256) {
-      int r = x % 16, m = x / 16, i = i0 + r;
+  for (int i0 = j0; i0 < N; i0 += RB) {
+    for (int x = tid; x < RB * NBR; x += 256) {
+      int r = x % RB, m = x / RB, i = i0 + r;
       double re = 0, im = 0;
       if (i < N && m < nbe) split_s<S>(V[i + (size_t)(j0 + m) * N], re, im);
       Vr[r][m] = re;
       if constexpr (CX) Vi[r][m] = im;
     }
-    for (int x = tid; x < 16 * AR_CT; x += 256) {
-      int r = x % 16, cc = x / 16, i = i0 + r, c = c0 + cc;
+    for (int x = tid; x < RB * AR_CT; x += 256) {
+      int r = x % RB, cc = x / RB, i = i0 + r, c = c0 + cc;
       double re = 0, im = 0;
       if (i < N && c < N) split_s<S>(C[i + (size_t)c * N], re, im);
       Cr[r][cc] = re;
       if constexpr (CX) Ci[r][cc] = im;
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    const int nks = min(RB, N - i0 + 3) / 4;
+#pragma unroll 2
+    for (int ks = 0; ks < nks; ++ks) {
       const int k = ks * 4 + lk;
       // A = V^H: A[m][k] = conj(V[k][m]); B = C: B[k][c]
       double ar = Vr[k][lr], br = Cr[k][wave * 16 + lr];
