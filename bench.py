@@ -45,6 +45,10 @@ def make_descs(name, k=None):
         return workloads.plain_L3()
     if name == "plain_L42":
         return workloads.plain_L42()
+    if name == "mixed_L30":
+        return workloads.mixed_L30(precision=1)
+    if name == "fp64_L30":
+        return workloads.mixed_L30(precision=0)
     raise SystemExit("unknown workload " + name)
 
 
@@ -150,7 +154,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if sim.shapes[0][2] else "f64",
+        "dtype": (("c64/c128" if sim.shapes[0][2] else "f32/f64") if descs[0]["precision"] == 1
+                  else ("c128" if sim.shapes[0][2] else "f64")),
         "data": "synthetic",
         "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
                    "dtau": descs[0]["dtau"], "proposal": "plain"},

@@ -64,6 +64,12 @@ typedef enum {
   DQMC_EUNSUPPORTED = -6  /* size or option not supported */
 } dqmc_status;
 
+/* DQMC_FP64: every step in double precision.  DQMC_MIXED: the wraps run the
+ * FFT in complex64 and the flushes form X Y with FP32 matrix cores (operands
+ * rounded to float, FP32 accumulation); G stays stored in FP64, and the
+ * acceptance ratios, the delayed-vector builder, the QR stabilisation and the
+ * estimators stay FP64.  The accumulated single-precision error is reported
+ * as the drift max |G_wrap - G_scratch| at each recomputation (dqmc_stats). */
 typedef enum { DQMC_FP64 = 0, DQMC_MIXED = 1 } dqmc_precision;
 
 /* One Markov chain.  All instances of a handle share n_stab, and every
@@ -76,7 +82,7 @@ typedef struct {
   double theta1, theta2;/* twist Theta_1, Theta_2 in radians along a1, a2; both 0 = periodic (real path) */
   int32_t n_delay;      /* flush rank k: flush once at least k accepted flips are pending, 1 <= k <= 192 */
   int32_t n_stab;       /* slices between recomputations of G (stabilisation) */
-  int32_t precision;    /* dqmc_precision (DQMC_FP64 only in this version) */
+  int32_t precision;    /* dqmc_precision, the same for all instances of a handle */
   int32_t sym_measure;  /* 1: estimators on exp(-dtau K/2) G exp(+dtau K/2) */
   uint64_t seed;        /* Philox key */
 } dqmc_instance_desc;
@@ -129,12 +135,14 @@ dqmc_status dqmc_get_green(dqmc_handle h, int32_t inst, int32_t spin, double* ho
 dqmc_status dqmc_set_green(dqmc_handle h, int32_t inst, const double* host_in);
 
 /* Apply one wrap to G of every instance with the fields of slice l (1..M):
- * dir 0: G <- B_l G B_l^{-1}; dir 1: G <- B_l^{-1} G B_l (Sec. III A). */
+ * dir 0: G <- B_l G B_l^{-1}; dir 1: G <- B_l^{-1} G B_l (Sec. III A).  In
+ * DQMC_MIXED handles the transform runs in complex64 as in the sweep. */
 dqmc_status dqmc_wrap(dqmc_handle h, int32_t dir, int32_t slice, void* stream);
 
 /* Rank-k flush G <- G - X Y on instance inst with host X (N x k, column
  * j at X + j*N) and Y (k x N, row m at Y + m*N); elements as for G.
- * Exercises the MFMA flush kernel (eq. FinalDelay); synchronises. */
+ * Exercises the MFMA flush kernel (eq. FinalDelay) of the handle's
+ * precision; synchronises. */
 dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
                             const double* host_Y, int32_t k);
 

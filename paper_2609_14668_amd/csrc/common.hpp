@@ -35,6 +35,30 @@ DQMC_HD cplx cdiv(cplx a, cplx b) {
 }
 DQMC_HD double cdiv(double a, double b) { return a / b; }
 
+// Single-precision complex for the mixed-precision wrap (complex64 arithmetic).
+struct cplxf {
+  float x, y;
+};
+DQMC_HD cplxf cmakef(float a, float b) { cplxf c; c.x = a; c.y = b; return c; }
+DQMC_HD cplxf operator+(cplxf a, cplxf b) { return cmakef(a.x + b.x, a.y + b.y); }
+DQMC_HD cplxf operator-(cplxf a, cplxf b) { return cmakef(a.x - b.x, a.y - b.y); }
+DQMC_HD cplxf operator-(cplxf a) { return cmakef(-a.x, -a.y); }
+DQMC_HD cplxf operator*(cplxf a, cplxf b) { return cmakef(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+DQMC_HD cplxf operator*(float s, cplxf a) { return cmakef(s * a.x, s * a.y); }
+DQMC_HD cplxf operator*(cplxf a, float s) { return cmakef(s * a.x, s * a.y); }
+DQMC_HD cplxf conjg(cplxf a) { return cmakef(a.x, -a.y); }
+
+// Complex type of a real precision: cx_of<double> = cplx, cx_of<float> = cplxf.
+template <typename R> struct cx_of;
+template <> struct cx_of<double> {
+  typedef cplx type;
+  static DQMC_HD cplx make(double a, double b) { return cmake(a, b); }
+};
+template <> struct cx_of<float> {
+  typedef cplxf type;
+  static DQMC_HD cplxf make(double a, double b) { return cmakef((float)a, (float)b); }
+};
+
 template <typename S> struct ST;
 template <> struct ST<double> {
   static constexpr bool is_complex = false;
@@ -121,7 +145,7 @@ struct InstDev {
   int32_t is_complex;
   int32_t sym_measure;
   int32_t fft_fixed;        // 1: a compile-time FFT plan exists for L
-  int32_t pad_fft;
+  int32_t mixed;            // 1: wraps and flushes in single precision
   double lam;               // HS coupling lambda
   double U, dtau, t;
   double theta1, theta2;

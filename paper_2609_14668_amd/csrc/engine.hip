@@ -76,7 +76,8 @@ dqmc_status validate(const dqmc_instance_desc* d, int n, std::string& err) {
     if (x.n_stab < 1 || ((int)std::lround(M)) % x.n_stab != 0) { err = "n_stab must divide beta/dtau"; return DQMC_EINVAL; }
     if (x.n_stab != d[0].n_stab) { err = "all instances must share n_stab"; return DQMC_EINVAL; }
     if (x.n_delay < 1 || x.n_delay > MAX_DELAY) { err = "n_delay must be in [1, 192]"; return DQMC_EINVAL; }
-    if (x.precision != DQMC_FP64) { err = "only DQMC_FP64 is supported"; return DQMC_EUNSUPPORTED; }
+    if (x.precision != DQMC_FP64 && x.precision != DQMC_MIXED) { err = "unknown precision"; return DQMC_EINVAL; }
+    if (x.precision != d[0].precision) { err = "all instances must share the precision"; return DQMC_EINVAL; }
   }
   return DQMC_OK;
 }
@@ -161,6 +162,7 @@ struct dqmc_ctx {
   int kcap_max = 0;
   std::vector<int> fixedL;   // distinct L with a compile-time FFT plan
   bool any_generic = false;  // some L uses the runtime-plan FFT
+  bool mixed = false;        // wraps and flushes in single precision
   std::string err;
   // live timing
   bool timing = false;
@@ -239,15 +241,18 @@ struct Ctx {
   hipStream_t s;
   hipError_t e = hipSuccess;
   void chk(hipError_t x) { if (e == hipSuccess && x != hipSuccess) e = x; }
+  // Mixed precision: the wraps of G run in complex64; the B products of the
+  // stabilisation and the measurement's half step stay in FP64.
   void fft(int op, int side, int mat, int j = 0) {
     FftArgs a{op, side, mat, j, 0, 0, 0, 0};
+    const bool single = h->mixed && (op == FOP_WRAP_PRE || op == FOP_WRAP_POST);
     chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
-                   (int)h->fixedL.size(), h->any_generic, s));
+                   (int)h->fixedL.size(), h->any_generic, single, s));
   }
   void fft_explicit(int side, int mat, int pre, int tab, int post, int slice) {
     FftArgs a{FOP_EXPLICIT, side, mat, 0, pre, tab, post, slice};
     chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
-                   (int)h->fixedL.size(), h->any_generic, s));
+                   (int)h->fixedL.size(), h->any_generic, h->mixed, s));
   }
   void gemm(GemmOperand A, GemmOperand B, GemmOperand C, GemmDim M, GemmDim N, GemmDim K,
             double alpha, double beta, int flags = 0) {
@@ -381,13 +386,13 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
     }
     {
       TimedScope t(h, c.s, DQMC_T_FLUSH);
-      c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, GF_IF_FULL, c.s));
+      c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_FULL, c.s));
     }
     c.chk(launch_flush_done(h->dinst, h->n, 0, c.s));
   }
   {
     TimedScope t(h, c.s, DQMC_T_FLUSH);
-    c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, GF_IF_ANY, c.s));
+    c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
   }
   c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
   {
@@ -473,6 +478,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
   h->Nmax = p.Nmax;
   h->Mmax = p.Mmax;
   h->n_stab = p.n_stab;
+  h->mixed = d[0].precision == DQMC_MIXED;
   h->desc.assign(d, d + n);
   h->plan = p;
   for (int i = 0; i < n; ++i) {
@@ -509,6 +515,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.is_complex = p.cplx;
     dv.sym_measure = x.sym_measure;
     dv.fft_fixed = fft_has_fixed(x.L) ? 1 : 0;
+    dv.mixed = x.precision == DQMC_MIXED ? 1 : 0;
     dv.lam = std::acosh(std::exp(x.dtau * x.U / 2.0));
     dv.U = x.U; dv.dtau = x.dtau; dv.t = x.t;
     dv.theta1 = x.theta1; dv.theta2 = x.theta2;
@@ -730,7 +737,7 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X, c
   HIPCHK(h, hipMemcpyAsync(d.mat[MAT_Y], host_Y, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync((char*)d.st + offsetof(InstState, fill), &k, sizeof(int32_t), hipMemcpyHostToDevice, s));
   Ctx c{h, s};
-  c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, GF_IF_ANY, s));
+  c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, s));
   c.chk(launch_flush_done(h->dinst, h->n, 1, s));
   if (c.e != hipSuccess) return fail(h, DQMC_EHIP, hipGetErrorString(c.e));
   HIPCHK(h, hipStreamSynchronize(s));

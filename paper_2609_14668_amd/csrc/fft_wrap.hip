@@ -69,33 +69,44 @@ __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) 
   return r;
 }
 
-__device__ __forceinline__ cplx root_pow(const cplx* roots, int L, int m, int sign) {
-  cplx w = roots[m % L];
+// Complex compute type C is cplx (complex128) or cplxf (complex64); RT is its
+// real type.  Tables and roots are held in double and rounded once on load.
+template <typename C> using real_of = decltype(C::x);
+template <typename C> __device__ __forceinline__ C mkc(double a, double b) {
+  return C{(real_of<C>)a, (real_of<C>)b};
+}
+template <typename C> __device__ __forceinline__ C to_c(cplx a) { return mkc<C>(a.x, a.y); }
+
+template <typename C>
+__device__ __forceinline__ C root_pow(const C* roots, int L, int m, int sign) {
+  C w = roots[m % L];
   return sign < 0 ? w : conjg(w);
 }
 
 // Radix-R DFT of v in place: y_s = sum_r v_r w^{rs}, w = exp(sign 2 pi i / R).
-template <int R>
-__device__ __forceinline__ void small_dft(cplx* v, const cplx* roots, int L, int sign) {
+template <int R, typename C>
+__device__ __forceinline__ void small_dft(C* v, int sign) {
+  typedef real_of<C> RT;
   if constexpr (R == 2) {
-    cplx a = v[0], b = v[1];
+    C a = v[0], b = v[1];
     v[0] = a + b;
     v[1] = a - b;
   } else if constexpr (R == 4) {
-    cplx x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
-    cplx s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
+    C x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
+    C s02 = x0 + x2, d02 = x0 - x2, s13 = x1 + x3, d13 = x1 - x3;
     // w = sign * i: w * z = (-sign * z.y, sign * z.x)
-    cplx wd13 = cmake(-sign * d13.y, sign * d13.x);
+    const RT sg = (RT)sign;
+    C wd13 = C{-sg * d13.y, sg * d13.x};
     v[0] = s02 + s13;
     v[1] = d02 + wd13;
     v[2] = s02 - s13;
     v[3] = d02 - wd13;
   } else if constexpr (R == 3) {
-    const double c = -0.5, sn = 0.86602540378443864676 * sign;  // w = (c, sn)
-    cplx x0 = v[0], x1 = v[1], x2 = v[2];
-    cplx t = x1 + x2, u = x1 - x2;
-    cplx m = x0 + c * t;
-    cplx ju = cmake(-sn * u.y, sn * u.x);  // i * sn * u
+    const RT c = (RT)-0.5, sn = (RT)(0.86602540378443864676 * sign);  // w = (c, sn)
+    C x0 = v[0], x1 = v[1], x2 = v[2];
+    C t = x1 + x2, u = x1 - x2;
+    C m = x0 + c * t;
+    C ju = C{-sn * u.y, sn * u.x};  // i * sn * u
     v[0] = x0 + t;
     v[1] = m + ju;
     v[2] = m - ju;
@@ -103,8 +114,8 @@ __device__ __forceinline__ void small_dft(cplx* v, const cplx* roots, int L, int
 }
 
 // One Stockham stage of radix R on all lines of the nv vectors: src -> dst.
-template <int R>
-__device__ void fft_stage(const cplx* __restrict__ src, cplx* __restrict__ dst, const cplx* roots, int L,
+template <int R, typename C>
+__device__ void fft_stage(const C* __restrict__ src, C* __restrict__ dst, const C* roots, int L,
                           int Nc, int N, int nv, int axis, int Ns, int sign) {
   const int per_line = L / R;
   const int nb = nv * 2 * L * per_line;
@@ -119,23 +130,23 @@ __device__ void fft_stage(const cplx* __restrict__ src, cplx* __restrict__ dst, 
     int base = vv * N + s * Nc + o * ostride;
     int jm = j % Ns;
     int tw = twstep * jm;
-    cplx v[R];
+    C v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      cplx x = src[base + (j + r * per_line) * estride];
+      C x = src[base + (j + r * per_line) * estride];
       v[r] = (r && tw) ? x * root_pow(roots, L, tw * r, sign) : x;
     }
     int d0 = base + ((j / Ns) * Ns * R + jm) * estride;
     if constexpr (R <= 4) {
-      small_dft<R>(v, roots, L, sign);
+      small_dft<R>(v, sign);
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[d0 + r * Ns * estride] = v[r];
     } else {
       // y_s = sum_r v_r w^{rs}, one output at a time (w^s from the root table)
 #pragma unroll 1
       for (int s2 = 0; s2 < R; ++s2) {
-        const cplx step = s2 ? root_pow(roots, L, (L / R) * s2, sign) : cmake(1.0, 0.0);
-        cplx w = step, acc = v[0];
+        const C step = s2 ? root_pow(roots, L, (L / R) * s2, sign) : mkc<C>(1.0, 0.0);
+        C w = step, acc = v[0];
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           acc = acc + v[r] * w;
@@ -151,9 +162,9 @@ __device__ void fft_stage(const cplx* __restrict__ src, cplx* __restrict__ dst, 
 // Largest radix a kernel instance supports; the host picks the smallest set
 // that covers the factors of every instance's L.  Ping-pongs between the two
 // LDS buffers; returns the buffer that holds the result.
-template <int RMAX>
-__device__ cplx* fft_2d(cplx* cur, cplx* other, const cplx* roots, const int* fac, int L, int Nc, int N,
-                        int nv, int sign) {
+template <int RMAX, typename C>
+__device__ C* fft_2d(C* cur, C* other, const C* roots, const int* fac, int L, int Nc, int N,
+                     int nv, int sign) {
   for (int axis = 0; axis < 2; ++axis) {
     int Ns = 1;
     for (int f = 0; fac[f]; ++f) {
@@ -168,7 +179,7 @@ __device__ cplx* fft_2d(cplx* cur, cplx* other, const cplx* roots, const int* fa
         case 13: if constexpr (RMAX >= 13) fft_stage<13>(cur, other, roots, L, Nc, N, nv, axis, Ns, sign); break;
         default: break;  // rejected on the host
       }
-      cplx* t = cur; cur = other; other = t;
+      C* t = cur; cur = other; other = t;
       Ns *= R;
     }
   }
@@ -194,26 +205,27 @@ constexpr int fac_at(int L, int i) {
   return 0;
 }
 
-template <int L, int AXIS, int I, int NS>
-__device__ __forceinline__ void fixed_stages(cplx*& cur, cplx*& other, const cplx* roots, int nv, int sign) {
+template <int L, int AXIS, int I, int NS, typename C>
+__device__ __forceinline__ void fixed_stages(C*& cur, C*& other, const C* roots, int nv, int sign) {
   if constexpr (I < fac_count(L)) {
     constexpr int R = fac_at(L, I);
     fft_stage<R>(cur, other, roots, L, L * L, 2 * L * L, nv, AXIS, NS, sign);
-    cplx* t = cur; cur = other; other = t;
+    C* t = cur; cur = other; other = t;
     fixed_stages<L, AXIS, I + 1, NS * R>(cur, other, roots, nv, sign);
   }
 }
 
-template <int L>
-__device__ __forceinline__ cplx* fft_2d_fixed(cplx* cur, cplx* other, const cplx* roots, int nv, int sign) {
+template <int L, typename C>
+__device__ __forceinline__ C* fft_2d_fixed(C* cur, C* other, const C* roots, int nv, int sign) {
   fixed_stages<L, 0, 0, 1>(cur, other, roots, nv, sign);
   fixed_stages<L, 1, 0, 1>(cur, other, roots, nv, sign);
   return cur;
 }
 
-template <typename S, int RMAX, int LC>
+template <typename S, int RMAX, int LC, typename C>
 __global__ void __launch_bounds__(FFT_THREADS)
 k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_only) {
+  typedef real_of<C> RT;
   extern __shared__ char smem_raw[];
   const InstDev& d = insts[blockIdx.y];
   if (LC > 0 ? d.L != LC : (generic_only && d.fft_fixed)) return;
@@ -225,17 +237,15 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
   const int v0 = blockIdx.x * nv;
   if (v0 >= nvec) return;
   const int nvl = min(nv, nvec - v0);
-  cplx* buf = reinterpret_cast<cplx*>(smem_raw);
-  cplx* buf2 = buf + (size_t)nv * N;
-  __shared__ cplx roots[64];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  C* buf2 = buf + (size_t)nv * N;
+  __shared__ C roots[64];
   __shared__ int fac[16];
-  __shared__ double dpre[1], dpost[1];
-  (void)dpre; (void)dpost;
-  if (threadIdx.x < L) roots[threadIdx.x] = d.roots[threadIdx.x];
+  if (threadIdx.x < L) roots[threadIdx.x] = to_c<C>(d.roots[threadIdx.x]);
   if (threadIdx.x < 16) fac[threadIdx.x] = d.factors[threadIdx.x];
   S* Mx = matp<S>(d, a.mat);
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
-  const double ep = exp(d.lam), em = exp(-d.lam);
+  const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
   const bool rows = a.side != 0;
   // load (+ pre diagonal)
   const int tot = nvl * N;
@@ -244,28 +254,29 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     if (!rows) { vv = e / N; r = e - vv * N; }
     else { vv = e % nvl; r = e / nvl; }
     int q = v0 + vv;
-    cplx val;
+    C val;
     if constexpr (ST<S>::is_complex) {
       cplx g = rows ? Mx[(size_t)r * N + q] : Mx[(size_t)q * N + r];
-      val = rows ? conjg(g) : g;
+      val = mkc<C>(g.x, rows ? -g.y : g.y);
     } else {
-      if (!rows) val = cmake(Mx[(size_t)(2 * q) * N + r], Mx[(size_t)(2 * q + 1) * N + r]);
-      else val = cmake(Mx[(size_t)r * N + 2 * q], Mx[(size_t)r * N + 2 * q + 1]);
+      if (!rows) val = mkc<C>(Mx[(size_t)(2 * q) * N + r], Mx[(size_t)(2 * q + 1) * N + r]);
+      else val = mkc<C>(Mx[(size_t)r * N + 2 * q], Mx[(size_t)r * N + 2 * q + 1]);
     }
     if (rs.pre) val = val * ((rs.pre * xs[r]) > 0 ? ep : em);
     buf[vv * N + r] = val;
   }
   __syncthreads();
-  cplx* cur;
+  C* cur;
   if constexpr (LC > 0) cur = fft_2d_fixed<LC>(buf, buf2, roots, nvl, -1);
   else cur = fft_2d<RMAX>(buf, buf2, roots, fac, L, Nc, N, nvl, -1);
-  cplx* oth = cur == buf ? buf2 : buf;
+  C* oth = cur == buf ? buf2 : buf;
   // 2x2 block per momentum
   const cplx* T = d.tab + (size_t)rs.tab * Nc * 4;
   for (int e = threadIdx.x; e < nvl * Nc; e += FFT_THREADS) {
     int vv = e / Nc, k = e - vv * Nc;
-    cplx qa = cur[vv * N + k], qb = cur[vv * N + Nc + k];
-    cplx t00 = T[4 * k], t01 = T[4 * k + 1], t10 = T[4 * k + 2], t11 = T[4 * k + 3];
+    C qa = cur[vv * N + k], qb = cur[vv * N + Nc + k];
+    C t00 = to_c<C>(T[4 * k]), t01 = to_c<C>(T[4 * k + 1]), t10 = to_c<C>(T[4 * k + 2]),
+      t11 = to_c<C>(T[4 * k + 3]);
     cur[vv * N + k] = t00 * qa + t01 * qb;
     cur[vv * N + Nc + k] = t10 * qa + t11 * qb;
   }
@@ -278,23 +289,24 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     if (!rows) { vv = e / N; r = e - vv * N; }
     else { vv = e % nvl; r = e / nvl; }
     int q = v0 + vv;
-    cplx val = cur[vv * N + r];
+    C val = cur[vv * N + r];
     if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
+    const double vx = (double)val.x, vy = (double)val.y;
     if constexpr (ST<S>::is_complex) {
-      if (rows) Mx[(size_t)r * N + q] = conjg(val);
-      else Mx[(size_t)q * N + r] = val;
+      if (rows) Mx[(size_t)r * N + q] = cmake(vx, -vy);
+      else Mx[(size_t)q * N + r] = cmake(vx, vy);
     } else {
-      if (!rows) { Mx[(size_t)(2 * q) * N + r] = val.x; Mx[(size_t)(2 * q + 1) * N + r] = val.y; }
-      else { Mx[(size_t)r * N + 2 * q] = val.x; Mx[(size_t)r * N + 2 * q + 1] = val.y; }
+      if (!rows) { Mx[(size_t)(2 * q) * N + r] = vx; Mx[(size_t)(2 * q + 1) * N + r] = vy; }
+      else { Mx[(size_t)r * N + 2 * q] = vx; Mx[(size_t)r * N + 2 * q + 1] = vy; }
     }
   }
 }
 
 }  // namespace
 
-int fft_vectors_per_block(int N, size_t lds_budget) {
+int fft_vectors_per_block(int N, size_t lds_budget, size_t elem_bytes) {
   // two ping-pong buffers of nv vectors
-  int nv = (int)(lds_budget / (2 * (size_t)N * sizeof(cplx)));
+  int nv = (int)(lds_budget / (2 * (size_t)N * elem_bytes));
   if (nv > 16) nv = 16;
   return nv < 1 ? 1 : nv;
 }
@@ -315,26 +327,44 @@ bool fft_has_fixed(int L) {
 }
 
 namespace {
-template <typename S, int LC>
+template <typename S, int LC, typename C>
 void launch_fixed(const InstDev* insts, int n_inst, const FftArgs& a, size_t lds_budget, hipStream_t s) {
   constexpr int N = 2 * LC * LC;
-  int nv = fft_vectors_per_block(N, lds_budget);
+  int nv = fft_vectors_per_block(N, lds_budget, sizeof(C));
   int nvec = ST<S>::is_complex ? N : N / 2;
   dim3 grid((nvec + nv - 1) / nv, n_inst);
-  size_t lds = 2 * (size_t)nv * N * sizeof(cplx);
-  constexpr int R = (fac_count(LC) > 0) ? 13 : 13;  // unused by the fixed path
-  hipLaunchKernelGGL((k_fft_apply<S, R, LC>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 0);
+  size_t lds = 2 * (size_t)nv * N * sizeof(C);
+  constexpr int R = 13;  // unused by the fixed path
+  hipLaunchKernelGGL((k_fft_apply<S, R, LC, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 0);
+}
+
+template <typename S, typename C>
+void launch_generic(const InstDev* insts, int n_inst, int Nmax, const FftArgs& a, size_t lds_budget, int rmax,
+                    hipStream_t s) {
+  int nv = fft_vectors_per_block(Nmax, lds_budget, sizeof(C));
+  int nvec = ST<S>::is_complex ? Nmax : Nmax / 2;
+  dim3 grid((nvec + nv - 1) / nv, n_inst);
+  size_t lds = 2 * (size_t)nv * Nmax * sizeof(C);
+  if (rmax <= 4) hipLaunchKernelGGL((k_fft_apply<S, 4, 0, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);
+  else if (rmax <= 7) hipLaunchKernelGGL((k_fft_apply<S, 7, 0, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);
+  else hipLaunchKernelGGL((k_fft_apply<S, 13, 0, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);
 }
 }  // namespace
 
 hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, const FftArgs& a,
-                      size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, hipStream_t s) {
+                      size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, bool single,
+                      hipStream_t s) {
   for (int q = 0; q < nL; ++q) {
     switch (Ls[q]) {
-#define DQMC_CASE(v)                                                          \
-  case v:                                                                     \
-    if (cplx_) launch_fixed<cplx, v>(insts, n_inst, a, lds_budget, s);        \
-    else launch_fixed<double, v>(insts, n_inst, a, lds_budget, s);            \
+#define DQMC_CASE(v)                                                                         \
+  case v:                                                                                    \
+    if (single) {                                                                            \
+      if (cplx_) launch_fixed<cplx, v, cplxf>(insts, n_inst, a, lds_budget, s);              \
+      else launch_fixed<double, v, cplxf>(insts, n_inst, a, lds_budget, s);                  \
+    } else {                                                                                 \
+      if (cplx_) launch_fixed<cplx, v, cplx>(insts, n_inst, a, lds_budget, s);               \
+      else launch_fixed<double, v, cplx>(insts, n_inst, a, lds_budget, s);                   \
+    }                                                                                        \
     break;
       DQMC_FIXED_L(DQMC_CASE)
 #undef DQMC_CASE
@@ -342,16 +372,12 @@ hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, co
     }
   }
   if (!any_generic) return hipGetLastError();
-  int nv = fft_vectors_per_block(Nmax, lds_budget);
-  int nvec = cplx_ ? Nmax : Nmax / 2;
-  dim3 grid((nvec + nv - 1) / nv, n_inst);
-  size_t lds = 2 * (size_t)nv * Nmax * sizeof(cplx);
-#define DQMC_FFT_LAUNCH(R)                                                                                         \
-  if (cplx_) hipLaunchKernelGGL((k_fft_apply<cplx, R, 0>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);   \
-  else hipLaunchKernelGGL((k_fft_apply<double, R, 0>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);
-  if (rmax <= 4) { DQMC_FFT_LAUNCH(4) }
-  else if (rmax <= 7) { DQMC_FFT_LAUNCH(7) }
-  else { DQMC_FFT_LAUNCH(13) }
-#undef DQMC_FFT_LAUNCH
+  if (single) {
+    if (cplx_) launch_generic<cplx, cplxf>(insts, n_inst, Nmax, a, lds_budget, rmax, s);
+    else launch_generic<double, cplxf>(insts, n_inst, Nmax, a, lds_budget, rmax, s);
+  } else {
+    if (cplx_) launch_generic<cplx, cplx>(insts, n_inst, Nmax, a, lds_budget, rmax, s);
+    else launch_generic<double, cplx>(insts, n_inst, Nmax, a, lds_budget, rmax, s);
+  }
   return hipGetLastError();
 }

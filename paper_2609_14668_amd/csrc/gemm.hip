@@ -315,6 +315,100 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
   }
 }
 
+// Single-precision flush for mixed-precision instances: the product X Y is
+// formed with FP32 MFMA 16x16x4 (X and Y rounded to float on load, FP32
+// accumulation) and subtracted from the FP64 G.  Same block structure as the
+// FP64 kernel; the FP32 MFMA result of lane l holds column l%16 of the
+// transposed block at rows 4(l/16) + r.
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_flush_f32(const InstDev* __restrict__ insts, int flags) {
+  constexpr bool CX = ST<S>::is_complex;
+  const InstDev& d = insts[blockIdx.y];
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return;
+  if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
+  if ((flags & GF_IF_ANY) && st.fill <= 0) return;
+  const int N = d.N;
+  const int K = st.fill;
+  const S* X = reinterpret_cast<const S*>(d.mat[MAT_X]);
+  const S* Y = reinterpret_cast<const S*>(d.mat[MAT_Y]);
+  S* G = reinterpret_cast<S*>(d.mat[MAT_G]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb32 = (N + 31) / 32;
+  const int nblk = nb32 * nb32;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+    const int i0 = (blk % nb32) * 32, j0 = (blk / nb32) * 32;
+    f4 ar_[2][2], ai_[2][2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) { ar_[ti][tj] = f4{0, 0, 0, 0}; ai_[ti][tj] = f4{0, 0, 0, 0}; }
+    auto frag = [&](int k, float (&xr)[2], float (&xi)[2], float (&yr)[2], float (&yi)[2]) {
+      const int kk = k + lk;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        int gi = i0 + t * 16 + lr, gj = j0 + t * 16 + lr;
+        double a = 0, b = 0, c = 0, e = 0;
+        if (kk < K) {
+          if (gi < N) split<S>(X[gi + (size_t)kk * N], a, b);
+          if (gj < N) split<S>(Y[(size_t)kk * N + gj], c, e);
+        }
+        xr[t] = (float)a; xi[t] = (float)b; yr[t] = (float)c; yi[t] = (float)e;
+      }
+    };
+    float xr[2], xi[2], yr[2], yi[2], nxr[2], nxi[2], nyr[2], nyi[2];
+    frag(0, xr, xi, yr, yi);
+    frag(4, nxr, nxi, nyr, nyi);
+    for (int k = 0; k < K; k += 4) {
+      float mxr[2], mxi[2], myr[2], myi[2];
+      frag(k + 8, mxr, mxi, myr, myi);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) ar_[ti][tj] = mfma32(yr[tj], xr[ti], ar_[ti][tj]);
+      if constexpr (CX) {
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma32(yi[tj], xr[ti], ai_[ti][tj]);
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) ar_[ti][tj] = mfma32(-yi[tj], xi[ti], ar_[ti][tj]);
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma32(yr[tj], xi[ti], ai_[ti][tj]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        xr[t] = nxr[t]; xi[t] = nxi[t]; yr[t] = nyr[t]; yi[t] = nyi[t];
+        nxr[t] = mxr[t]; nxi[t] = mxi[t]; nyr[t] = myr[t]; nyi[t] = myi[t];
+      }
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int gi = i0 + ti * 16 + lr, gj = j0 + tj * 16 + 4 * lk + r;
+          if (gi < N && gj < N) {
+            S& g = G[gi + (size_t)gj * N];
+            if constexpr (CX) g = cmake(g.x - (double)ar_[ti][tj][r], g.y - (double)ai_[ti][tj][r]);
+            else g = g - (double)ar_[ti][tj][r];
+          }
+        }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, GemmOperand A,
@@ -332,12 +426,18 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
   return hipGetLastError();
 }
 
-hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int flags, hipStream_t s) {
+hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, bool single, int flags,
+                               hipStream_t s) {
   int nb32 = (Nmax + 31) / 32;
   int blocks = (nb32 * nb32 + 3) / 4;
   int cap = 8192 / (n_inst > 0 ? n_inst : 1);
   if (cap < 16) cap = 16;
   dim3 grid(blocks < cap ? blocks : cap, n_inst);
+  if (single) {
+    if (cplx_) hipLaunchKernelGGL(k_flush_f32<cplx>, grid, dim3(256), 0, s, insts, flags);
+    else hipLaunchKernelGGL(k_flush_f32<double>, grid, dim3(256), 0, s, insts, flags);
+    return hipGetLastError();
+  }
   if (cplx_) hipLaunchKernelGGL(k_flush_direct<cplx>, grid, dim3(256), 0, s, insts, flags);
   else hipLaunchKernelGGL(k_flush_direct<double>, grid, dim3(256), 0, s, insts, flags);
   return hipGetLastError();

@@ -12,12 +12,13 @@ struct FftArgs {
   int j;       // chunk position for FOP_STAB_B
   int ex_pre, ex_tab, ex_post, ex_slice;  // FOP_EXPLICIT: diagonal signs, table, slice
 };
-int fft_vectors_per_block(int N, size_t lds_budget);
+int fft_vectors_per_block(int N, size_t lds_budget, size_t elem_bytes);
 // Ls: the distinct L with a compile-time plan among the instances;
 // any_generic: some instance needs the runtime-plan kernel.
 bool fft_has_fixed(int L);
 hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, const FftArgs& a,
-                      size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, hipStream_t s);
+                      size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, bool single,
+                      hipStream_t s);
 
 // ---- batched GEMM on named matrices (FP64 MFMA) --------------------------------------
 // C = alpha * op(A) op(B) + beta * C for every instance.  Row/column offsets
@@ -42,8 +43,10 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
                        double alpha, double beta, int flags, hipStream_t s);
 
 // Flush G <- G - X[:, :fill] Y[:fill, :] straight from memory (no LDS);
-// flags: GF_IF_FULL or GF_IF_ANY.
-hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int flags, hipStream_t s);
+// flags: GF_IF_FULL or GF_IF_ANY.  single: the product X Y is formed with
+// FP32 MFMA (operands rounded to float) and subtracted from the FP64 G.
+hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, bool single, int flags,
+                               hipStream_t s);
 
 // ---- delayed update -------------------------------------------------------------------
 hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, int replay,
