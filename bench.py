@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--k", type=int, default=None, help="flush rank override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-fp64-twin", action="store_true",
+                    help="mixed precision: skip the FP64 run of the same chains used for the bias")
     return ap.parse_args()
 
 
@@ -85,6 +87,42 @@ def cpu_baseline(descs, seconds):
     return {"value": props / dt, "unit": "HS field updates/s", "cores": int(cores), "kind": "oracle",
             "sample": "%d upward slice-steps of one L=%d chain (%d proposals, %.1f s), both spins dense"
                       % (slices, d["L"], props, dt)}
+
+
+def fp64_twin(descs, warmup, sweeps, main_series):
+    """Run the same chains (same seeds) in FP64 for the same number of sweeps
+    and compare the per-sweep estimator means: bias = mean(mixed) - mean(fp64)
+    with the combined standard error of the two series (sweep means taken as
+    independent, which understates sigma when tau_int > 1/2)."""
+    import torch
+    from paper_2609_14668_amd import Simulation
+    d64 = [dict(d, precision=0) for d in descs]
+    sim = Simulation(d64)
+    for _ in range(warmup):
+        sim.sweep(1, measure=True)
+    sim.reset_obs()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(sweeps):
+        sim.sweep(1, measure=True)
+        torch.cuda.synchronize()
+        print("fp64 twin sweep %d done" % (s + 1), file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    out = {"ms_per_sweep": 1e3 * dt / max(sweeps, 1), "drift_max": max(sim.stats(i)["drift_max"]
+                                                                     for i in range(len(d64)))}
+    bias = {}
+    for key in ("D", "ekin", "e", "m2", "Szz_G"):
+        a = np.concatenate([main_series[i][key] for i in range(len(d64))])
+        b = np.concatenate([sim.series(i)[key] for i in range(len(d64))])
+        n = min(len(a), len(b))
+        if n < 2:
+            continue
+        a, b = a[-n:], b[-n:]
+        sig = float(np.sqrt(a.var(ddof=1) / n + b.var(ddof=1) / n))
+        bias[key] = {"mixed_minus_fp64": float(a.mean() - b.mean()), "sigma": sig}
+    out["bias"] = bias
+    sim.close()
+    return out
 
 
 def main():
@@ -179,6 +217,13 @@ def main():
                                  "traffic": None, "launches": wr["launches"],
                                  "avg_launch_us": 1e3 * wr["ms"] / max(wr["launches"], 1)}
     line["time_split_ms"] = {k: round(tim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab")}
+    if descs[0]["precision"] == 1:
+        line["roofline"]["kernel"] = "k_flush_f32 (G -= X Y, FP32 MFMA)"
+        line["roofline"]["peak"] = 157.3  # FP32 matrix peak for the FP32 flush
+        line["roofline"]["frac"] = line["roofline"]["achieved"] / 157.3
+        if not a.no_fp64_twin:
+            ser = [sim.series(i) for i in range(n)]
+            line["fp64_twin"] = fp64_twin(descs, a.warmup, a.steps, ser)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(descs, a.cpu_seconds)
     print(json.dumps(line))
