@@ -177,8 +177,9 @@ class RandomSource:
 class Chain:
     """One DQMC Markov chain; both spins propagated densely and independently."""
 
-    def __init__(self, model, fields, sym_measure=False):
+    def __init__(self, model, fields, sym_measure=False, learned=None):
         self.m = model
+        self.learned = learned     # oracle.pnet.LearnedMoves applied after each slice's site updates
         self.fields = np.array(fields, dtype=np.int8).reshape(model.M, model.N).copy()
         if not np.all(np.abs(self.fields) == 1):
             raise ValueError("fields must be +-1")
@@ -224,6 +225,8 @@ class Chain:
                     self.G[s] = G - np.outer(xv, yv)
                 self.fields[l - 1, i] = -self.fields[l - 1, i]
                 self.accepted += 1
+        if self.learned is not None:
+            self.learned.apply(self, l, pas)
 
     def stabilise(self, l, measure=True):
         for s in (0, 1):

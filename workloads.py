@@ -81,3 +81,27 @@ def plain_L42():
 # channel, beta t = L, dtau = 0.05, symmetric Trotter measurement).
 def table_point(L, U=3.75):
     return desc(L, U, float(L), dtau=0.05, sym_measure=1)
+
+
+# ---- proposal network inputs (random weights of the layout [tap][out][in]) ----------
+NET_SHAPES = [(27, 32, 2), (32,), (27, 32, 32), (32,), (27, 2, 32), (2,)]
+
+
+def net_weights(seed, gain=1.0, bias=0.1):
+    """Flat parameter vector W1, b1, W2, b2, W3, b3 with N(0, gain^2 / fan_in)
+    weights and N(0, bias^2) biases."""
+    rng = np.random.default_rng(int(seed))
+    out = []
+    for shp in NET_SHAPES:
+        if len(shp) == 3:
+            fan = shp[0] * shp[2]
+            out.append(rng.standard_normal(shp).ravel() * gain / math.sqrt(fan))
+        else:
+            out.append(rng.standard_normal(shp) * bias)
+    return np.concatenate(out)
+
+
+def net_targets(seed, shape):
+    """Targets in [0, 1] for loss/gradient checks."""
+    rng = np.random.default_rng(int(seed))
+    return rng.random(shape)
