@@ -97,6 +97,7 @@ typedef struct {
   int64_t proposals, accepted, flushes, sweeps;
   double drift_max, drift_last;
   int32_t numeric_err;
+  int64_t learn_proposals, learn_accepted;  /* learned multi-site moves */
 } dqmc_stats;
 
 /* Bytes of device workspace for n instances (ws: output). */
@@ -161,7 +162,7 @@ dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out);  /* sy
  * wrap = 2 N^2 s bytes per instance per side-pass (one read and one write of
  * G, s = bytes per element). */
 typedef enum { DQMC_T_WRAP = 0, DQMC_T_WINDOW, DQMC_T_EXPAND, DQMC_T_FLUSH, DQMC_T_STAB, DQMC_T_MEASURE,
-               DQMC_T_COUNT } dqmc_timing_class;
+               DQMC_T_LEARN, DQMC_T_COUNT } dqmc_timing_class;
 typedef struct {
   int64_t launches[DQMC_T_COUNT];
   double ms[DQMC_T_COUNT];
@@ -170,6 +171,106 @@ typedef struct {
 } dqmc_timing;
 dqmc_status dqmc_set_timing(dqmc_handle h, int32_t on);   /* on: 1 enable (and reset), 0 disable */
 dqmc_status dqmc_get_timing(dqmc_handle h, dqmc_timing* out);  /* synchronises */
+
+/* ---- Learned multi-site moves (an extension; the paper proposes single sites).
+ *
+ * After the single-site updates of every slice visit, per_slice moves flip an
+ * ordered set S of m distinct sites of that slice at once.  S is drawn from
+ * the Plackett-Luce law of the weights sigmoid(y_i) of the network outputs
+ * y_i of the slice, i.e. of the logits z_i = log sigmoid(y_i) (q(S|X) =
+ * prod_j e^{z_{s_j}} / sum over the sites not yet chosen of e^{z_i}), with
+ * Gumbel-top-m: the m largest z_i - log(-log u_i).  Trained on the Barker
+ * acceptances below (y ~ log Rt) this is a locally balanced informed
+ * proposal.  The move is accepted iff
+ * u < R_S q(S|X') / q(S|X), where R_S = e^{2 lambda sum_S x} |det(1_m +
+ * Delta_S (1 - G)_{SS})|^2 is the block form of the paper's single-site ratio
+ * (eqs. DRatio, rRatioLocal) and X' has the sites of S flipped; on acceptance
+ * G takes the block Sherman-Morrison update through the delayed-update
+ * buffers (eqs. DelayRgenk, FinalDelay).  The chain stays exact for any
+ * network.  Uniforms: Philox4x32-10 with the instance's key and counter
+ * (site, slice, sweep, 4 + 4 move + pass) for the Gumbel noise, with
+ * u = (floor(k/2) + 1/2) 2^-52 for the 53-bit k of the site uniforms, and
+ * counter (0xffffffff, slice, sweep, 4 + 4 move + pass) for the acceptance
+ * u = k 2^-53.
+ *
+ * The network maps the fields of all slices on the cell grid, channels
+ * (x_A, x_B), through three periodic 3x3x3 convolutions over (slice, n2, n1)
+ * of widths 2 -> 32 -> 32 -> 2 (tanh after the first two, biases everywhere)
+ * to the outputs (y_A, y_B) of each cell.  Parameters, FP32, in this order:
+ * W1 [27][32][2], b1 [32], W2 [27][32][32], b2 [32], W3 [27][2][32], b3 [2]
+ * (DQMC_NET_NPARAM values); tap (dt+1)*9 + (d2+1)*3 + (d1+1) of an output
+ * at (t, n2, n1) reads (t+dt, n2+d2, n1+d1), periodic; [tap][out][in].
+ * The device computes with BF16 weights and activations and FP32
+ * accumulation.  A new handle starts with all parameters zero (uniform
+ * proposals).  The training loss is the mean binary cross-entropy between
+ * sigmoid(y_i) and targets a_i in [0, 1] over all sites and slices. */
+#define DQMC_NET_NPARAM 31170
+
+/* Moves per slice visit (0 disables, at most 8) and sites per move (1..8);
+ * not applied in replay mode. */
+dqmc_status dqmc_set_proposals(dqmc_handle h, int32_t per_slice, int32_t m);
+
+/* Parameters in and out (host FP32, n = DQMC_NET_NPARAM).  Setting them
+ * resets the Adam moments. */
+dqmc_status dqmc_net_set_weights(dqmc_handle h, const float* host_w, int64_t n);
+dqmc_status dqmc_net_get_weights(dqmc_handle h, float* host_w, int64_t n);
+/* Starting point for training: W1, W2 drawn N(0, 1/fan_in) from a generator
+ * seeded with seed, W3 and all biases zero (the proposals stay uniform until
+ * trained); resets the Adam moments. */
+dqmc_status dqmc_net_init(dqmc_handle h, uint64_t seed);
+
+/* Training data recorded by the sampler: for every site of instance inst,
+ * the Barker acceptance Rt / (1 + Rt) of flipping it again right after its
+ * single-site decision in the last downward pass (Rt = 1/R after an accepted
+ * flip, R after a rejected one), M x N floats. */
+dqmc_status dqmc_get_targets(dqmc_handle h, int32_t inst, float* host_out);
+
+/* Training samples.  With every > 0, after the single-site updates of every
+ * downward-pass slice l with l % every == 0, each instance stores its field
+ * window of slices l-3 .. l+3 (mod M; 7 x N int8) and the targets of slice l
+ * (N floats) in a device ring of `capacity` slots (a multiple of the number
+ * of instances n): instance i writes slots (c n + i) % capacity for its c-th
+ * sample.  The logits of slice l depend on no field outside that window. */
+dqmc_status dqmc_collect(dqmc_handle h, int32_t every);
+/* Slots filled so far (all instances), and the ring capacity.  Synchronises. */
+dqmc_status dqmc_sample_count(dqmc_handle h, int64_t* filled, int64_t* capacity);
+/* Copy count slots from slot first: windows count x 7 x Nmax int8 (rows of
+ * Nmax entries, an instance's first N used), targets count x Nmax floats;
+ * Nmax = the largest N of the handle.  Synchronises. */
+dqmc_status dqmc_get_samples(dqmc_handle h, int64_t first, int32_t count, int8_t* host_win, float* host_tg);
+
+/* Device scratch for dqmc_net_logits / dqmc_net_grad on configurations of one
+ * size (L, M), n_samples of them per call, minibatches of batch <= 64; with
+ * M = 7 also enough for window samples. */
+dqmc_status dqmc_net_workspace_size(int32_t L, int32_t M, int64_t n_samples, int32_t batch, size_t* bytes);
+
+/* Logits of n configurations (host int8 n x M x N) into host_out
+ * (n x M x N floats), convolutions periodic in time; n <= 64.  dev_ws:
+ * caller-owned device scratch of dqmc_net_workspace_size(L, M, n, n) bytes.
+ * Synchronises. */
+dqmc_status dqmc_net_logits(dqmc_handle h, void* dev_ws, size_t bytes, const int8_t* host_fields, int32_t n,
+                            int32_t L, int32_t M, float* host_out);
+
+/* Loss and gradient (host, DQMC_NET_NPARAM floats) over a batch of n <= 64
+ * samples.  window = 0: whole configurations (n x M x N) with targets for
+ * every site (n x M x N floats).  window = 1: 7-slice windows (n x 7 x N,
+ * M = 7) with targets of the centre slice only (n x N floats), evaluated as
+ * the sampler and the trainer do.  Synchronises. */
+dqmc_status dqmc_net_grad(dqmc_handle h, void* dev_ws, size_t bytes, const int8_t* host_fields,
+                          const float* host_targets, int32_t n, int32_t L, int32_t M, int32_t window,
+                          float* host_loss, float* host_grad);
+
+/* Device scratch for dqmc_net_train with minibatches of `batch` samples. */
+dqmc_status dqmc_net_train_workspace_size(dqmc_handle h, int32_t batch, size_t* bytes);
+
+/* steps Adam steps (lr; beta1 0.9, beta2 0.999, eps 1e-8) on the window
+ * loss of minibatches of `batch` samples drawn with replacement from the
+ * filled ring slots by a generator seeded with seed.  host_loss (nullable)
+ * receives the minibatch loss of every step.  The sampler uses the new
+ * parameters from its next launch on.  DQMC_ESTATE if no sample has been
+ * collected.  Synchronises. */
+dqmc_status dqmc_net_train(dqmc_handle h, void* dev_ws, size_t bytes, int32_t steps, int32_t batch, float lr,
+                           uint64_t seed, float* host_loss);
 
 /* Matrix dimension N, slices M and whether G is complex, for instance inst. */
 dqmc_status dqmc_shape(dqmc_handle h, int32_t inst, int32_t* N, int32_t* M, int32_t* is_complex);

@@ -177,9 +177,19 @@ class RandomSource:
 class Chain:
     """One DQMC Markov chain; both spins propagated densely and independently."""
 
-    def __init__(self, model, fields, sym_measure=False, learned=None):
+    def __init__(self, model, fields, sym_measure=False, learned=None, collect_every=0):
         self.m = model
         self.learned = learned     # oracle.pnet.LearnedMoves applied after each slice's site updates
+        # training data of the proposal network: for every site, the Barker
+        # acceptance Rt/(1+Rt) of flipping it again right after its decision in
+        # the downward pass (Rt = 1/R after an accepted flip, R after a
+        # rejected one), and
+        # (every collect_every-th slice l of that pass, l % collect_every == 0)
+        # the 7-slice field window l-3 .. l+3 (mod M) with slice l's targets,
+        # taken after the slice's single-site updates
+        self.targets = np.zeros((model.M, model.N))
+        self.collect_every = int(collect_every)
+        self.collected = []
         self.fields = np.array(fields, dtype=np.int8).reshape(model.M, model.N).copy()
         if not np.all(np.abs(self.fields) == 1):
             raise ValueError("fields must be +-1")
@@ -216,7 +226,8 @@ class Chain:
             R = (r[0] * r[1]).real
             self.ratios.append(R)
             self.proposals += 1
-            if decide(self.sweep_index, pas, l, i, R):
+            acc = decide(self.sweep_index, pas, l, i, R)
+            if acc:
                 for s in (0, 1):
                     G = self.G[s]
                     xv = G[:, i] * (dl[s] / r[s])
@@ -225,6 +236,11 @@ class Chain:
                     self.G[s] = G - np.outer(xv, yv)
                 self.fields[l - 1, i] = -self.fields[l - 1, i]
                 self.accepted += 1
+            if pas == 1:
+                self.targets[l - 1, i] = 1.0 / (1.0 + R) if acc else R / (1.0 + R)
+        if pas == 1 and self.collect_every and l % self.collect_every == 0:
+            rows = [(l - 1 + a - 3) % self.m.M for a in range(7)]
+            self.collected.append((l, self.fields[rows].copy(), self.targets[l - 1].copy()))
         if self.learned is not None:
             self.learned.apply(self, l, pas)
 

@@ -22,18 +22,23 @@ channel 1 of the B site.  Tap index (dt+1)*9 + (d2+1)*3 + (d1+1): output
 stored [tap][out channel][in channel]; the flat parameter vector is
 W1 (27x32x2), b1 (32), W2 (27x32x32), b2 (32), W3 (27x2x32), b3 (2).
 
-Training loss: mean binary cross-entropy between sigmoid(z_i) and a target
-a_i in [0, 1] (the single-flip acceptance probability recorded by the
-sampler), over all sites and slices of the batch.
+Training loss: mean binary cross-entropy between sigmoid(y_i) of the
+network output y_i and a target a_i in [0, 1] (the Barker acceptance
+Rt/(1+Rt) of a single flip, recorded by the sampler), over all sites and
+slices of the batch.
 
 Proposal: an ordered set S = (s_1..s_m) of distinct sites of slice l drawn
-from the Plackett-Luce distribution of the slice's logits,
+from the Plackett-Luce distribution of the weights w_i = sigmoid(y_i), i.e.
+of the logits z_i = log sigmoid(y_i),
     q(S | X) = prod_j exp(z_{s_j}) / sum_{i not in s_1..s_{j-1}} exp(z_i),
 sampled as the m largest z_i + g_i (Gumbel-top-m, Gumbel noise
-g = -log(-log u)).  Uniforms: Philox4x32-10 with key (seed lo, seed hi) and
+g = -log(-log u)).  A network that predicts y = log Rt turns this into the
+locally balanced (Barker) informed proposal.  Uniforms: Philox4x32-10 with key (seed lo, seed hi) and
 counter (site, slice, sweep, 4 + 4 move + pass) for the Gumbel noise of a
-site, (0xffffffff, slice, sweep, 4 + 4 move + pass) for the acceptance; the
-Gumbel uniform is the open-interval (k + 1/2) 2^-53 of the same 53 bits k.
+site, (0xffffffff, slice, sweep, 4 + 4 move + pass) for the acceptance.  The
+acceptance uniform is the usual 53-bit k 2^-53, k = w0 2^21 + (w1 >> 11); the
+Gumbel uniform is the open-interval value (floor(k / 2) + 1/2) 2^-52, exact in
+double precision and never 0 or 1.
 """
 import numpy as np
 
@@ -123,8 +128,18 @@ def logits(p, x, L):
 
 
 def slice_logits(p, x, L, l):
-    """Logits of the N sites of slice l (1-based) of the configuration x (M, N)."""
+    """Network outputs y of the N sites of slice l (1-based) of the configuration x (M, N)."""
     return logits(p, x, L)[l - 1]
+
+
+def log_sigmoid(y):
+    y = np.asarray(y, dtype=np.float64)
+    return np.where(y >= 0, -np.log1p(np.exp(-np.abs(y))), y - np.log1p(np.exp(-np.abs(y))))
+
+
+def proposal_logits(p, x, L, l):
+    """Plackett-Luce logits z = log sigmoid(y) of the sites of slice l."""
+    return log_sigmoid(slice_logits(p, x, L, l))
 
 
 def bce(z, a):
@@ -132,9 +147,11 @@ def bce(z, a):
     return np.maximum(z, 0.0) - a * z + np.log1p(np.exp(-np.abs(z)))
 
 
-def loss_and_grad(p, xs, targets, L):
+def loss_and_grad(p, xs, targets, L, slices=None):
     """Mean BCE over a batch of configurations xs (B, T, N) with targets
-    (B, T, N); returns (loss, flat gradient)."""
+    (B, T, N); returns (loss, flat gradient).  With slices (a list of slice
+    indices) the targets are (B, len(slices), N) and only those slices'
+    logits enter the loss."""
     xs = np.asarray(xs)
     targets = np.asarray(targets, dtype=np.float64)
     B = xs.shape[0]
@@ -144,8 +161,14 @@ def loss_and_grad(p, xs, targets, L):
     for b in range(B):
         z, (a0, h1, h2) = forward(p, xs[b], L, cache=True)
         zs = output_to_sites(z)
-        tot += bce(zs, targets[b]).sum()
-        dzs = (1.0 / (1.0 + np.exp(-zs)) - targets[b]) / count
+        tb = targets[b]
+        if slices is not None:
+            full = np.full(zs.shape, np.nan)
+            full[list(slices)] = tb
+            tb = full
+        live = ~np.isnan(tb)
+        tot += bce(zs[live], tb[live]).sum()
+        dzs = np.where(live, 1.0 / (1.0 + np.exp(-zs)) - np.nan_to_num(tb), 0.0) / count
         T = zs.shape[0]
         Nc = L * L
         dz = np.empty_like(z)
@@ -161,11 +184,26 @@ def loss_and_grad(p, xs, targets, L):
     return tot / count, pack(grads)
 
 
-def loss(p, xs, targets, L):
+def loss(p, xs, targets, L, slices=None):
     xs = np.asarray(xs)
     targets = np.asarray(targets, dtype=np.float64)
-    tot = sum(bce(logits(p, xs[b], L), targets[b]).sum() for b in range(xs.shape[0]))
+    tot = 0.0
+    for b in range(xs.shape[0]):
+        z = logits(p, xs[b], L)
+        if slices is not None:
+            z = z[list(slices)]
+        tot += bce(z, targets[b]).sum()
     return tot / targets.size
+
+
+WINDOW = 7      # slices l-3 .. l+3 around the proposal slice; its logits depend on no other slice
+
+
+def window_loss_and_grad(p, wins, targets, L):
+    """Loss and gradient for 7-slice windows (B, 7, N) with targets of the
+    centre slice (B, N)."""
+    t = np.asarray(targets, dtype=np.float64)[:, None, :]
+    return loss_and_grad(p, wins, t, L, slices=[3])
 
 
 # ---- Plackett-Luce proposal ---------------------------------------------------------
@@ -193,7 +231,8 @@ def gumbel_uniforms(seed, sweep, pas, l, move, N):
     out = np.empty(N)
     for i in range(N):
         w = philox4x32_10((i, l, sweep, c3), key)
-        out[i] = (((w[0] << 21) + (w[1] >> 11)) + 0.5) * (1.0 / 9007199254740992.0)
+        k = (w[0] << 21) + (w[1] >> 11)
+        out[i] = ((k >> 1) + 0.5) * (1.0 / 4503599627370496.0)
     return out
 
 
@@ -249,7 +288,7 @@ class LearnedMoves:
         mdl = chain.m
         L, N = mdl.lat.L, mdl.N
         for j in range(self.per_slice):
-            z = slice_logits(self.p, chain.fields, L, l)
+            z = proposal_logits(self.p, chain.fields, L, l)
             u = gumbel_uniforms(self.seed, chain.sweep_index, pas, l, j, N)
             S = gumbel_top_m(z, u, self.m)
             lq = log_q(z, S)
@@ -262,7 +301,7 @@ class LearnedMoves:
             R = (dets[0] * dets[1]).real
             xp = chain.fields.copy()
             xp[l - 1, S] = -xp[l - 1, S]
-            lq2 = log_q(slice_logits(self.p, xp, L, l), S)
+            lq2 = log_q(proposal_logits(self.p, xp, L, l), S)
             ua = accept_uniform(self.seed, chain.sweep_index, pas, l, j)
             self.proposals += 1
             if ua < R * np.exp(lq2 - lq):

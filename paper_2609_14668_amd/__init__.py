@@ -41,14 +41,16 @@ class Obs(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64), ("flushes", ctypes.c_int64),
                 ("sweeps", ctypes.c_int64), ("drift_max", ctypes.c_double), ("drift_last", ctypes.c_double),
-                ("numeric_err", ctypes.c_int32)]
+                ("numeric_err", ctypes.c_int32), ("learn_proposals", ctypes.c_int64),
+                ("learn_accepted", ctypes.c_int64)]
 
 
-TIMING_CLASSES = ("wrap", "window", "expand", "flush", "stab", "measure")
+TIMING_CLASSES = ("wrap", "window", "expand", "flush", "stab", "measure", "learn")
+NET_NPARAM = 31170
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 6), ("ms", ctypes.c_double * 6),
+    _fields_ = [("launches", ctypes.c_int64 * len(TIMING_CLASSES)), ("ms", ctypes.c_double * len(TIMING_CLASSES)),
                 ("flush_flops", ctypes.c_double), ("wrap_bytes", ctypes.c_double)]
 
 
@@ -73,6 +75,22 @@ _SIGS = {
                    ctypes.POINTER(ctypes.c_int32)],
     "dqmc_set_timing": [_P, ctypes.c_int32],
     "dqmc_get_timing": [_P, ctypes.POINTER(Timing)],
+    "dqmc_set_proposals": [_P, ctypes.c_int32, ctypes.c_int32],
+    "dqmc_net_set_weights": [_P, _P, ctypes.c_int64],
+    "dqmc_net_get_weights": [_P, _P, ctypes.c_int64],
+    "dqmc_net_init": [_P, ctypes.c_uint64],
+    "dqmc_get_targets": [_P, ctypes.c_int32, _P],
+    "dqmc_net_workspace_size": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_size_t)],
+    "dqmc_net_logits": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_net_grad": [_P, _P, ctypes.c_size_t, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                      ctypes.c_int32, _P, _P],
+    "dqmc_collect": [_P, ctypes.c_int32],
+    "dqmc_sample_count": [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "dqmc_get_samples": [_P, ctypes.c_int64, ctypes.c_int32, _P, _P],
+    "dqmc_net_train_workspace_size": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "dqmc_net_train": [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                       _P],
     "dqmc_status_string": [ctypes.c_int32],
     "dqmc_last_error": [_P],
 }
@@ -270,3 +288,108 @@ class Simulation:
         return out
 
     timing = dqmc_get_timing
+
+    # ---- learned multi-site moves and the proposal network
+    def dqmc_set_proposals(self, per_slice, m):
+        self._chk(self.lib.dqmc_set_proposals(self.h, int(per_slice), int(m)), "set_proposals")
+
+    set_proposals = dqmc_set_proposals
+
+    def dqmc_net_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._chk(self.lib.dqmc_net_set_weights(self.h, w.ctypes.data, w.size), "net_set_weights")
+
+    net_set_weights = dqmc_net_set_weights
+
+    def dqmc_net_init(self, seed=1):
+        self._chk(self.lib.dqmc_net_init(self.h, int(seed)), "net_init")
+
+    net_init = dqmc_net_init
+
+    def dqmc_net_get_weights(self):
+        w = np.empty(NET_NPARAM, dtype=np.float32)
+        self._chk(self.lib.dqmc_net_get_weights(self.h, w.ctypes.data, w.size), "net_get_weights")
+        return w
+
+    net_get_weights = dqmc_net_get_weights
+
+    def dqmc_get_targets(self, inst=0):
+        N, M, _ = self.shapes[inst]
+        out = np.empty((M, N), dtype=np.float32)
+        self._chk(self.lib.dqmc_get_targets(self.h, inst, out.ctypes.data), "get_targets")
+        return out
+
+    targets = dqmc_get_targets
+
+    def _net_ws(self, L, M, n_samples, batch):
+        import torch
+        size = ctypes.c_size_t(0)
+        self._chk(self.lib.dqmc_net_workspace_size(L, M, n_samples, batch, ctypes.byref(size)), "net_workspace_size")
+        key = (size.value,)
+        if getattr(self, "_nws_key", None) != key:
+            self._nws = torch.empty(size.value + 256, dtype=torch.uint8, device=self.ws.device)
+            self._nws_key = key
+        ptr = (self._nws.data_ptr() + 255) & ~255
+        return ptr, size.value
+
+    def dqmc_net_logits(self, fields, L):
+        """fields: int8 (n, M, N) -> logits float32 (n, M, N)."""
+        x = np.ascontiguousarray(fields, dtype=np.int8)
+        n, M, N = x.shape
+        ptr, size = self._net_ws(L, M, n, n)
+        out = np.empty((n, M, N), dtype=np.float32)
+        self._chk(self.lib.dqmc_net_logits(self.h, ptr, size, x.ctypes.data, n, L, M, out.ctypes.data), "net_logits")
+        return out
+
+    net_logits = dqmc_net_logits
+
+    def dqmc_net_grad(self, fields, targets, L, window=False):
+        """window=False: configurations (n, M, N) with targets (n, M, N);
+        window=True: 7-slice windows (n, 7, N) with centre targets (n, N)."""
+        x = np.ascontiguousarray(fields, dtype=np.int8)
+        t = np.ascontiguousarray(targets, dtype=np.float32)
+        n, M, N = x.shape
+        ptr, size = self._net_ws(L, M, n, n)
+        loss = ctypes.c_float(0)
+        g = np.empty(NET_NPARAM, dtype=np.float32)
+        self._chk(self.lib.dqmc_net_grad(self.h, ptr, size, x.ctypes.data, t.ctypes.data, n, L, M, int(bool(window)),
+                                         ctypes.byref(loss), g.ctypes.data), "net_grad")
+        return loss.value, g
+
+    net_grad = dqmc_net_grad
+
+    def dqmc_collect(self, every):
+        self._chk(self.lib.dqmc_collect(self.h, int(every)), "collect")
+
+    collect = dqmc_collect
+
+    def dqmc_sample_count(self):
+        f = ctypes.c_int64()
+        c = ctypes.c_int64()
+        self._chk(self.lib.dqmc_sample_count(self.h, ctypes.byref(f), ctypes.byref(c)), "sample_count")
+        return f.value, c.value
+
+    sample_count = dqmc_sample_count
+
+    def dqmc_get_samples(self, first, count):
+        nmax = max(s[0] for s in self.shapes)
+        win = np.empty((count, 7, nmax), dtype=np.int8)
+        tg = np.empty((count, nmax), dtype=np.float32)
+        self._chk(self.lib.dqmc_get_samples(self.h, int(first), int(count), win.ctypes.data, tg.ctypes.data),
+                  "get_samples")
+        return win, tg
+
+    get_samples = dqmc_get_samples
+
+    def dqmc_net_train(self, steps, batch=8, lr=1e-3, seed=1):
+        import torch
+        size = ctypes.c_size_t(0)
+        self._chk(self.lib.dqmc_net_train_workspace_size(self.h, batch, ctypes.byref(size)), "net_train_ws")
+        buf = torch.empty(size.value + 256, dtype=torch.uint8, device=self.ws.device)
+        ptr = (buf.data_ptr() + 255) & ~255
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        self._chk(self.lib.dqmc_net_train(self.h, ptr, size.value, int(steps), int(batch), float(lr), int(seed),
+                                          losses.ctypes.data), "net_train")
+        return losses[:steps]
+
+    net_train = dqmc_net_train

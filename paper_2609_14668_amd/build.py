@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdqmc.so")
-SOURCES = ["engine.hip", "fft_wrap.hip", "gemm.hip", "update.hip", "stab.hip", "measure.hip"]
+SOURCES = ["engine.hip", "fft_wrap.hip", "gemm.hip", "update.hip", "stab.hip", "measure.hip", "pnet.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DQMC_ARCH", "gfx950")
 

@@ -128,6 +128,22 @@ struct InstState {
   int32_t pad0;
   int64_t flush_rank_sum;  // sum of the ranks of all flushes
   int64_t series_base;   // sweep index at the last reset of the estimators
+  int64_t learn_props, learn_acc;  // learned multi-site moves proposed / accepted
+  int64_t collect_n;               // training samples stored by this instance
+};
+
+// One learned multi-site proposal in flight (at most LEARN_MMAX sites).
+// Coefficient tables hold S-typed values (two doubles per complex entry).
+constexpr int LEARN_MMAX = 8;
+struct LearnState {
+  int32_t S[LEARN_MMAX];                       // ordered sites
+  int32_t m;                                   // sites in S
+  int32_t valid;                               // 0: the block ratio was not usable
+  double logq;                                 // log q(S | X)
+  double R;                                    // block weight ratio R_S
+  double c[LEARN_MMAX][2];                     // Delta_k / r_k
+  double xw[LEARN_MMAX][LEARN_MMAX][2];        // x_k at S positions a > k
+  double yw[LEARN_MMAX][LEARN_MMAX][2];        // y_k at S positions b > k
 };
 
 // Running sums of equal-time estimators.
@@ -161,7 +177,13 @@ struct InstDev {
   const cplx* roots;        // L-th roots of unity exp(-2 pi i m / L)
   const int32_t* factors;   // radix list of L (terminated by 0)
   int32_t* perm;            // column permutation of the current QR
-  int32_t* acc_site;        // window: accepted site offsets
+  int32_t* acc_site;        // accepted sites: position in the window (or in S)
+  int32_t* acc_gsite;       // accepted sites: site index
+  float* targets;           // M x N single-flip acceptance after each decision (downward pass)
+  LearnState* learn;        // learned move in flight
+  void* lwin[3];            // bf16 activations of the proposal net: 7, 5, 3 slices around l
+  float* zcur;              // logits of slice l at the current fields (Nc x 16)
+  float* zprop;             // logits of slice l at the proposed fields
   double* wcoef;            // window: c_k, then x/y window vectors
   InstState* st;
   double* obs;              // running sums [OBS_COUNT]

@@ -15,6 +15,7 @@
 #include <complex>
 #include <cstring>
 #include <string>
+#include <random>
 #include <vector>
 
 #include "common.hpp"
@@ -49,7 +50,7 @@ bool is_twisted(const dqmc_instance_desc& d) {
 }
 
 struct Offs {
-  size_t st, obs, series, fields, tab, roots, factors, perm, acc, wcoef;
+  size_t st, obs, series, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn;
   size_t vec[VEC_COUNT];
   size_t mat[MAT_COUNT];
   size_t stackU, stackT, stackD;
@@ -61,7 +62,17 @@ struct Plan {
   int Nmax = 0, Mmax = 0, n_stab = 0;
   size_t insts_off = 0, total = 0;
   std::vector<Offs> offs;
+  // proposal network: FP32 master weights, Adam moments, gradient, BF16
+  // copies; per-instance sampler windows, laid out with a common stride
+  size_t net_master = 0, net_m = 0, net_v = 0, net_grad = 0, net_w = 0, net_Ls = 0;
+  size_t lwin[3] = {0, 0, 0}, zcur = 0, zprop = 0;
+  size_t lwin_stride[3] = {0, 0, 0}, z_stride = 0;
+  // training samples: ring_cap slots of a 7 x Nmax int8 window and Nmax targets
+  size_t ring_win = 0, ring_tg = 0;
+  int ring_cap = 0;
 };
+
+constexpr int NET_RING = 2048;   // training sample slots (rounded up to a multiple of the instances)
 
 dqmc_status validate(const dqmc_instance_desc* d, int n, std::string& err) {
   if (!d || n < 1) { err = "need at least one instance"; return DQMC_EINVAL; }
@@ -107,7 +118,10 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.factors = o; o = al(o + sizeof(int32_t) * 16);
     f.perm = o; o = al(o + sizeof(int32_t) * N);
     f.acc = o; o = al(o + sizeof(int32_t) * WINDOW);
+    f.gsite = o; o = al(o + sizeof(int32_t) * WINDOW);
     f.wcoef = o; o = al(o + ss * (WINDOW + 2 * WINDOW * WINDOW));
+    f.targets = o; o = al(o + sizeof(float) * (size_t)M * N);
+    f.learn = o; o = al(o + sizeof(LearnState));
     for (int v = 0; v < VEC_COUNT; ++v) { f.vec[v] = o; o = al(o + sizeof(double) * 2 * N); }
     const size_t mb = ss * (size_t)N * N;
     for (int m = 0; m < MAT_COUNT; ++m) {
@@ -122,6 +136,24 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.end = o;
     p.offs.push_back(f);
   }
+  const size_t ncm = (size_t)p.Nmax / 2;
+  p.net_master = o; o = al(o + sizeof(float) * NET_NPARAM);
+  p.net_m = o; o = al(o + sizeof(float) * NET_NPARAM);
+  p.net_v = o; o = al(o + sizeof(float) * NET_NPARAM);
+  p.net_grad = o; o = al(o + sizeof(float) * NET_NPARAM);
+  p.net_w = o; o = al(o + NET_WBYTES + 256 * 8);
+  p.net_Ls = o; o = al(o + sizeof(int32_t) * n);
+  const int wt[3] = {7, 5, 3}, wc[3] = {16, 32, 32};
+  for (int q = 0; q < 3; ++q) {
+    p.lwin_stride[q] = (size_t)wt[q] * ncm * wc[q];       // bf16 elements per instance
+    p.lwin[q] = o; o = al(o + 2 * p.lwin_stride[q] * n);
+  }
+  p.z_stride = ncm * 16;                                  // float elements per instance
+  p.zcur = o; o = al(o + sizeof(float) * p.z_stride * n);
+  p.zprop = o; o = al(o + sizeof(float) * p.z_stride * n);
+  p.ring_cap = ((NET_RING + n - 1) / n) * n;
+  p.ring_win = o; o = al(o + (size_t)p.ring_cap * 7 * p.Nmax);
+  p.ring_tg = o; o = al(o + sizeof(float) * (size_t)p.ring_cap * p.Nmax);
   p.total = o;
   return p;
 }
@@ -163,6 +195,13 @@ struct dqmc_ctx {
   std::vector<int> fixedL;   // distinct L with a compile-time FFT plan
   bool any_generic = false;  // some L uses the runtime-plan FFT
   bool mixed = false;        // wraps and flushes in single precision
+  // learned multi-site moves
+  int learn_P = 0, learn_m = 0;   // moves per slice visit, sites per move
+  int collect_every = 0;          // store a training sample every this many downward slices (0: off)
+  NetW netw{};
+  float *net_master = nullptr, *net_m = nullptr, *net_v = nullptr, *net_grad = nullptr;
+  int* net_Ls = nullptr;
+  int adam_step = 0;
   std::string err;
   // live timing
   bool timing = false;
@@ -363,6 +402,45 @@ double wrap_pass_bytes(dqmc_ctx* h, int64_t s, bool up) {
   return b;
 }
 
+// Logits of the current slice of every instance from the 7-slice window in
+// lwin[0]: three valid-in-time convolutions (7 -> 5 -> 3 -> 1 slices).
+void window_logits(Ctx& c, float* z_base) {
+  dqmc_ctx* h = c.h;
+  const Plan& p = h->plan;
+  char* b = h->ws;
+  const int ncm = h->Nmax / 2;
+  ConvGeom g1{0, h->net_Ls, 7, 5, 1, (long long)p.lwin_stride[0], (long long)p.lwin_stride[1]};
+  c.chk(launch_conv(CONV_F1, b + p.lwin[0], b + p.lwin[1], h->netw, g1, h->n, ncm, c.s));
+  ConvGeom g2{0, h->net_Ls, 5, 3, 1, (long long)p.lwin_stride[1], (long long)p.lwin_stride[2]};
+  c.chk(launch_conv(CONV_F2, b + p.lwin[1], b + p.lwin[2], h->netw, g2, h->n, ncm, c.s));
+  ConvGeom g3{0, h->net_Ls, 3, 1, 1, (long long)p.lwin_stride[2], (long long)p.z_stride};
+  c.chk(launch_conv(CONV_F3, b + p.lwin[2], z_base, h->netw, g3, h->n, ncm, c.s));
+}
+
+// learn_P learned m-site moves on the current slice after its single-site
+// updates (the delayed-update buffers are empty here): logits at the current
+// fields, then per move: propose S and its block ratio, logits at the
+// proposed fields, Metropolis-Hastings decision, and on acceptance the m
+// rank-1 terms appended to X, Y; a final flush before the wrap.
+void learned_moves(Ctx& c) {
+  dqmc_ctx* h = c.h;
+  const Plan& p = h->plan;
+  float* zc = (float*)(h->ws + p.zcur);
+  float* zp = (float*)(h->ws + p.zprop);
+  const int ncm = h->Nmax / 2;
+  c.chk(launch_learn_window(h->dinst, h->n, ncm, 0, c.s));
+  window_logits(c, zc);
+  for (int j = 0; j < h->learn_P; ++j) {
+    c.chk(launch_learn_propose(h->dinst, h->n, h->cplx, j, h->learn_m, c.s));
+    c.chk(launch_learn_window(h->dinst, h->n, ncm, 1, c.s));
+    window_logits(c, zp);
+    c.chk(launch_learn_decide(h->dinst, h->n, h->cplx, j, c.s));
+    c.chk(launch_expand(h->dinst, h->n, h->Nmax, h->cplx, h->kcap_max, c.s));
+  }
+  c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
+  c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
+}
+
 void step(Ctx& c, int64_t s, bool measure, int replay) {
   dqmc_ctx* h = c.h;
   {
@@ -395,6 +473,13 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
     c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
   }
   c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
+  if (h->collect_every > 0)
+    c.chk(launch_collect(h->dinst, h->n, (int8_t*)(h->ws + h->plan.ring_win), (float*)(h->ws + h->plan.ring_tg),
+                         h->plan.ring_cap, h->Nmax, h->collect_every, c.s));
+  if (h->learn_P > 0 && !replay) {
+    TimedScope t(h, c.s, DQMC_T_LEARN);
+    learned_moves(c);
+  }
   {
     TimedScope t(h, c.s, DQMC_T_WRAP);
     c.fft(FOP_WRAP_POST, 0, MAT_G);
@@ -533,6 +618,12 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.factors = (const int32_t*)(b + f.factors);
     dv.perm = (int32_t*)(b + f.perm);
     dv.acc_site = (int32_t*)(b + f.acc);
+    dv.acc_gsite = (int32_t*)(b + f.gsite);
+    dv.targets = (float*)(b + f.targets);
+    dv.learn = (LearnState*)(b + f.learn);
+    for (int q = 0; q < 3; ++q) dv.lwin[q] = b + p.lwin[q] + 2 * p.lwin_stride[q] * i;
+    dv.zcur = (float*)(b + p.zcur) + p.z_stride * i;
+    dv.zprop = (float*)(b + p.zprop) + p.z_stride * i;
     dv.wcoef = (double*)(b + f.wcoef);
     dv.st = (InstState*)(b + f.st);
     dv.obs = (double*)(b + f.obs);
@@ -573,6 +664,8 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
         (e = hipMemsetAsync(b + f.st, 0, sizeof(InstState), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.series, 0, sizeof(double) * OBS_COUNT * MAX_SERIES, s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.targets, 0, sizeof(float) * (size_t)dv.M * dv.N, s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.learn, 0, sizeof(LearnState), s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
       std::string m = std::string("create upload: ") + hipGetErrorString(e);
       delete h;
@@ -584,6 +677,36 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     h->lds_budget = std::min<size_t>(65536, (size_t)lds);
+  {
+    // proposal network: zero weights (uniform proposals) until set or trained
+    char* b = h->ws;
+    h->net_master = (float*)(b + p.net_master);
+    h->net_m = (float*)(b + p.net_m);
+    h->net_v = (float*)(b + p.net_v);
+    h->net_grad = (float*)(b + p.net_grad);
+    char* w = b + p.net_w;
+    auto take = [&](size_t bytes) { char* r = w; w += (bytes + 255) / 256 * 256; return r; };
+    h->netw.w1f = take(2 * 27 * 32 * 16);
+    h->netw.w2f = take(2 * 27 * 32 * 32);
+    h->netw.w3f = take(2 * 27 * 16 * 32);
+    h->netw.w2b = take(2 * 27 * 32 * 32);
+    h->netw.w3b = take(2 * 27 * 32 * 16);
+    h->netw.b1 = (float*)take(4 * 32);
+    h->netw.b2 = (float*)take(4 * 32);
+    h->netw.b3 = (float*)take(4 * 16);
+    h->net_Ls = (int*)(b + p.net_Ls);
+    std::vector<int> Ls(n);
+    for (int i = 0; i < n; ++i) Ls[i] = d[i].L;
+    hipError_t e;
+    if ((e = hipMemsetAsync(h->net_master, 0, sizeof(float) * NET_NPARAM, s)) != hipSuccess ||
+        (e = hipMemsetAsync(h->net_m, 0, sizeof(float) * NET_NPARAM, s)) != hipSuccess ||
+        (e = hipMemsetAsync(h->net_v, 0, sizeof(float) * NET_NPARAM, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->net_Ls, Ls.data(), sizeof(int) * n, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_net_prep(h->net_master, h->netw, s)) != hipSuccess) {
+      delete h;
+      return DQMC_EHIP;
+    }
+  }
   dqmc_status st = upload_insts(h, s);
   if (st == DQMC_OK) st = init_green(h, s);
   if (st == DQMC_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(h, DQMC_EHIP, "create: stream sync failed");
@@ -850,6 +973,400 @@ dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out) {
   out->drift_max = st.drift_max;
   out->drift_last = st.drift_last;
   out->numeric_err = st.numeric_err;
+  out->learn_proposals = st.learn_props;
+  out->learn_accepted = st.learn_acc;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_proposals(dqmc_handle h, int32_t per_slice, int32_t m) {
+  if (!h || per_slice < 0 || per_slice > 8) return DQMC_EINVAL;
+  if (per_slice > 0 && (m < 1 || m > LEARN_MMAX)) return DQMC_EINVAL;
+  for (auto& d : h->hd)
+    if (per_slice > 0 && m >= d.N) return fail(h, DQMC_EINVAL, "m must be smaller than the number of sites");
+  h->learn_P = per_slice;
+  h->learn_m = per_slice > 0 ? m : 0;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_net_set_weights(dqmc_handle h, const float* host_w, int64_t n) {
+  if (!h || !host_w || n != NET_NPARAM) return DQMC_EINVAL;
+  hipStream_t s = h->stream;
+  HIPCHK(h, hipMemcpyAsync(h->net_master, host_w, sizeof(float) * NET_NPARAM, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemsetAsync(h->net_m, 0, sizeof(float) * NET_NPARAM, s));
+  HIPCHK(h, hipMemsetAsync(h->net_v, 0, sizeof(float) * NET_NPARAM, s));
+  HIPCHK(h, launch_net_prep(h->net_master, h->netw, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  h->adam_step = 0;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_net_init(dqmc_handle h, uint64_t seed) {
+  if (!h) return DQMC_EINVAL;
+  // W1, W2 ~ N(0, 1/fan_in) so that gradients reach every layer; W3 and the
+  // biases zero, so that the proposals start uniform
+  std::mt19937_64 g(seed);
+  std::normal_distribution<double> nd(0.0, 1.0);
+  std::vector<float> w(NET_NPARAM, 0.f);
+  for (int i = NET_OFF_W1; i < NET_OFF_B1; ++i) w[i] = (float)(nd(g) / std::sqrt(27.0 * 2.0));
+  for (int i = NET_OFF_W2; i < NET_OFF_B2; ++i) w[i] = (float)(nd(g) / std::sqrt(27.0 * NET_CH));
+  return dqmc_net_set_weights(h, w.data(), NET_NPARAM);
+}
+
+dqmc_status dqmc_net_get_weights(dqmc_handle h, float* host_w, int64_t n) {
+  if (!h || !host_w || n != NET_NPARAM) return DQMC_EINVAL;
+  HIPCHK(h, hipMemcpyAsync(host_w, h->net_master, sizeof(float) * NET_NPARAM, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_targets(dqmc_handle h, int32_t inst, float* host_out) {
+  if (!h || inst < 0 || inst >= h->n || !host_out) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  HIPCHK(h, hipMemcpyAsync(host_out, d.targets, sizeof(float) * (size_t)d.M * d.N, hipMemcpyDeviceToHost,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int NET_VCH = 1024;   // output voxels per weight-gradient workgroup
+
+// Layout of the training scratch for configurations of one size.
+struct NetPlan {
+  int L = 0, M = 0, N = 0, Nc = 0, batch = 0, chunks = 0, lblocks = 0;
+  int64_t n_samples = 0;
+  size_t fields = 0, targets = 0, a0 = 0, h1 = 0, h2 = 0, z = 0, dz = 0, d2 = 0, d1 = 0, part = 0, partb = 0,
+         lossp = 0, lossv = 0, total = 0;
+};
+constexpr int NET_LOSS_SLOTS = 1024;
+
+bool net_plan(int L, int M, int64_t n_samples, int batch, NetPlan& p) {
+  if (L < 2 || L > 45 || M < 1 || n_samples < 1 || batch < 1 || batch > NET_MAXBATCH) return false;
+  p.L = L; p.M = M; p.Nc = L * L; p.N = 2 * p.Nc; p.batch = batch; p.n_samples = n_samples;
+  const size_t vox = (size_t)M * p.Nc, B = batch;
+  p.chunks = wgrad_chunks(M, p.Nc, NET_VCH);
+  p.lblocks = (int)((vox + 255) / 256);
+  size_t o = 0;
+  p.fields = o; o = al(o + (size_t)n_samples * M * p.N);
+  p.targets = o; o = al(o + sizeof(float) * (size_t)n_samples * M * p.N);
+  p.a0 = o; o = al(o + 2 * B * vox * 16);
+  p.h1 = o; o = al(o + 2 * B * vox * 32);
+  p.h2 = o; o = al(o + 2 * B * vox * 32);
+  p.z = o; o = al(o + 4 * B * vox * 16);
+  p.dz = o; o = al(o + 2 * B * vox * 16);
+  p.d2 = o; o = al(o + 2 * B * vox * 32);
+  p.d1 = o; o = al(o + 2 * B * vox * 32);
+  p.part = o; o = al(o + sizeof(float) * B * p.chunks * 27 * 32 * 32);
+  p.partb = o; o = al(o + sizeof(float) * B * p.chunks * 32);
+  p.lossp = o; o = al(o + sizeof(float) * B * p.lblocks);
+  p.lossv = o; o = al(o + sizeof(float) * NET_LOSS_SLOTS);
+  p.total = o;
+  return true;
+}
+
+// Forward pass of the batch idx; with targets, the loss into loss_slot and
+// (backward) the gradient into h->net_grad.
+hipError_t net_pass(dqmc_ctx* h, const NetPlan& p, char* ws, const BatchIdx& idx, bool loss, bool backward,
+                    int loss_slot, hipStream_t s) {
+  const int M = p.M, Nc = p.Nc, N = p.N, L = p.L;
+  const long long v = (long long)M * Nc;
+  hipError_t e;
+  auto ok = [&](hipError_t x) { e = x; return x == hipSuccess; };
+  ConvGeom g{L, nullptr, M, M, 0, v * 16, v * 32};
+  if (!ok(launch_net_input((const int8_t*)(ws + p.fields), N, Nc, M, idx, ws + p.a0, s))) return e;
+  if (!ok(launch_conv(CONV_F1, ws + p.a0, ws + p.h1, h->netw, g, idx.n, Nc, s))) return e;
+  g.in_stride = v * 32; g.out_stride = v * 32;
+  if (!ok(launch_conv(CONV_F2, ws + p.h1, ws + p.h2, h->netw, g, idx.n, Nc, s))) return e;
+  g.in_stride = v * 32; g.out_stride = v * 16;
+  if (!ok(launch_conv(CONV_F3, ws + p.h2, ws + p.z, h->netw, g, idx.n, Nc, s))) return e;
+  if (!loss) return hipSuccess;
+  float* lossv = (float*)(ws + p.lossv) + loss_slot;
+  if (!ok(launch_net_loss((const float*)(ws + p.z), (const float*)(ws + p.targets), idx, N, Nc, M, ws + p.dz,
+                          (float*)(ws + p.lossp), lossv, s)))
+    return e;
+  if (!backward) return hipSuccess;
+  float* part = (float*)(ws + p.part);
+  float* partb = (float*)(ws + p.partb);
+  const int nch = p.chunks * idx.n;
+  // layer 3: dW3 from (h2, dz); dh2 = conv^T(dz)
+  ConvGeom gw{L, nullptr, M, M, 0, v * 32, v * 16};
+  if (!ok(launch_wgrad(WGRAD_3, ws + p.h2, ws + p.dz, part, partb, gw, idx.n, Nc, NET_VCH, s))) return e;
+  if (!ok(launch_wgrad_reduce(WGRAD_3, part, partb, nch, h->net_grad, s))) return e;
+  ConvGeom gb{L, nullptr, M, M, 0, v * 16, v * 32};
+  if (!ok(launch_conv(CONV_B3, ws + p.dz, ws + p.d2, h->netw, gb, idx.n, Nc, s))) return e;
+  if (!ok(launch_tanh_back(ws + p.d2, ws + p.h2, (size_t)idx.n * v * 32, s))) return e;
+  // layer 2
+  gw.in_stride = v * 32; gw.out_stride = v * 32;
+  if (!ok(launch_wgrad(WGRAD_2, ws + p.h1, ws + p.d2, part, partb, gw, idx.n, Nc, NET_VCH, s))) return e;
+  if (!ok(launch_wgrad_reduce(WGRAD_2, part, partb, nch, h->net_grad, s))) return e;
+  gb.in_stride = v * 32; gb.out_stride = v * 32;
+  if (!ok(launch_conv(CONV_B2, ws + p.d2, ws + p.d1, h->netw, gb, idx.n, Nc, s))) return e;
+  if (!ok(launch_tanh_back(ws + p.d1, ws + p.h1, (size_t)idx.n * v * 32, s))) return e;
+  // layer 1
+  gw.in_stride = v * 16; gw.out_stride = v * 32;
+  if (!ok(launch_wgrad(WGRAD_1, ws + p.a0, ws + p.d1, part, partb, gw, idx.n, Nc, NET_VCH, s))) return e;
+  return launch_wgrad_reduce(WGRAD_1, part, partb, nch, h->net_grad, s);
+}
+
+dqmc_status net_upload(dqmc_ctx* h, const NetPlan& p, char* ws, const int8_t* fields, const float* targets,
+                       hipStream_t s) {
+  const size_t n = (size_t)p.n_samples * p.M * p.N;
+  for (size_t i = 0; i < n; ++i)
+    if (fields[i] != 1 && fields[i] != -1) return fail(h, DQMC_EINVAL, "fields must be +-1");
+  HIPCHK(h, hipMemcpyAsync(ws + p.fields, fields, n, hipMemcpyHostToDevice, s));
+  if (targets) HIPCHK(h, hipMemcpyAsync(ws + p.targets, targets, sizeof(float) * n, hipMemcpyHostToDevice, s));
+  return DQMC_OK;
+}
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Scratch of the window (7-slice) training pass: batch items with up to
+// ncm cells; host windows (n_host of them, rows of row sites) when given.
+struct WinPlan {
+  int ncm = 0, batch = 0, chunks = 0, lblocks = 0;
+  size_t Ls = 0, wins = 0, tgs = 0, a0 = 0, h1 = 0, h2 = 0, z = 0, dz = 0, d2 = 0, d1 = 0, part = 0, partb = 0,
+         lossp = 0, lossv = 0, total = 0;
+};
+
+WinPlan win_plan(int ncm, int batch, int n_host, int row) {
+  WinPlan p;
+  p.ncm = ncm; p.batch = batch;
+  const size_t B = batch, c = ncm;
+  p.chunks = wgrad_chunks(5, ncm, NET_VCH);
+  p.lblocks = (ncm + 255) / 256;
+  size_t o = 0;
+  p.Ls = o; o = al(o + sizeof(int) * NET_MAXBATCH);
+  p.wins = o; o = al(o + (size_t)n_host * 7 * row);
+  p.tgs = o; o = al(o + sizeof(float) * (size_t)n_host * row);
+  p.a0 = o; o = al(o + 2 * B * 7 * c * 16);
+  p.h1 = o; o = al(o + 2 * B * 5 * c * 32);
+  p.h2 = o; o = al(o + 2 * B * 3 * c * 32);
+  p.z = o; o = al(o + 4 * B * c * 16);
+  p.dz = o; o = al(o + 2 * B * c * 16);
+  p.d2 = o; o = al(o + 2 * B * 3 * c * 32);
+  p.d1 = o; o = al(o + 2 * B * 5 * c * 32);
+  p.part = o; o = al(o + sizeof(float) * B * p.chunks * 27 * 32 * 32);
+  p.partb = o; o = al(o + sizeof(float) * B * p.chunks * 32);
+  p.lossp = o; o = al(o + sizeof(float) * B * p.lblocks);
+  p.lossv = o; o = al(o + sizeof(float) * NET_LOSS_SLOTS);
+  p.total = o;
+  return p;
+}
+
+// Loss of the centre-slice logits of the windows in idx (and with backward
+// the gradient into h->net_grad): valid-in-time convolutions 7 -> 5 -> 3 -> 1
+// slices forward, transposed convolutions with zero time padding backward.
+hipError_t net_window_pass(dqmc_ctx* h, const WinPlan& p, char* ws, const int8_t* wins, long long win_stride,
+                           int row, const float* tgs, long long tg_stride, const BatchIdx& idx, bool backward,
+                           int loss_slot, hipStream_t s) {
+  const int c = p.ncm;
+  const long long c16 = (long long)c * 16, c32 = (long long)c * 32;
+  hipError_t e;
+  auto ok = [&](hipError_t x) { e = x; return x == hipSuccess; };
+  int* dLs = (int*)(ws + p.Ls);
+  long long nsite = 0;
+  for (int b = 0; b < idx.n; ++b) nsite += 2LL * idx.L[b] * idx.L[b];
+  if (!ok(launch_batch_L(idx, dLs, s))) return e;
+  if (!ok(launch_net_input_window(wins, win_stride, row, idx, dLs, c, ws + p.a0, s))) return e;
+  ConvGeom g1{0, dLs, 7, 5, 1, 7 * c16, 5 * c32, 0};
+  if (!ok(launch_conv(CONV_F1, ws + p.a0, ws + p.h1, h->netw, g1, idx.n, c, s))) return e;
+  ConvGeom g2{0, dLs, 5, 3, 1, 5 * c32, 3 * c32, 0};
+  if (!ok(launch_conv(CONV_F2, ws + p.h1, ws + p.h2, h->netw, g2, idx.n, c, s))) return e;
+  ConvGeom g3{0, dLs, 3, 1, 1, 3 * c32, c16, 0};
+  if (!ok(launch_conv(CONV_F3, ws + p.h2, ws + p.z, h->netw, g3, idx.n, c, s))) return e;
+  float* lossv = (float*)(ws + p.lossv) + loss_slot;
+  if (!ok(launch_net_loss_window((const float*)(ws + p.z), tgs, tg_stride, idx, dLs, c, (float)(1.0 / nsite),
+                                 ws + p.dz, (float*)(ws + p.lossp), lossv, s)))
+    return e;
+  if (!backward) return hipSuccess;
+  float* part = (float*)(ws + p.part);
+  float* partb = (float*)(ws + p.partb);
+  // layer 3: dW3 from (h2, dz); dh2 = conv^T(dz) over 3 slices
+  ConvGeom w3{0, dLs, 3, 1, 1, 3 * c32, c16, 0};
+  if (!ok(launch_wgrad(WGRAD_3, ws + p.h2, ws + p.dz, part, partb, w3, idx.n, c, NET_VCH, s))) return e;
+  if (!ok(launch_wgrad_reduce(WGRAD_3, part, partb, idx.n * wgrad_chunks(1, c, NET_VCH), h->net_grad, s)))
+    return e;
+  ConvGeom b3{0, dLs, 1, 3, -1, c16, 3 * c32, 1};
+  if (!ok(launch_conv(CONV_B3, ws + p.dz, ws + p.d2, h->netw, b3, idx.n, c, s))) return e;
+  if (!ok(launch_tanh_back(ws + p.d2, ws + p.h2, (size_t)idx.n * 3 * c32, s))) return e;
+  // layer 2
+  ConvGeom w2{0, dLs, 5, 3, 1, 5 * c32, 3 * c32, 0};
+  if (!ok(launch_wgrad(WGRAD_2, ws + p.h1, ws + p.d2, part, partb, w2, idx.n, c, NET_VCH, s))) return e;
+  if (!ok(launch_wgrad_reduce(WGRAD_2, part, partb, idx.n * wgrad_chunks(3, c, NET_VCH), h->net_grad, s)))
+    return e;
+  ConvGeom b2{0, dLs, 3, 5, -1, 3 * c32, 5 * c32, 1};
+  if (!ok(launch_conv(CONV_B2, ws + p.d2, ws + p.d1, h->netw, b2, idx.n, c, s))) return e;
+  if (!ok(launch_tanh_back(ws + p.d1, ws + p.h1, (size_t)idx.n * 5 * c32, s))) return e;
+  // layer 1
+  ConvGeom w1{0, dLs, 7, 5, 1, 7 * c16, 5 * c32, 0};
+  if (!ok(launch_wgrad(WGRAD_1, ws + p.a0, ws + p.d1, part, partb, w1, idx.n, c, NET_VCH, s))) return e;
+  return launch_wgrad_reduce(WGRAD_1, part, partb, idx.n * wgrad_chunks(5, c, NET_VCH), h->net_grad, s);
+}
+
+// Ring slots holding a sample: instance i writes slots i, i + n, ...
+int64_t ring_filled(dqmc_ctx* h, dqmc_status& st) {
+  int64_t cmin = -1;
+  for (int i = 0; i < h->n; ++i) {
+    InstState x;
+    if (hipMemcpyAsync(&x, h->hd[i].st, sizeof(x), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      st = DQMC_EHIP;
+      return 0;
+    }
+    cmin = cmin < 0 ? x.collect_n : std::min(cmin, x.collect_n);
+  }
+  st = DQMC_OK;
+  return std::min<int64_t>((int64_t)h->plan.ring_cap, std::max<int64_t>(cmin, 0) * h->n);
+}
+
+}  // namespace
+
+extern "C" {
+
+dqmc_status dqmc_net_workspace_size(int32_t L, int32_t M, int64_t n_samples, int32_t batch, size_t* bytes) {
+  NetPlan p;
+  if (!bytes || !net_plan(L, M, n_samples, batch, p)) return DQMC_EINVAL;
+  size_t t = p.total;
+  if (M == 7) t = std::max(t, win_plan(L * L, (int)std::max<int64_t>(n_samples, batch), (int)n_samples, 2 * L * L).total);
+  *bytes = t;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_net_logits(dqmc_handle h, void* dev_ws, size_t bytes, const int8_t* host_fields, int32_t n,
+                            int32_t L, int32_t M, float* host_out) {
+  NetPlan p;
+  if (!h || !dev_ws || !host_fields || !host_out || !net_plan(L, M, n, n, p)) return DQMC_EINVAL;
+  if (((uintptr_t)dev_ws) & 255) return DQMC_EINVAL;
+  if (bytes < p.total) return DQMC_ENOMEM;
+  hipStream_t s = h->stream;
+  char* ws = (char*)dev_ws;
+  dqmc_status st = net_upload(h, p, ws, host_fields, nullptr, s);
+  if (st != DQMC_OK) return st;
+  BatchIdx idx{};
+  idx.n = n;
+  for (int b = 0; b < n; ++b) idx.idx[b] = b;
+  HIPCHK(h, net_pass(h, p, ws, idx, false, false, 0, s));
+  float* out = (float*)(ws + p.targets);   // reuse the target area for the logits
+  HIPCHK(h, launch_net_logits_out((const float*)(ws + p.z), idx, p.N, p.Nc, M, out, s));
+  HIPCHK(h, hipMemcpyAsync(host_out, out, sizeof(float) * (size_t)n * M * p.N, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_net_grad(dqmc_handle h, void* dev_ws, size_t bytes, const int8_t* host_fields,
+                          const float* host_targets, int32_t n, int32_t L, int32_t M, int32_t window,
+                          float* host_loss, float* host_grad) {
+  NetPlan p;
+  if (!h || !dev_ws || !host_fields || !host_targets || !net_plan(L, M, n, n, p)) return DQMC_EINVAL;
+  if (window && M != 7) return fail(h, DQMC_EINVAL, "window samples have 7 slices");
+  if (((uintptr_t)dev_ws) & 255) return DQMC_EINVAL;
+  hipStream_t s = h->stream;
+  char* ws = (char*)dev_ws;
+  BatchIdx idx{};
+  idx.n = n;
+  for (int b = 0; b < n; ++b) idx.idx[b] = b;
+  float* lossv = nullptr;
+  if (!window) {
+    if (bytes < p.total) return DQMC_ENOMEM;
+    dqmc_status st = net_upload(h, p, ws, host_fields, host_targets, s);
+    if (st != DQMC_OK) return st;
+    HIPCHK(h, net_pass(h, p, ws, idx, true, true, 0, s));
+    lossv = (float*)(ws + p.lossv);
+  } else {
+    const int N = 2 * L * L;
+    WinPlan w = win_plan(L * L, n, n, N);
+    if (bytes < w.total) return DQMC_ENOMEM;
+    for (size_t i = 0; i < (size_t)n * 7 * N; ++i)
+      if (host_fields[i] != 1 && host_fields[i] != -1) return fail(h, DQMC_EINVAL, "fields must be +-1");
+    HIPCHK(h, hipMemcpyAsync(ws + w.wins, host_fields, (size_t)n * 7 * N, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(ws + w.tgs, host_targets, sizeof(float) * (size_t)n * N, hipMemcpyHostToDevice, s));
+    for (int b = 0; b < n; ++b) idx.L[b] = L;
+    HIPCHK(h, net_window_pass(h, w, ws, (const int8_t*)(ws + w.wins), 7LL * N, N, (const float*)(ws + w.tgs), N,
+                              idx, true, 0, s));
+    lossv = (float*)(ws + w.lossv);
+  }
+  if (host_loss) HIPCHK(h, hipMemcpyAsync(host_loss, lossv, sizeof(float), hipMemcpyDeviceToHost, s));
+  if (host_grad)
+    HIPCHK(h, hipMemcpyAsync(host_grad, h->net_grad, sizeof(float) * NET_NPARAM, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_collect(dqmc_handle h, int32_t every) {
+  if (!h || every < 0) return DQMC_EINVAL;
+  h->collect_every = every;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_sample_count(dqmc_handle h, int64_t* filled, int64_t* capacity) {
+  if (!h) return DQMC_EINVAL;
+  dqmc_status st;
+  int64_t f = ring_filled(h, st);
+  if (st != DQMC_OK) return fail(h, st, "sample_count");
+  if (filled) *filled = f;
+  if (capacity) *capacity = h->plan.ring_cap;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_samples(dqmc_handle h, int64_t first, int32_t count, int8_t* host_win, float* host_tg) {
+  if (!h || first < 0 || count < 0 || first + count > h->plan.ring_cap || !host_win || !host_tg)
+    return DQMC_EINVAL;
+  const size_t nm = (size_t)h->Nmax;
+  HIPCHK(h, hipMemcpyAsync(host_win, h->ws + h->plan.ring_win + (size_t)first * 7 * nm, (size_t)count * 7 * nm,
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(host_tg, h->ws + h->plan.ring_tg + sizeof(float) * (size_t)first * nm,
+                           sizeof(float) * (size_t)count * nm, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_net_train_workspace_size(dqmc_handle h, int32_t batch, size_t* bytes) {
+  if (!h || !bytes || batch < 1 || batch > NET_MAXBATCH) return DQMC_EINVAL;
+  *bytes = win_plan(h->Nmax / 2, batch, 0, 0).total;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_net_train(dqmc_handle h, void* dev_ws, size_t bytes, int32_t steps, int32_t batch, float lr,
+                           uint64_t seed, float* host_loss) {
+  if (!h || !dev_ws || steps < 0 || !(lr > 0.f) || batch < 1 || batch > NET_MAXBATCH) return DQMC_EINVAL;
+  if (((uintptr_t)dev_ws) & 255) return DQMC_EINVAL;
+  WinPlan w = win_plan(h->Nmax / 2, batch, 0, 0);
+  if (bytes < w.total) return DQMC_ENOMEM;
+  dqmc_status st;
+  const int64_t filled = ring_filled(h, st);
+  if (st != DQMC_OK) return fail(h, st, "net_train");
+  if (filled < 1) return fail(h, DQMC_ESTATE, "no training samples collected");
+  hipStream_t s = h->stream;
+  char* ws = (char*)dev_ws;
+  const int8_t* wins = (const int8_t*)(h->ws + h->plan.ring_win);
+  const float* tgs = (const float*)(h->ws + h->plan.ring_tg);
+  uint64_t rs = seed;
+  for (int k = 0; k < steps; ++k) {
+    BatchIdx idx{};
+    idx.n = batch;
+    for (int b = 0; b < batch; ++b) {
+      idx.idx[b] = (int)(splitmix64(rs) % (uint64_t)filled);
+      idx.L[b] = h->hd[idx.idx[b] % h->n].L;
+    }
+    const int slot = k % NET_LOSS_SLOTS;
+    HIPCHK(h, net_window_pass(h, w, ws, wins, 7LL * h->Nmax, h->Nmax, tgs, h->Nmax, idx, true, slot, s));
+    HIPCHK(h, launch_adam(h->net_master, h->net_grad, h->net_m, h->net_v, NET_NPARAM, lr, ++h->adam_step, s));
+    HIPCHK(h, launch_net_prep(h->net_master, h->netw, s));
+    if (host_loss && (slot == NET_LOSS_SLOTS - 1 || k == steps - 1)) {
+      const int first = k - slot;
+      HIPCHK(h, hipMemcpyAsync(host_loss + first, ws + w.lossv, sizeof(float) * (slot + 1), hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+    }
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
   return DQMC_OK;
 }
 

@@ -93,3 +93,88 @@ hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cp
 hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
 hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int blk, hipStream_t s);
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
+
+// ---- proposal network (BF16 operands, FP32 accumulation) ---------------------------
+// Flat FP32 parameters: W1 [27][32][2], b1 [32], W2 [27][32][32], b2 [32],
+// W3 [27][2][32], b3 [2]; tap (dt+1)*9 + (d2+1)*3 + (d1+1) reads (t+dt, n2+d2, n1+d1).
+constexpr int NET_CH = 32;
+constexpr int NET_OFF_W1 = 0;
+constexpr int NET_OFF_B1 = NET_OFF_W1 + 27 * NET_CH * 2;
+constexpr int NET_OFF_W2 = NET_OFF_B1 + NET_CH;
+constexpr int NET_OFF_B2 = NET_OFF_W2 + 27 * NET_CH * NET_CH;
+constexpr int NET_OFF_W3 = NET_OFF_B2 + NET_CH;
+constexpr int NET_OFF_B3 = NET_OFF_W3 + 27 * 2 * NET_CH;
+constexpr int NET_NPARAM = NET_OFF_B3 + 2;
+// Device copies of the weights in the layouts the convolutions read:
+// forward [27][out][in] with the 2-channel ends padded to 16, backward-data
+// [27][in of the layer][out of the layer] with the taps mirrored.
+struct NetW {
+  void* w1f;   // bf16 [27][32][16]
+  void* w2f;   // bf16 [27][32][32]
+  void* w3f;   // bf16 [27][16][32]
+  void* w2b;   // bf16 [27][32][32]
+  void* w3b;   // bf16 [27][32][16]
+  float* b1;   // [32]
+  float* b2;   // [32]
+  float* b3;   // [16]
+};
+constexpr size_t NET_WBYTES = 2 * (27 * 32 * 16 + 27 * 32 * 32 + 27 * 16 * 32 + 27 * 32 * 32 + 27 * 32 * 16) +
+                              4 * (32 + 32 + 16);
+// Grid geometry of a convolution over items (configurations or windows):
+// output slice t reads input slices t + toff - 1 .. t + toff + 1 (mod T_in).
+struct ConvGeom {
+  int Lu;             // cells per side when Ls is null
+  const int* Ls;      // per-item L (device), nullable
+  int T_in, T_out, toff;
+  long long in_stride, out_stride;   // elements between items
+  int tzero;          // 1: input slices outside [0, T_in) read as zero instead of wrapping
+};
+enum ConvKind : int { CONV_F1 = 0, CONV_F2, CONV_F3, CONV_B3, CONV_B2 };
+enum WgradKind : int { WGRAD_1 = 0, WGRAD_2, WGRAD_3 };
+constexpr int NET_MAXBATCH = 64;
+struct BatchIdx { int n; int idx[NET_MAXBATCH]; int L[NET_MAXBATCH]; };
+// device copy of idx.L (stream-ordered, from the kernel arguments)
+hipError_t launch_batch_L(const BatchIdx& idx, int* dLs, hipStream_t s);
+
+hipError_t launch_net_prep(const float* master, NetW w, hipStream_t s);
+hipError_t launch_conv(int kind, const void* in, void* out, NetW w, ConvGeom g, int n_items, int max_nc,
+                       hipStream_t s);
+// Partial weight/bias gradients per chunk of vch output voxels; returns the
+// number of chunks per item.
+int wgrad_chunks(int T_out, int Nc, int vch);
+hipError_t launch_wgrad(int kind, const void* in, const void* dout, float* part, float* partb, ConvGeom g,
+                        int n_items, int max_nc, int vch, hipStream_t s);
+hipError_t launch_wgrad_reduce(int kind, const float* part, const float* partb, int nchunks, float* grad,
+                               hipStream_t s);
+hipError_t launch_net_input(const int8_t* fields, int N, int Nc, int M, BatchIdx idx, void* a0, hipStream_t s);
+hipError_t launch_net_loss(const float* z, const float* targets, BatchIdx idx, int N, int Nc, int M, void* dz,
+                           float* lossp, float* loss_out, hipStream_t s);
+hipError_t launch_net_logits_out(const float* z, BatchIdx idx, int N, int Nc, int M, float* out, hipStream_t s);
+hipError_t launch_tanh_back(void* dh, const void* h, size_t n, hipStream_t s);
+// 7-slice windows (int8, rows of row_stride sites, win_stride bytes per
+// sample) -> channels-last input; per-item L on the device.
+hipError_t launch_net_input_window(const int8_t* wins, long long win_stride, int row_stride, BatchIdx idx,
+                                   const int* Ls, int nc_max, void* a0, hipStream_t s);
+// loss of the centre-slice logits (z: [item][nc_max][16]) against targets
+// (tg_stride floats per sample, site order A then B); inv_count = 1 / sum N.
+hipError_t launch_net_loss_window(const float* z, const float* tgs, long long tg_stride, BatchIdx idx,
+                                  const int* Ls, int nc_max, float inv_count, void* dz, float* lossp,
+                                  float* loss_out, hipStream_t s);
+// Training samples: every `every`-th slice l of the downward pass (l % every
+// == 0), after the slice's single-site updates, each instance stores its
+// window of slices l-3 .. l+3 and the targets of slice l in ring slot
+// (count * n_inst + inst) % ring_cap.
+hipError_t launch_collect(const InstDev* insts, int n_inst, int8_t* ring_win, float* ring_tg, int ring_cap,
+                          int n_max, int every, hipStream_t s);
+hipError_t launch_adam(float* master, const float* g, float* m, float* v, int n, float lr, int step,
+                       hipStream_t s);
+// Sampler side: 7-slice input windows around the current slice (flip: with
+// the sites of the move in flight reversed), proposal and decision.
+hipError_t launch_learn_window(const InstDev* insts, int n_inst, int nc_max, int flip, hipStream_t s);
+hipError_t launch_learn_propose(const InstDev* insts, int n_inst, bool cplx_, int move, int m, hipStream_t s);
+hipError_t launch_learn_decide(const InstDev* insts, int n_inst, bool cplx_, int move, hipStream_t s);
+// Window coefficient table (in units of the matrix element type): c_k at
+// [0, WMAX), x_k at [WC_X + k WMAX + a], y_k at [WC_Y + k WMAX + b].
+constexpr int DQMC_WMAX = 64;
+constexpr int DQMC_WC_X = DQMC_WMAX;
+constexpr int DQMC_WC_Y = DQMC_WMAX + DQMC_WMAX * DQMC_WMAX;

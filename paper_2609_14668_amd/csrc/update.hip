@@ -32,6 +32,7 @@ constexpr int WIN_THREADS = 256;
 // window coefficient layout (in units of S): [0, WMAX) c_k; then xw[k][a]; then yw[k][b]
 constexpr int WC_X = WMAX;
 constexpr int WC_Y = WMAX + WMAX * WMAX;
+static_assert(WMAX == DQMC_WMAX && WC_X == DQMC_WC_X && WC_Y == DQMC_WC_Y, "window table layout");
 
 template <typename S>
 __global__ void __launch_bounds__(WIN_THREADS)
@@ -118,6 +119,12 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
       unsigned long long mask = __ballot(cand && acc_q);
       int qstar = mask ? (__ffsll((long long)mask) - 1) : wn;
       if (cand && q <= qstar && d.replay_ratio) d.replay_ratio[rpos + q] = R;
+      // training target of the proposal network: Barker acceptance Rt/(1+Rt)
+      // of flipping the site again right after this decision (downward
+      // pass), Rt = 1/R after an accepted flip and R after a rejected one
+      if (cand && q <= qstar && pass == 1 && d.targets)
+        d.targets[(size_t)(l - 1) * N + w0 + q] =
+            (float)(q == qstar ? 1.0 / (1.0 + R) : (R < 1e300 ? R / (1.0 + R) : 1.0));
       if (q == qstar && cand) {
         sh_c = cdiv(dl, r);
       }
@@ -140,6 +147,7 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
     if (tid == 0) {
       wc[k] = cfac;
       d.acc_site[k] = qs;
+      d.acc_gsite[k] = w0 + qs;
     }
     __syncthreads();
     // trailing-block rank-1 update C -= x y^T
@@ -166,8 +174,8 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
   }
 }
 
-// Full-length x_k, y_k for the accepted sites of the last window, by the
-// recursion of eq. DelayRgenk:
+// Full-length x_k, y_k for the accepted sites of the last window (or of an
+// accepted learned block move), by the recursion of eq. DelayRgenk:
 //   x_k[j] = c_k (G0[j, i_k] - sum_{m<k} x_m[j] y_m[i_k]),
 //   y_k[j] = delta_{i_k j} - G0[i_k, j] + sum_{m<k} x_m[i_k] y_m[j],
 // one thread per j (row of X and column of Y), accepted sites taken KC at a
@@ -189,7 +197,7 @@ k_expand(const InstDev* __restrict__ insts) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j = j0 + lane;
   const bool ok = j < N;
-  const int fill0 = st->fill, w0 = st->wstart;
+  const int fill0 = st->fill;
   const S* G = matp<S>(d, MAT_G);
   S* X = matp<S>(d, MAT_X);
   S* Y = matp<S>(d, MAT_Y);
@@ -200,8 +208,11 @@ k_expand(const InstDev* __restrict__ insts) {
   S* ycf = reinterpret_cast<S*>(xsmem);
   S* xcf = ycf + (size_t)d.kcap * KC;
   __shared__ S pax[KC][64], pay[KC][64];
-  __shared__ int sites[WMAX];
-  if (tid < WMAX) sites[tid] = tid < mw ? d.acc_site[tid] : 0;
+  __shared__ int sites[WMAX], gsites[WMAX];   // table position, site index
+  if (tid < WMAX) {
+    sites[tid] = tid < mw ? d.acc_site[tid] : 0;
+    gsites[tid] = tid < mw ? d.acc_gsite[tid] : 0;
+  }
   __syncthreads();
 
   for (int k0 = 0; k0 < mw; k0 += KC) {
@@ -211,7 +222,7 @@ k_expand(const InstDev* __restrict__ insts) {
       int m = x / KC, kk = x % KC;
       S yv = ST<S>::zero(), xv = ST<S>::zero();
       if (kk < kn) {
-        int ik = sites[k0 + kk], gi = w0 + ik;
+        int ik = sites[k0 + kk], gi = gsites[k0 + kk];
         if (m < fill0) {
           yv = Y[(size_t)m * N + gi];
           xv = X[gi + (size_t)m * N];
@@ -233,7 +244,7 @@ k_expand(const InstDev* __restrict__ insts) {
       for (int q = 0; q < KW; ++q) {
         int kk = wave * KW + q;
         if (kk < kn) {
-          int gi = w0 + sites[k0 + kk];
+          int gi = gsites[k0 + kk];
           ax[q] = G[j + (size_t)gi * N];
           ay[q] = -G[gi + (size_t)j * N];
           if (j == gi) ay[q] = ay[q] + ST<S>::one();
@@ -358,6 +369,8 @@ __global__ void k_reset_counters(const InstDev* __restrict__ insts, int n) {
   st->drift_last = 0.0;
   st->flush_rank_sum = 0;
   st->series_base = st->sweep;
+  st->learn_props = 0;
+  st->learn_acc = 0;
 }
 
 }  // namespace

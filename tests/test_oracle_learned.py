@@ -162,11 +162,69 @@ def test_learned_move_satisfies_detailed_balance():
             R *= det
         return R.real
 
-    lq = pnet.log_q(pnet.slice_logits(p, x, L, l), S)
-    lqp = pnet.log_q(pnet.slice_logits(p, xp, L, l), S)
+    lq = pnet.log_q(pnet.proposal_logits(p, x, L, l), S)
+    lqp = pnet.log_q(pnet.proposal_logits(p, xp, L, l), S)
     a_fwd = min(1.0, ratio(x) * np.exp(lqp - lq))
     a_bwd = min(1.0, ratio(xp) * np.exp(lq - lqp))
     lhs = weight(x) * np.exp(lq) * a_fwd
     rhs = weight(xp) * np.exp(lqp) * a_bwd
     assert lhs == pytest.approx(rhs, rel=1e-10)
     assert abs(lq - lqp) > 1e-3   # the proposal really is asymmetric here
+
+
+def test_window_loss_gradient_matches_central_differences():
+    L, B = 2, 2
+    p = _params(6, gain=1.5)
+    wins = np.stack([workloads.random_fields(40 + b, 7, 2 * L * L) for b in range(B)])
+    tg = workloads.net_targets(9, (B, 2 * L * L))
+    _, g = pnet.window_loss_and_grad(p, wins, tg, L)
+    flat = pnet.pack(p)
+    rng = np.random.default_rng(2)
+    idx = list(rng.choice(flat.size, 30, replace=False)) + [flat.size - 1]
+    h = 1e-5
+
+    def f(v):
+        return pnet.loss(pnet.unpack(v), wins, tg[:, None, :], L, slices=[3])
+    for i in idx:
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += h
+        fm[i] -= h
+        fd = (f(fp) - f(fm)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_centre_logits_of_a_window_equal_the_full_configuration():
+    # the centre slice of a 7-slice window sees exactly its receptive field
+    L, M = 3, 11
+    p = _params(4)
+    x = workloads.random_fields(3, M, 2 * L * L)
+    l = 2
+    rows = [(l - 1 + a - 3) % M for a in range(7)]
+    zw = pnet.logits(p, x[rows], L)[3]
+    assert np.abs(zw - pnet.slice_logits(p, x, L, l)).max() < 1e-12
+
+
+def test_collected_targets_are_post_decision_acceptances():
+    from oracle.dqmc import BitSource
+    m = tiny_model(U=3.8, dtau=0.25, M=4)
+    x = workloads.random_fields(8, m.M, m.N)
+    bits = workloads.accept_bits(9, 2 * m.M * m.N, 0.5)
+    ch = Chain(m, x, collect_every=2)
+    ch.sweep(BitSource(bits), measure=False)
+    assert [c[0] for c in ch.collected] == [4, 2]
+    R = np.array(ch.ratios[m.M * m.N:])            # downward pass, slices M..1
+    b = bits[m.M * m.N:]
+    Rt = np.where(b == 1, 1.0 / R, R)        # ratio of flipping back after the decision
+    a = Rt / (1.0 + Rt)
+    for k, l in enumerate(range(m.M, 0, -1)):
+        assert np.allclose(ch.targets[l - 1], a[k * m.N:(k + 1) * m.N], rtol=1e-15, atol=0)
+    l, win, tg = ch.collected[0]
+    assert np.array_equal(tg, ch.targets[l - 1])
+    assert win.shape == (7, m.N)
+
+
+def test_log_sigmoid_is_stable_and_exact():
+    y = np.array([-800.0, -30.0, -1.0, 0.0, 2.5, 40.0, 800.0])
+    ref = np.array([-800.0, -30.0 - np.log1p(np.exp(-30.0)), -np.log1p(np.e), -np.log(2.0),
+                    -np.log1p(np.exp(-2.5)), -np.log1p(np.exp(-40.0)), 0.0])
+    assert np.allclose(pnet.log_sigmoid(y), ref, rtol=1e-15, atol=1e-300)
