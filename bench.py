@@ -27,7 +27,7 @@ PEAK_HBM = 8.0e12       # MI355X HBM3E, B/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="twist_L18")
     ap.add_argument("--k", type=int, default=None, help="flush rank override")
@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-fp64-twin", action="store_true",
                     help="mixed precision: skip the FP64 run of the same chains used for the bias")
+    ap.add_argument("--proposal", default="both", choices=("plain", "learned", "both"))
+    ap.add_argument("--learn-per-slice", type=int, default=4)
+    ap.add_argument("--learn-m", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=400)
     return ap.parse_args()
 
 
@@ -125,6 +129,62 @@ def fp64_twin(descs, warmup, sweeps, main_series):
     return out
 
 
+def tau_int_grouped(series, groups, c=5.0):
+    """Integrated autocorrelation time of per-sweep series from many chains:
+    deviations from the mean of the chain's group (chains with the same
+    parameters), autocovariance pooled over chains, Sokal window W >= c tau."""
+    by = {}
+    for x, g in zip(series, groups):
+        by.setdefault(g, []).append(np.asarray(x, dtype=np.float64))
+    devs = []
+    for xs in by.values():
+        n = min(len(x) for x in xs)
+        if n < 3:
+            continue
+        mu = np.mean([x[-n:] for x in xs])
+        devs += [x[-n:] - mu for x in xs]
+    if not devs:
+        return None
+    n = min(len(d) for d in devs)
+    D = np.array([d[-n:] for d in devs])
+    c0 = np.mean(D * D)
+    if c0 <= 0:
+        return None
+    tau = 0.5
+    for t in range(1, n):
+        tau += np.mean(D[:, t:] * D[:, :-t]) / c0
+        if t >= c * tau:
+            break
+    return max(tau, 0.5)
+
+
+def timed_leg(sim, steps, label, learn_m=0):
+    import torch
+    n = sim.n
+    sim.reset_obs()
+    st0 = [sim.stats(i) for i in range(n)]
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        sim.sweep(1, measure=True)
+        torch.cuda.synchronize()
+        print("%s sweep %d done (%.2f s)" % (label, s + 1, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    tim = sim.timing()
+    sim.set_timing(False)
+    st1 = [sim.stats(i) for i in range(n)]
+    d = lambda k: sum(st1[i][k] - st0[i][k] for i in range(n))
+    props, acc, sweeps = d("proposals"), d("accepted"), d("sweeps")
+    lprops, lacc = d("learn_proposals"), d("learn_accepted")
+    groups = [(x["L"], round(x["theta1"], 9), round(x["theta2"], 9)) for x in sim.descs]
+    tau = tau_int_grouped([sim.series(i)["m2"] for i in range(n)], groups)
+    return {"dt": dt, "tim": tim, "props": props, "acc": acc, "sweeps": sweeps, "lprops": lprops, "lacc": lacc,
+            "value": (props + learn_m * lprops) / dt, "tau_m2": tau,
+            "ess_per_s": (sweeps / dt / (2 * tau)) if tau else None,
+            "drift": max(s["drift_max"] for s in st1)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -140,50 +200,19 @@ def main():
     Mmax = max(s[1] for s in sim.shapes)
     print("workload %s: %d instances, Nmax %d, Mmax %d, complex %s" % (a.workload, n, Nmax, Mmax,
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
+    learned = a.proposal in ("learned", "both")
     for w in range(a.warmup):
+        if learned and w == a.warmup - 1:
+            sim.collect(8)     # training windows from the last warm-up sweep
         sim.sweep(1, measure=True)
         torch.cuda.synchronize()
         print("warmup sweep %d done" % (w + 1), file=sys.stderr, flush=True)
-    sim.reset_obs()
-    st0 = [sim.stats(i) for i in range(n)]
-    sim.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(a.steps):
-        sim.sweep(1, measure=True)
-        torch.cuda.synchronize()
-        print("timed sweep %d done (%.2f s)" % (s + 1, time.perf_counter() - t0), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    tim = sim.timing()
-    sim.set_timing(False)
-    st1 = [sim.stats(i) for i in range(n)]
-    props = sum(st1[i]["proposals"] - st0[i]["proposals"] for i in range(n))
-    acc = sum(st1[i]["accepted"] - st0[i]["accepted"] for i in range(n))
-    sweeps = sum(st1[i]["sweeps"] - st0[i]["sweeps"] for i in range(n))
-    drift = max(s["drift_max"] for s in st1)
-    value = props / dt
-    # effective samples: pooled autocorrelation of the per-sweep m^2 series
-    ess_rate = None
-    try:
-        from oracle import stats as ostats  # the oracle's statistics helpers only
-        ser = [sim.series(i)["m2"] for i in range(n)]
-        ser = [x for x in ser if len(x) >= 4]
-        if ser:
-            L = min(len(x) for x in ser)
-            rho = np.mean([ostats.autocorr(x[-L:]) for x in ser], axis=0)
-            tau = 0.5
-            for W in range(1, L):
-                tau += rho[W]
-                if W >= 5 * tau:
-                    break
-            tau = max(tau, 0.5)
-            ess_rate = sweeps / dt / (2 * tau)
-    except Exception:
-        ess_rate = None
+    sim.collect(0)
+    plain = timed_leg(sim, a.steps, "plain")
+    dt, tim = plain["dt"], plain["tim"]
     line = {
-        "metric": "HS field updates/s + effective samples/s at L=18,βt=18 (learned vs plain)",
-        "value": value,
+        "metric": "HS field updates/s + effective samples/s at L=18,\u03b2t=18 (learned vs plain)",
+        "value": plain["value"],
         "unit": "HS field updates/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -197,9 +226,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
                    "dtau": descs[0]["dtau"], "proposal": "plain"},
-        "ess_per_s": ess_rate,
-        "acceptance": acc / max(props, 1),
-        "drift_max": drift,
+        "ess_per_s": plain["ess_per_s"],
+        "tau_int_m2_sweeps": plain["tau_m2"],
+        "acceptance": plain["acc"] / max(plain["props"], 1),
+        "drift_max": plain["drift"],
     }
     # roofline of the rank-k flush (FP64 MFMA GEMM, complex128 as 4 real products)
     fl = tim["flush"]
@@ -224,6 +254,29 @@ def main():
         if not a.no_fp64_twin:
             ser = [sim.series(i) for i in range(n)]
             line["fp64_twin"] = fp64_twin(descs, a.warmup, a.steps, ser)
+    if learned:
+        f, cap = sim.sample_count()
+        sim.net_init(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = sim.net_train(a.train_steps, batch=16, lr=3e-3, seed=1)
+        train_s = time.perf_counter() - t0
+        print("trained %d steps on %d windows in %.2f s (loss %.4f -> %.4f)" % (
+            a.train_steps, f, train_s, losses[:20].mean(), losses[-20:].mean()), file=sys.stderr, flush=True)
+        sim.set_proposals(a.learn_per_slice, a.learn_m)
+        lg = timed_leg(sim, a.steps, "learned", learn_m=a.learn_m)
+        sim.set_proposals(0, 0)
+        line["learned"] = {
+            "value": lg["value"], "unit": "HS field updates/s (a learned move counts m)",
+            "ms_per_step": 1e3 * lg["dt"] / max(a.steps, 1),
+            "ess_per_s": lg["ess_per_s"], "tau_int_m2_sweeps": lg["tau_m2"],
+            "acceptance_single": lg["acc"] / max(lg["props"], 1),
+            "acceptance_learned": lg["lacc"] / max(lg["lprops"], 1),
+            "per_slice": a.learn_per_slice, "m": a.learn_m,
+            "train": {"steps": a.train_steps, "windows": f, "seconds": train_s,
+                      "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
+            "learn_ms": round(lg["tim"]["learn"]["ms"], 1),
+        }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(descs, a.cpu_seconds)
     print(json.dumps(line))
