@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--no-fp64-twin", action="store_true",
                     help="mixed precision: skip the FP64 run of the same chains used for the bias")
     ap.add_argument("--proposal", default="both", choices=("plain", "learned", "both"))
+    ap.add_argument("--no-timing", action="store_true", help="no per-launch HIP events (for counter runs)")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -158,12 +159,12 @@ def tau_int_grouped(series, groups, c=5.0):
     return max(tau, 0.5)
 
 
-def timed_leg(sim, steps, label, learn_m=0):
+def timed_leg(sim, steps, label, learn_m=0, events=True):
     import torch
     n = sim.n
     sim.reset_obs()
     st0 = [sim.stats(i) for i in range(n)]
-    sim.set_timing(True)
+    sim.set_timing(events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
@@ -208,7 +209,7 @@ def main():
         torch.cuda.synchronize()
         print("warmup sweep %d done" % (w + 1), file=sys.stderr, flush=True)
     sim.collect(0)
-    plain = timed_leg(sim, a.steps, "plain")
+    plain = timed_leg(sim, a.steps, "plain", events=not a.no_timing)
     dt, tim = plain["dt"], plain["tim"]
     line = {
         "metric": "HS field updates/s + effective samples/s at L=18,\u03b2t=18 (learned vs plain)",
@@ -247,10 +248,11 @@ def main():
                                  "traffic": None, "launches": wr["launches"],
                                  "avg_launch_us": 1e3 * wr["ms"] / max(wr["launches"], 1)}
     line["time_split_ms"] = {k: round(tim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab")}
-    if descs[0]["precision"] == 1:
+    if descs[0]["precision"] == 1 and "roofline" in line:
         line["roofline"]["kernel"] = "k_flush_f32 (G -= X Y, FP32 MFMA)"
         line["roofline"]["peak"] = 157.3  # FP32 matrix peak for the FP32 flush
         line["roofline"]["frac"] = line["roofline"]["achieved"] / 157.3
+    if descs[0]["precision"] == 1:
         if not a.no_fp64_twin:
             ser = [sim.series(i) for i in range(n)]
             line["fp64_twin"] = fp64_twin(descs, a.warmup, a.steps, ser)

@@ -59,6 +59,24 @@ template <> struct cx_of<float> {
   static DQMC_HD cplxf make(double a, double b) { return cmakef((float)a, (float)b); }
 };
 
+// Loads and stores through the global address space.  Pointers taken from
+// the instance descriptors are generic; accesses through them compile to FLAT
+// instructions, which also count against the LDS wait counter, so a wait for
+// an LDS read would wait for every memory load still in flight.
+typedef const __attribute__((address_space(1))) double* gdptr;
+typedef __attribute__((address_space(1))) double* gdptr_w;
+__device__ __forceinline__ double gld(const double* p) { return *(gdptr)p; }
+__device__ __forceinline__ cplx gld(const cplx* p) {
+  gdptr q = (gdptr)p;   // component loads: a struct load through the cast stays FLAT
+  return cmake(q[0], q[1]);
+}
+__device__ __forceinline__ void gst(double* p, double v) { *(gdptr_w)p = v; }
+__device__ __forceinline__ void gst(cplx* p, cplx v) {
+  gdptr_w q = (gdptr_w)p;
+  q[0] = v.x;
+  q[1] = v.y;
+}
+
 template <typename S> struct ST;
 template <> struct ST<double> {
   static constexpr bool is_complex = false;

@@ -69,38 +69,35 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
   const int tm = (M + BM - 1) / BM, tn = (NC + BN - 1) / BN;
   const int ntiles = tm * tn;
 
-  // global -> register staging of one BK chunk (4 values of op(A), 4 of op(B) per thread)
-  double ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+  // global -> register staging of one BK chunk (4 values of op(A), 4 of op(B)
+  // per thread).  Addresses are clamped and the raw values kept with an
+  // in-range mask; masking and conjugation happen in store_chunk, so the
+  // loads of the next chunk stay in flight while the current one is
+  // multiplied (no branch, no select right behind the loads).
+  S va[4], vb[4];
+  unsigned mask_a = 0, mask_b = 0;
   auto load_chunk = [&](int m0, int n0, int k0) {
+    mask_a = 0;
+    mask_b = 0;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int i, kk;
       if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
       else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
-      int gi = m0 + i, gk = k0 + kk;
-      double re = 0.0, im = 0.0;
-      if (gi < M && gk < K && !(a_upper && gi > gk)) {
-        S v = A.op == 0 ? pa[gi + (size_t)gk * ld] : pa[gk + (size_t)gi * ld];
-        split<S>(v, re, im);
-        if (A.op == 2) im = -im;
-      }
-      ra_r[p] = re;
-      ra_i[p] = im;
+      const int gi = m0 + i, gk = k0 + kk;
+      if (gi < M && gk < K && !(a_upper && gi > gk)) mask_a |= 1u << p;
+      const int gic = min(gi, M - 1), gkc = min(gk, K - 1);
+      va[p] = gld(pa + (A.op == 0 ? gic + (size_t)gkc * ld : gkc + (size_t)gic * ld));
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int j, kk;
       if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
-      int gj = n0 + j, gk = k0 + kk;
-      double re = 0.0, im = 0.0;
-      if (gj < NC && gk < K) {
-        S v = B.op == 0 ? pb[gk + (size_t)gj * ld] : pb[gj + (size_t)gk * ld];
-        split<S>(v, re, im);
-        if (B.op == 2) im = -im;
-      }
-      rb_r[p] = re;
-      rb_i[p] = im;
+      const int gj = n0 + j, gk = k0 + kk;
+      if (gj < NC && gk < K) mask_b |= 1u << p;
+      const int gjc = min(gj, NC - 1), gkc = min(gk, K - 1);
+      vb[p] = gld(pb + (B.op == 0 ? gkc + (size_t)gjc * ld : gjc + (size_t)gkc * ld));
     }
   };
   auto store_chunk = [&]() {
@@ -109,16 +106,24 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
       int i, kk;
       if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
       else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
-      Ar[kk][i] = ra_r[p];
-      if constexpr (CX) Ai[kk][i] = ra_i[p];
+      double re, im;
+      split<S>(va[p], re, im);
+      if (A.op == 2) im = -im;
+      const bool in = (mask_a >> p) & 1u;
+      Ar[kk][i] = in ? re : 0.0;
+      if constexpr (CX) Ai[kk][i] = in ? im : 0.0;
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int j, kk;
       if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
-      Br[kk][j] = rb_r[p];
-      if constexpr (CX) Bi[kk][j] = rb_i[p];
+      double re, im;
+      split<S>(vb[p], re, im);
+      if (B.op == 2) im = -im;
+      const bool in = (mask_b >> p) & 1u;
+      Br[kk][j] = in ? re : 0.0;
+      if constexpr (CX) Bi[kk][j] = in ? im : 0.0;
     }
   };
 
@@ -145,12 +150,11 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
           for (int r = 0; r < 4; ++r) {
             int gi = m0 + wr + ti * 16 + (lane & 15);
             int gj = n0 + wc + tj * 16 + (lane >> 4) + 4 * r;
-            if (gi < M && gj < NC) {
-              double re, im;
-              split<S>(pc[gi + (size_t)gj * ld], re, im);
-              acc_r[ti][tj][r] = cscale * re;
-              acc_i[ti][tj][r] = cscale * im;
-            }
+            const bool in = gi < M && gj < NC;
+            double re, im;
+            split<S>(gld(pc + min(gi, M - 1) + (size_t)min(gj, NC - 1) * ld), re, im);
+            acc_r[ti][tj][r] = in ? cscale * re : 0.0;
+            acc_i[ti][tj][r] = in ? cscale * im : 0.0;
           }
     }
     // upper-triangular op(A): chunks with k < m0 contribute nothing
@@ -242,30 +246,35 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
   for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
     const int i0 = (blk % nb32) * 32, j0 = (blk / nb32) * 32;
     d4 ar_[2][2], ai_[2][2];   // [ti][tj] accumulators (transposed blocks)
-    // start from -G (alpha = -1): acc = X Y - G, G_new = -acc
+    // start from -G (alpha = -1): acc = X Y - G, G_new = -acc.  Every load
+    // reads a clamped, valid address and out-of-range values are zeroed
+    // afterwards, so that no load sits behind a branch (and its wait).
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          int gi = i0 + ti * 16 + lr, gj = j0 + tj * 16 + lk + 4 * r;
-          double re = 0.0, im = 0.0;
-          if (gi < N && gj < N) split<S>(G[gi + (size_t)gj * N], re, im);
-          ar_[ti][tj][r] = -re;
-          ai_[ti][tj][r] = -im;
+          const int gi = i0 + ti * 16 + lr, gj = j0 + tj * 16 + lk + 4 * r;
+          const bool in = gi < N && gj < N;
+          double re, im;
+          split<S>(gld(G + min(gi, N - 1) + (size_t)min(gj, N - 1) * N), re, im);
+          ar_[ti][tj][r] = in ? -re : 0.0;
+          ai_[ti][tj][r] = in ? -im : 0.0;
         }
     auto frag = [&](int k, double (&xr)[2], double (&xi)[2], double (&yr)[2], double (&yi)[2]) {
       const int kk = k + lk;
+      const bool kin = kk < K;
+      const size_t kc = (size_t)(kin ? kk : 0) * N;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        int gi = i0 + t * 16 + lr, gj = j0 + t * 16 + lr;
-        double a = 0, b = 0, c = 0, e = 0;
-        if (kk < K) {
-          if (gi < N) split<S>(X[gi + (size_t)kk * N], a, b);
-          if (gj < N) split<S>(Y[(size_t)kk * N + gj], c, e);
-        }
-        xr[t] = a; xi[t] = b; yr[t] = c; yi[t] = e;
+        const int gi = i0 + t * 16 + lr, gj = j0 + t * 16 + lr;
+        const bool xin = kin && gi < N, yin = kin && gj < N;
+        double a, b, c, e;
+        split<S>(gld(X + min(gi, N - 1) + kc), a, b);
+        split<S>(gld(Y + kc + min(gj, N - 1)), c, e);
+        xr[t] = xin ? a : 0.0; xi[t] = xin ? b : 0.0;
+        yr[t] = yin ? c : 0.0; yi[t] = yin ? e : 0.0;
       }
     };
     // fragments two k-steps ahead; independent accumulators interleaved so
@@ -352,15 +361,17 @@ k_flush_f32(const InstDev* __restrict__ insts, int flags) {
       for (int tj = 0; tj < 2; ++tj) { ar_[ti][tj] = f4{0, 0, 0, 0}; ai_[ti][tj] = f4{0, 0, 0, 0}; }
     auto frag = [&](int k, float (&xr)[2], float (&xi)[2], float (&yr)[2], float (&yi)[2]) {
       const int kk = k + lk;
+      const bool kin = kk < K;
+      const size_t kc = (size_t)(kin ? kk : 0) * N;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        int gi = i0 + t * 16 + lr, gj = j0 + t * 16 + lr;
-        double a = 0, b = 0, c = 0, e = 0;
-        if (kk < K) {
-          if (gi < N) split<S>(X[gi + (size_t)kk * N], a, b);
-          if (gj < N) split<S>(Y[(size_t)kk * N + gj], c, e);
-        }
-        xr[t] = (float)a; xi[t] = (float)b; yr[t] = (float)c; yi[t] = (float)e;
+        const int gi = i0 + t * 16 + lr, gj = j0 + t * 16 + lr;
+        const bool xin = kin && gi < N, yin = kin && gj < N;
+        double a, b, c, e;
+        split<S>(gld(X + min(gi, N - 1) + kc), a, b);
+        split<S>(gld(Y + kc + min(gj, N - 1)), c, e);
+        xr[t] = xin ? (float)a : 0.f; xi[t] = xin ? (float)b : 0.f;
+        yr[t] = yin ? (float)c : 0.f; yi[t] = yin ? (float)e : 0.f;
       }
     };
     float xr[2], xi[2], yr[2], yi[2], nxr[2], nxi[2], nyr[2], nyi[2];
