@@ -630,32 +630,50 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
   S* C = matp<S>(d, target);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  constexpr int RB = 64;   // rows of V and C staged per step
+  constexpr int RB = 32;   // rows of V and C staged per step
   __shared__ double Vr[RB][NBR + 1], Vi[CX ? RB : 1][NBR + 1];
   __shared__ double Cr[RB][AR_CT + 1], Ci[CX ? RB : 1][AR_CT + 1];
   __shared__ S Ws[NBR][AR_CT + 1];
   __shared__ S Tt[NBR][NBR + 1];
-  // ---- W = V^H C: wave w owns columns 16w..16w+15 of the tile
+  // ---- W = V^H C: wave w owns columns 16w..16w+15 of the tile.  Each
+  // thread stages 2 elements of V and 8 of C per row block; all loads read
+  // clamped addresses and are issued before the first is used.
+  constexpr int NV = RB * NBR / 256, NC = RB * AR_CT / 256;
   d4 wr = d4{0, 0, 0, 0}, wi = d4{0, 0, 0, 0};
+#pragma unroll 1
   for (int i0 = j0; i0 < N; i0 += RB) {
-    for (int x = tid; x < RB * NBR; x += 256) {
-      int r = x % RB, m = x / RB, i = i0 + r;
-      double re = 0, im = 0;
-      if (i < N && m < nbe) split_s<S>(V[i + (size_t)(j0 + m) * N], re, im);
-      Vr[r][m] = re;
-      if constexpr (CX) Vi[r][m] = im;
+    S vv[NV], cv[NC];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int x = tid + 256 * q, r = x % RB, m = x / RB;
+      vv[q] = gld(V + min(i0 + r, N - 1) + (size_t)(j0 + min(m, nbe - 1)) * N);
     }
-    for (int x = tid; x < RB * AR_CT; x += 256) {
-      int r = x % RB, cc = x / RB, i = i0 + r, c = c0 + cc;
-      double re = 0, im = 0;
-      if (i < N && c < N) split_s<S>(C[i + (size_t)c * N], re, im);
-      Cr[r][cc] = re;
-      if constexpr (CX) Ci[r][cc] = im;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int x = tid + 256 * q, r = x % RB, cc = x / RB;
+      cv[q] = gld(C + min(i0 + r, N - 1) + (size_t)min(c0 + cc, N - 1) * N);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int x = tid + 256 * q, r = x % RB, m = x / RB;
+      const bool in = i0 + r < N && m < nbe;
+      double re, im;
+      split_s<S>(vv[q], re, im);
+      Vr[r][m] = in ? re : 0.0;
+      if constexpr (CX) Vi[r][m] = in ? im : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int x = tid + 256 * q, r = x % RB, cc = x / RB;
+      const bool in = i0 + r < N && c0 + cc < N;
+      double re, im;
+      split_s<S>(cv[q], re, im);
+      Cr[r][cc] = in ? re : 0.0;
+      if constexpr (CX) Ci[r][cc] = in ? im : 0.0;
     }
     __syncthreads();
-    const int nks = min(RB, N - i0 + 3) / 4;
 #pragma unroll 2
-    for (int ks = 0; ks < nks; ++ks) {
+    for (int ks = 0; ks < RB / 4; ++ks) {
       const int k = ks * 4 + lk;
       // A = V^H: A[m][k] = conj(V[k][m]); B = C: B[k][c]
       double ar = Vr[k][lr], br = Cr[k][wave * 16 + lr];
@@ -675,23 +693,22 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
     if constexpr (CX) Ws[lk + 4 * r][wave * 16 + lr] = cmake(wr[r], wi[r]);
     else Ws[lk + 4 * r][wave * 16 + lr] = wr[r];
   }
+  // op(T) into LDS: T itself, or T^H[r][c] = conj(T[c][r])
   for (int x = tid; x < NBR * NBR; x += 256) {
-    int r = x % NBR, c = x / NBR;
-    S t = (r < nbe && c < nbe) ? TB[(j0 + r) + (size_t)c * N] : ST<S>::zero();
-    // op(T): T^H[r][c] = conj(T[c][r]) -> stored transposed below
-    Tt[r][c] = t;
+    const int r = x % NBR, c = x / NBR;
+    const int tr = use_th ? c : r, tc = use_th ? r : c;
+    S t = (tr < nbe && tc < nbe) ? TB[(j0 + tr) + (size_t)tc * N] : ST<S>::zero();
+    Tt[r][c] = use_th ? conjg(t) : t;
   }
   __syncthreads();
   // ---- W' = op(T) W (16 x 64), written over Ws after a barrier
   S wp[4];
-#pragma unroll
+#pragma unroll 1
   for (int u = 0; u < 4; ++u) {
-    int x = tid + 256 * u, m = x % NBR, c = x / NBR;
+    const int x = tid + 256 * u, m = x % NBR, c = x / NBR;
     S acc = ST<S>::zero();
-    for (int k = 0; k < NBR; ++k) {
-      S t = use_th ? conjg(Tt[k][m]) : Tt[m][k];
-      acc = acc + t * Ws[k][c];
-    }
+#pragma unroll 4
+    for (int k = 0; k < NBR; ++k) acc = acc + Tt[m][k] * Ws[k][c];
     wp[u] = acc;
   }
   __syncthreads();
@@ -705,38 +722,45 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
   // Operands fed as (W', V) so a lane owns one row and four columns of the
   // block and the stores coalesce along the column.
   const int cw = c0 + wave * 16;
+  double br[4], bi[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) split_s<S>(Ws[ks * 4 + lk][wave * 16 + lr], br[ks], bi[ks]);
+#pragma unroll 1
   for (int i0 = j0; i0 < N; i0 += 16) {
+    const int i = i0 + lr, ic = min(i, N - 1);
+    S cl[4], vl[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, N - 1) * N);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) vl[ks] = gld(V + ic + (size_t)(j0 + min(ks * 4 + lk, nbe - 1)) * N);
     d4 cr, ci;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int i = i0 + lr, c = cw + lk + 4 * r;
-      double re = 0, im = 0;
-      if (i < N && c < N) split_s<S>(C[i + (size_t)c * N], re, im);
+      double re, im;
+      split_s<S>(cl[r], re, im);
       cr[r] = -re;
       ci[r] = -im;
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int m = ks * 4 + lk;
-      const int i = i0 + lr;
-      double vr = 0, vi = 0;
-      if (i < N && m < nbe) split_s<S>(V[i + (size_t)(j0 + m) * N], vr, vi);
-      double br, bi;
-      split_s<S>(Ws[m][wave * 16 + lr], br, bi);
+      double vr, vi;
+      split_s<S>(vl[ks], vr, vi);
+      if (!(i < N && m < nbe)) { vr = 0.0; vi = 0.0; }
       // acc^T += W'^T V^T : A-operand W'[m][c] as (c, m), B-operand V[i][m] as (m, i)
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(br[ks], vr, cr, 0, 0, 0);
       if constexpr (CX) {
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi, vi, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vr, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vi, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi[ks], vi, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[ks], vr, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(br[ks], vi, ci, 0, 0, 0);
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int i = i0 + lr, c = cw + lk + 4 * r;
+      int c = cw + lk + 4 * r;
       if (i < N && c < N) {
-        if constexpr (CX) C[i + (size_t)c * N] = cmake(-cr[r], -ci[r]);
-        else C[i + (size_t)c * N] = -cr[r];
+        if constexpr (CX) gst(C + i + (size_t)c * N, cmake(-cr[r], -ci[r]));
+        else gst(C + i + (size_t)c * N, -cr[r]);
       }
     }
   }
