@@ -37,6 +37,7 @@ def parse():
                     help="mixed precision: skip the FP64 run of the same chains used for the bias")
     ap.add_argument("--proposal", default="both", choices=("plain", "learned", "both"))
     ap.add_argument("--no-timing", action="store_true", help="no per-launch HIP events (for counter runs)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the workload's flush rank")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -202,6 +203,13 @@ def main():
     print("workload %s: %d instances, Nmax %d, Mmax %d, complex %s" % (a.workload, n, Nmax, Mmax,
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
     learned = a.proposal in ("learned", "both")
+    tuned = None
+    if a.k is None and not a.no_autotune:
+        nst = descs[0]["n_stab"]
+        cand = [k for k in (16, 24, 32, 48, 64, 96, 128)]
+        best, per = sim.autotune(cand, 2 * nst)
+        tuned = {"k": best, "ms_per_step": {str(k): round(v, 3) for k, v in per.items()}}
+        print("autotuned flush rank k=%d: %s" % (best, tuned["ms_per_step"]), file=sys.stderr, flush=True)
     for w in range(a.warmup):
         if learned and w == a.warmup - 1:
             sim.collect(8)     # training windows from the last warm-up sweep
@@ -227,6 +235,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
                    "dtau": descs[0]["dtau"], "proposal": "plain"},
+        "autotune": tuned,
         "ess_per_s": plain["ess_per_s"],
         "tau_int_m2_sweeps": plain["tau_m2"],
         "acceptance": plain["acc"] / max(plain["props"], 1),

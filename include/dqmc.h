@@ -80,7 +80,8 @@ typedef struct {
   double t, U;          /* hopping and Hubbard U */
   double beta, dtau;    /* M = beta/dtau must be an integer within 1e-9 */
   double theta1, theta2;/* twist Theta_1, Theta_2 in radians along a1, a2; both 0 = periodic (real path) */
-  int32_t n_delay;      /* flush rank k: flush once at least k accepted flips are pending, 1 <= k <= 192 */
+  int32_t n_delay;      /* flush rank k: flush once at least k accepted flips are pending, 1 <= k <= 192
+                         * (retunable later with dqmc_set_delay / dqmc_autotune) */
   int32_t n_stab;       /* slices between recomputations of G (stabilisation) */
   int32_t precision;    /* dqmc_precision, the same for all instances of a handle */
   int32_t sym_measure;  /* 1: estimators on exp(-dtau K/2) G exp(+dtau K/2) */
@@ -271,6 +272,19 @@ dqmc_status dqmc_net_train_workspace_size(dqmc_handle h, int32_t batch, size_t* 
  * collected.  Synchronises. */
 dqmc_status dqmc_net_train(dqmc_handle h, void* dev_ws, size_t bytes, int32_t steps, int32_t batch, float lr,
                            uint64_t seed, float* host_loss);
+
+/* Flush rank k of every instance (1 <= k <= max(n_delay, 128) of the
+ * creation descriptors).  The rank changes when the buffered rank-1 terms
+ * are applied, never the sequence of G's or decisions.  Synchronises. */
+dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k);
+
+/* Autotuner of the flush rank: for each of the n_cand candidate ranks, run
+ * `steps` slice steps (a multiple of n_stab; the chains advance as in a
+ * sweep, without estimators), time them with HIP events, and keep the
+ * fastest (written to *best; ms_per_step[q], nullable, gets the time per
+ * step of candidate q).  Synchronises. */
+dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
+                          double* ms_per_step);
 
 /* Matrix dimension N, slices M and whether G is complex, for instance inst. */
 dqmc_status dqmc_shape(dqmc_handle h, int32_t inst, int32_t* N, int32_t* M, int32_t* is_complex);

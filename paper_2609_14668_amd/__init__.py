@@ -91,6 +91,8 @@ _SIGS = {
     "dqmc_net_train_workspace_size": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "dqmc_net_train": [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
                        _P],
+    "dqmc_set_delay": [_P, ctypes.c_int32],
+    "dqmc_autotune": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
     "dqmc_status_string": [ctypes.c_int32],
     "dqmc_last_error": [_P],
 }
@@ -393,3 +395,20 @@ class Simulation:
         return losses[:steps]
 
     net_train = dqmc_net_train
+
+    def dqmc_set_delay(self, k):
+        self._chk(self.lib.dqmc_set_delay(self.h, int(k)), "set_delay")
+
+    set_delay = dqmc_set_delay
+
+    def dqmc_autotune(self, candidates, steps):
+        """Time `steps` slice steps per candidate flush rank and keep the
+        fastest; returns (best, {k: ms per step})."""
+        c = np.ascontiguousarray(candidates, dtype=np.int32)
+        ms = np.zeros(c.size, dtype=np.float64)
+        best = ctypes.c_int32()
+        self._chk(self.lib.dqmc_autotune(self.h, int(steps), c.ctypes.data, c.size, ctypes.byref(best),
+                                         ms.ctypes.data), "autotune")
+        return best.value, {int(k): float(t) for k, t in zip(c, ms)}
+
+    autotune = dqmc_autotune

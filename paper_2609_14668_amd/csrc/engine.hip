@@ -72,7 +72,8 @@ struct Plan {
   int ring_cap = 0;
 };
 
-constexpr int NET_RING = 2048;   // training sample slots (rounded up to a multiple of the instances)
+constexpr int NET_RING = 2048;
+constexpr int KTUNE_MAX = 128;   // largest flush rank dqmc_set_delay may choose without a new workspace   // training sample slots (rounded up to a multiple of the instances)
 
 dqmc_status validate(const dqmc_instance_desc* d, int n, std::string& err) {
   if (!d || n < 1) { err = "need at least one instance"; return DQMC_EINVAL; }
@@ -105,7 +106,7 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     const int L = d[i].L, N = 2 * L * L, Nc = L * L;
     const int M = (int)std::lround(d[i].beta / d[i].dtau);
     const int C = M / d[i].n_stab;
-    const int kcap = d[i].n_delay + WINDOW;
+    const int kcap = std::max(d[i].n_delay, KTUNE_MAX) + WINDOW;   // the flush rank can be retuned up to KTUNE_MAX
     p.Nmax = std::max(p.Nmax, N);
     p.Mmax = std::max(p.Mmax, M);
     Offs f;
@@ -596,7 +597,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.n_stab = x.n_stab;
     dv.n_ckpt = dv.M / x.n_stab;
     dv.kflush = x.n_delay;
-    dv.kcap = x.n_delay + WINDOW;
+    dv.kcap = std::max(x.n_delay, KTUNE_MAX) + WINDOW;
     dv.is_complex = p.cplx;
     dv.sym_measure = x.sym_measure;
     dv.fft_fixed = fft_has_fixed(x.L) ? 1 : 0;
@@ -752,15 +753,70 @@ dqmc_status dqmc_get_fields(dqmc_handle h, int32_t inst, int8_t* host_x) {
   return DQMC_OK;
 }
 
-static dqmc_status run_sweeps(dqmc_handle h, int32_t n_sweeps, int32_t measure, hipStream_t s, int replay) {
+// steps is a multiple of n_stab, so the stabilisation points stay aligned
+// across calls.
+static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay) {
   Ctx c{h, s};
-  const int64_t steps = (int64_t)n_sweeps * 2 * h->Mmax;
   for (int64_t k = 0; k < steps; ++k) {
     step(c, k, measure != 0, replay);
     if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c.e));
   }
-  h->sweeps_done += n_sweeps;
   return DQMC_OK;
+}
+
+static dqmc_status run_sweeps(dqmc_handle h, int32_t n_sweeps, int32_t measure, hipStream_t s, int replay) {
+  dqmc_status st = run_steps(h, (int64_t)n_sweeps * 2 * h->Mmax, measure, s, replay);
+  if (st == DQMC_OK) h->sweeps_done += n_sweeps;
+  return st;
+}
+
+dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k) {
+  if (!h || k < 1) return DQMC_EINVAL;
+  for (auto& d : h->hd)
+    if (k > d.kcap - WINDOW) return fail(h, DQMC_EINVAL, "flush rank exceeds the allocated capacity");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (auto& d : h->hd) d.kflush = k;
+  h->kcap_max = k + WINDOW;
+  dqmc_status st = upload_insts(h, h->stream);
+  if (st != DQMC_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
+                          double* ms_per_step) {
+  if (!h || !cand || n_cand < 1 || steps < 1 || steps % h->n_stab != 0) return DQMC_EINVAL;
+  hipStream_t s = h->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  const bool timing = h->timing;
+  h->timing = false;
+  double best_ms = 1e300;
+  int32_t bk = h->hd[0].kflush;
+  dqmc_status st = DQMC_OK;
+  for (int q = 0; q < n_cand && st == DQMC_OK; ++q) {
+    st = dqmc_set_delay(h, cand[q]);
+    if (st != DQMC_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(h, DQMC_EHIP, "autotune event"); break; }
+    st = run_steps(h, steps, 0, s, 0);
+    if (st != DQMC_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(h, DQMC_EHIP, "autotune timing");
+      break;
+    }
+    const double per = ms / steps;
+    if (ms_per_step) ms_per_step[q] = per;
+    if (per < best_ms) { best_ms = per; bk = cand[q]; }
+  }
+  h->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != DQMC_OK) return st;
+  if (best) *best = bk;
+  return dqmc_set_delay(h, bk);
 }
 
 dqmc_status dqmc_sweep(dqmc_handle h, int32_t n_sweeps, int32_t measure, void* stream) {

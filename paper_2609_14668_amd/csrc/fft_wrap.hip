@@ -247,23 +247,42 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
   const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
   const bool rows = a.side != 0;
-  // load (+ pre diagonal)
+  // load (+ pre diagonal), LU elements per thread at a time: every load of a
+  // group reads a clamped address and is issued before the first is used
   const int tot = nvl * N;
-  for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
-    int vv, r;
-    if (!rows) { vv = e / N; r = e - vv * N; }
-    else { vv = e % nvl; r = e / nvl; }
-    int q = v0 + vv;
-    C val;
-    if constexpr (ST<S>::is_complex) {
-      cplx g = rows ? Mx[(size_t)r * N + q] : Mx[(size_t)q * N + r];
-      val = mkc<C>(g.x, rows ? -g.y : g.y);
-    } else {
-      if (!rows) val = mkc<C>(Mx[(size_t)(2 * q) * N + r], Mx[(size_t)(2 * q + 1) * N + r]);
-      else val = mkc<C>(Mx[(size_t)r * N + 2 * q], Mx[(size_t)r * N + 2 * q + 1]);
+  constexpr int LU = 8;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += LU * FFT_THREADS) {
+    S raw[LU][ST<S>::is_complex ? 1 : 2];
+    int8_t xr[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = min(e0 + u * FFT_THREADS, tot - 1);
+      int vv, r;
+      if (!rows) { vv = e / N; r = e - vv * N; }
+      else { vv = e % nvl; r = e / nvl; }
+      const int q = v0 + vv;
+      if constexpr (ST<S>::is_complex) {
+        raw[u][0] = gld(rows ? Mx + (size_t)r * N + q : Mx + (size_t)q * N + r);
+      } else {
+        raw[u][0] = gld(rows ? Mx + (size_t)r * N + 2 * q : Mx + (size_t)(2 * q) * N + r);
+        raw[u][1] = gld(rows ? Mx + (size_t)r * N + 2 * q + 1 : Mx + (size_t)(2 * q + 1) * N + r);
+      }
+      xr[u] = rs.pre ? xs[r] : (int8_t)1;
     }
-    if (rs.pre) val = val * ((rs.pre * xs[r]) > 0 ? ep : em);
-    buf[vv * N + r] = val;
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = e0 + u * FFT_THREADS;
+      if (e < tot) {
+        int vv, r;
+        if (!rows) { vv = e / N; r = e - vv * N; }
+        else { vv = e % nvl; r = e / nvl; }
+        C val;
+        if constexpr (ST<S>::is_complex) val = mkc<C>(raw[u][0].x, rows ? -raw[u][0].y : raw[u][0].y);
+        else val = mkc<C>(raw[u][0], raw[u][1]);
+        if (rs.pre) val = val * ((rs.pre * xr[u]) > 0 ? ep : em);
+        buf[vv * N + r] = val;
+      }
+    }
   }
   __syncthreads();
   C* cur;
@@ -293,11 +312,11 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
     const double vx = (double)val.x, vy = (double)val.y;
     if constexpr (ST<S>::is_complex) {
-      if (rows) Mx[(size_t)r * N + q] = cmake(vx, -vy);
-      else Mx[(size_t)q * N + r] = cmake(vx, vy);
+      if (rows) gst(Mx + (size_t)r * N + q, cmake(vx, -vy));
+      else gst(Mx + (size_t)q * N + r, cmake(vx, vy));
     } else {
-      if (!rows) { Mx[(size_t)(2 * q) * N + r] = vx; Mx[(size_t)(2 * q + 1) * N + r] = vy; }
-      else { Mx[(size_t)r * N + 2 * q] = vx; Mx[(size_t)r * N + 2 * q + 1] = vy; }
+      if (!rows) { gst(Mx + (size_t)(2 * q) * N + r, vx); gst(Mx + (size_t)(2 * q + 1) * N + r, vy); }
+      else { gst(Mx + (size_t)r * N + 2 * q, vx); gst(Mx + (size_t)r * N + 2 * q + 1, vy); }
     }
   }
 }

@@ -68,18 +68,31 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
   __shared__ S sh_c;
 
   // ---- C = G[w,w] - X[w,:fill0] Y[:fill0,w]
+  // every load below reads a clamped address and is masked afterwards, so
+  // that the loads of a group are issued together
   S acc[16];
+  const int ac = w0 + min(lane, wn - 1);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    int a = lane, b = wave + 4 * q;
-    acc[q] = (a < wn && b < wn) ? G[(w0 + a) + (size_t)(w0 + b) * N] : ST<S>::zero();
-  }
+  for (int q = 0; q < 16; ++q) acc[q] = gld(G + ac + (size_t)(w0 + min(wave + 4 * q, wn - 1)) * N);
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (!(lane < wn && wave + 4 * q < wn)) acc[q] = ST<S>::zero();
   for (int m0 = 0; m0 < fill0; m0 += 16) {
-    for (int e = tid; e < 16 * WMAX; e += WIN_THREADS) {
-      int mm = e / WMAX, a = e % WMAX;
-      bool ok = (m0 + mm < fill0) && a < wn;
-      Xw[mm][a] = ok ? X[(w0 + a) + (size_t)(m0 + mm) * N] : ST<S>::zero();
-      Yw[mm][a] = ok ? Y[(size_t)(m0 + mm) * N + w0 + a] : ST<S>::zero();
+    S xv[16 * WMAX / WIN_THREADS], yv[16 * WMAX / WIN_THREADS];
+#pragma unroll
+    for (int u = 0; u < 16 * WMAX / WIN_THREADS; ++u) {
+      const int e = tid + u * WIN_THREADS, mm = e / WMAX, a = e % WMAX;
+      const size_t mc = (size_t)min(m0 + mm, fill0 - 1) * N;
+      const int aw = w0 + min(a, wn - 1);
+      xv[u] = gld(X + aw + mc);
+      yv[u] = gld(Y + mc + aw);
+    }
+#pragma unroll
+    for (int u = 0; u < 16 * WMAX / WIN_THREADS; ++u) {
+      const int e = tid + u * WIN_THREADS, mm = e / WMAX, a = e % WMAX;
+      const bool ok = (m0 + mm < fill0) && a < wn;
+      Xw[mm][a] = ok ? xv[u] : ST<S>::zero();
+      Yw[mm][a] = ok ? yv[u] : ST<S>::zero();
     }
     __syncthreads();
     int mlim = min(16, fill0 - m0);
@@ -98,6 +111,18 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
 
   const double lam = d.lam;
   const int64_t rpos = st->replay_pos;
+  // per-site constants of the scan, fixed for the whole window (a site's
+  // field only changes when it is accepted, which ends its candidacy):
+  // Delta, e^{2 lambda x}, and the uniform u (or the replayed decision)
+  double dlt = 0.0, e2x = 1.0, usite = 0.0;
+  bool rbit = false;
+  if (wave == 0 && lane < wn) {
+    const double x = (double)xs[lane];
+    dlt = exp(-2.0 * lam * x) - 1.0;
+    e2x = exp(2.0 * lam * x);
+    if (replay) rbit = d.replay_bits[rpos + lane] != 0;
+    else usite = site_uniform(d.seed, (uint64_t)st->sweep, pass, l, w0 + lane);
+  }
   int p = 0;
   while (true) {
     if (wave == 0) {
@@ -107,13 +132,10 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
       double R = 0.0;
       S r = ST<S>::one(), dl = ST<S>::zero();
       if (cand) {
-        double x = (double)xs[q];
-        double delta = exp(-2.0 * lam * x) - 1.0;
-        dl = ST<S>::from_re(delta);
+        dl = ST<S>::from_re(dlt);
         r = ST<S>::one() + dl * (ST<S>::one() - C[q][q]);
-        R = exp(2.0 * lam * x) * absq(r);
-        if (replay) acc_q = d.replay_bits[rpos + q] != 0;
-        else acc_q = site_uniform(d.seed, (uint64_t)st->sweep, pass, l, w0 + q) < R;
+        R = e2x * absq(r);
+        acc_q = replay ? rbit : usite < R;
         if (!(R == R) || R == 0.0 || R > 1e300) st->numeric_err = 1;
       }
       unsigned long long mask = __ballot(cand && acc_q);
@@ -184,7 +206,7 @@ constexpr int KC = 8;
 constexpr int EXP_WAVES = 4;   // each wave accumulates KC / EXP_WAVES of the chunk
 template <typename S>
 __global__ void __launch_bounds__(64 * EXP_WAVES)
-k_expand(const InstDev* __restrict__ insts) {
+k_expand(const InstDev* __restrict__ insts, int lcap) {
   constexpr int KW = KC / EXP_WAVES;
   const InstDev& d = insts[blockIdx.y];
   const InstState* st = d.st;
@@ -204,9 +226,10 @@ k_expand(const InstDev* __restrict__ insts) {
   const S* wc = reinterpret_cast<const S*>(d.wcoef);
 
   extern __shared__ char xsmem[];
-  // [m][kk]: y_m[i_k], x_m[i_k] for m < kcap
+  // [m][kk]: y_m[i_k], x_m[i_k] for m < lcap (the launch's LDS capacity,
+  // at least the largest fill a window can leave: kflush - 1 + WMAX)
   S* ycf = reinterpret_cast<S*>(xsmem);
-  S* xcf = ycf + (size_t)d.kcap * KC;
+  S* xcf = ycf + (size_t)lcap * KC;
   __shared__ S pax[KC][64], pay[KC][64];
   __shared__ int sites[WMAX], gsites[WMAX];   // table position, site index
   if (tid < WMAX) {
@@ -237,28 +260,44 @@ k_expand(const InstDev* __restrict__ insts) {
     }
     __syncthreads();
     const int mpre = fill0 + k0;
-    if (ok) {
-      // this wave's share of the chunk: kk = wave*KW .. wave*KW + KW - 1
+    {
+      // this wave's share of the chunk: kk = wave*KW .. wave*KW + KW - 1.
+      // Lanes past N read row/column N-1 and their results are never stored.
+      const int jc = min(j, N - 1);
       S ax[KW], ay[KW];
 #pragma unroll
       for (int q = 0; q < KW; ++q) {
-        int kk = wave * KW + q;
-        if (kk < kn) {
-          int gi = gsites[k0 + kk];
-          ax[q] = G[j + (size_t)gi * N];
-          ay[q] = -G[gi + (size_t)j * N];
-          if (j == gi) ay[q] = ay[q] + ST<S>::one();
-        } else {
-          ax[q] = ST<S>::zero();
-          ay[q] = ST<S>::zero();
-        }
+        const int kk = wave * KW + q;
+        const int gi = gsites[k0 + min(kk, kn - 1)];
+        ax[q] = gld(G + jc + (size_t)gi * N);
+        ay[q] = -gld(G + gi + (size_t)jc * N);
+        if (jc == gi) ay[q] = ay[q] + ST<S>::one();
+        if (kk >= kn) { ax[q] = ST<S>::zero(); ay[q] = ST<S>::zero(); }
       }
-      for (int m = 0; m < mpre; ++m) {
-        S xv = X[j + (size_t)m * N];
-        S yv = Y[(size_t)m * N + j];
+      constexpr int MU = 4;   // rows of X / columns of Y loaded per group
+      int m = 0;
+      for (; m + MU <= mpre; m += MU) {
+        S xv[MU], yv[MU];
+#pragma unroll
+        for (int u = 0; u < MU; ++u) {
+          xv[u] = gld(X + jc + (size_t)(m + u) * N);
+          yv[u] = gld(Y + (size_t)(m + u) * N + jc);
+        }
+#pragma unroll
+        for (int u = 0; u < MU; ++u)
+#pragma unroll
+          for (int q = 0; q < KW; ++q) {
+            const int kk = wave * KW + q;
+            ax[q] = ax[q] - xv[u] * ycf[(m + u) * KC + kk];
+            ay[q] = ay[q] + xcf[(m + u) * KC + kk] * yv[u];
+          }
+      }
+      for (; m < mpre; ++m) {
+        S xv = gld(X + jc + (size_t)m * N);
+        S yv = gld(Y + (size_t)m * N + jc);
 #pragma unroll
         for (int q = 0; q < KW; ++q) {
-          int kk = wave * KW + q;
+          const int kk = wave * KW + q;
           ax[q] = ax[q] - xv * ycf[m * KC + kk];
           ay[q] = ay[q] + xcf[m * KC + kk] * yv;
         }
@@ -400,8 +439,8 @@ hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, in
 hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int kcap_max, hipStream_t s) {
   dim3 grid((Nmax + 63) / 64, n_inst);
   size_t lds = (size_t)2 * kcap_max * KC * (cplx_ ? sizeof(cplx) : sizeof(double));
-  if (cplx_) hipLaunchKernelGGL(k_expand<cplx>, grid, dim3(64 * EXP_WAVES), lds, s, insts);
-  else hipLaunchKernelGGL(k_expand<double>, grid, dim3(64 * EXP_WAVES), lds, s, insts);
+  if (cplx_) hipLaunchKernelGGL(k_expand<cplx>, grid, dim3(64 * EXP_WAVES), lds, s, insts, kcap_max);
+  else hipLaunchKernelGGL(k_expand<double>, grid, dim3(64 * EXP_WAVES), lds, s, insts, kcap_max);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bump, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);

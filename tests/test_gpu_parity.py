@@ -137,3 +137,18 @@ def test_replay_larger_lattice():
     sim, ch, _ = _replay_case(d, 31, p=0.3)
     assert np.array_equal(sim.fields(0), ch.fields)
     assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
+
+
+def test_flush_rank_does_not_change_the_chain():
+    """The flush rank only regroups the rank-1 terms: the same Philox chain
+    with ranks 8 and 100 (set at run time) has identical fields and G to
+    FP64 rounding, and the autotuner keeps one of its candidates."""
+    d = workloads.desc(4, 3.8, 2.0, theta=(0.4, 1.1), k=8, n_stab=10, seed=91)
+    a, b = _sim([d]), _sim([d])
+    b.set_delay(100)
+    a.sweep(1, measure=False)
+    b.sweep(1, measure=False)
+    assert np.array_equal(a.fields(0), b.fields(0))
+    assert np.abs(a.green(0) - b.green(0)).max() < 1e-10
+    best, per = a.autotune([8, 32, 64], 20)
+    assert best in (8, 32, 64) and all(v > 0 for v in per.values())
