@@ -217,8 +217,11 @@ def main():
         torch.cuda.synchronize()
         print("warmup sweep %d done" % (w + 1), file=sys.stderr, flush=True)
     sim.collect(0)
-    plain = timed_leg(sim, a.steps, "plain", events=not a.no_timing)
-    dt, tim = plain["dt"], plain["tim"]
+    # throughput without per-launch events (both instance groups overlap);
+    # then one sweep with live HIP-event timing for the per-kernel rooflines
+    plain = timed_leg(sim, a.steps, "plain", events=False)
+    dt = plain["dt"]
+    tim = timed_leg(sim, 1, "profiled", events=True)["tim"] if not a.no_timing else plain["tim"]
     line = {
         "metric": "HS field updates/s + effective samples/s at L=18,\u03b2t=18 (learned vs plain)",
         "value": plain["value"],

@@ -286,6 +286,15 @@ dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k);
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 
+/* Instance groups: with 2 (the default for two or more instances) the
+ * instances are split in two contiguous groups of about equal work, group 0
+ * running on the call's stream and group 1 on a second stream of the handle,
+ * so that the latency-bound kernels of one group overlap the others'; the
+ * call's stream waits for both before the call returns.  1 runs every
+ * instance in the same launches.  Live timing (dqmc_set_timing) runs one
+ * group. */
+dqmc_status dqmc_set_streams(dqmc_handle h, int32_t groups);
+
 /* Matrix dimension N, slices M and whether G is complex, for instance inst. */
 dqmc_status dqmc_shape(dqmc_handle h, int32_t inst, int32_t* N, int32_t* M, int32_t* is_complex);
 

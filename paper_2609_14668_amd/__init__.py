@@ -92,6 +92,7 @@ _SIGS = {
     "dqmc_net_train": [_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
                        _P],
     "dqmc_set_delay": [_P, ctypes.c_int32],
+    "dqmc_set_streams": [_P, ctypes.c_int32],
     "dqmc_autotune": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
     "dqmc_status_string": [ctypes.c_int32],
     "dqmc_last_error": [_P],
@@ -412,3 +413,8 @@ class Simulation:
         return best.value, {int(k): float(t) for k, t in zip(c, ms)}
 
     autotune = dqmc_autotune
+
+    def dqmc_set_streams(self, groups):
+        self._chk(self.lib.dqmc_set_streams(self.h, int(groups)), "set_streams")
+
+    set_streams = dqmc_set_streams

@@ -199,6 +199,11 @@ struct dqmc_ctx {
   // learned multi-site moves
   int learn_P = 0, learn_m = 0;   // moves per slice visit, sites per move
   int collect_every = 0;          // store a training sample every this many downward slices (0: off)
+  // two instance groups on two streams (see run_steps)
+  int n_groups = 1;
+  int group_off[2] = {0, 0}, group_n[2] = {0, 0};
+  hipStream_t aux = nullptr;
+  hipEvent_t join_ev[2] = {nullptr, nullptr};
   NetW netw{};
   float *net_master = nullptr, *net_m = nullptr, *net_v = nullptr, *net_grad = nullptr;
   int* net_Ls = nullptr;
@@ -279,6 +284,9 @@ void drain_timing(dqmc_ctx* h) {
 struct Ctx {
   dqmc_ctx* h;
   hipStream_t s;
+  const InstDev* di;   // first instance of the group this context launches for
+  int n;               // instances in the group
+  int off;             // index of di in the handle
   hipError_t e = hipSuccess;
   void chk(hipError_t x) { if (e == hipSuccess && x != hipSuccess) e = x; }
   // Mixed precision: the wraps of G run in complex64; the B products of the
@@ -286,21 +294,21 @@ struct Ctx {
   void fft(int op, int side, int mat, int j = 0) {
     FftArgs a{op, side, mat, j, 0, 0, 0, 0};
     const bool single = h->mixed && (op == FOP_WRAP_PRE || op == FOP_WRAP_POST);
-    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
+    chk(launch_fft(di, n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
                    (int)h->fixedL.size(), h->any_generic, single, s));
   }
   void fft_explicit(int side, int mat, int pre, int tab, int post, int slice) {
     FftArgs a{FOP_EXPLICIT, side, mat, 0, pre, tab, post, slice};
-    chk(launch_fft(h->dinst, h->n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
+    chk(launch_fft(di, n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
                    (int)h->fixedL.size(), h->any_generic, h->mixed, s));
   }
   void gemm(GemmOperand A, GemmOperand B, GemmOperand C, GemmDim M, GemmDim N, GemmDim K,
             double alpha, double beta, int flags = 0) {
-    chk(launch_gemm(h->dinst, h->n, h->Nmax, h->cplx, A, B, C, M, N, K, alpha, beta, flags, s));
+    chk(launch_gemm(di, n, h->Nmax, h->cplx, A, B, C, M, N, K, alpha, beta, flags, s));
   }
   void elem(int op, int a = 0, int b = 0, int c = 0, int v = 0) {
     ElemArgs x{op, a, b, c, v};
-    chk(launch_elem(h->dinst, h->n, h->Nmax, h->cplx, x, s));
+    chk(launch_elem(di, n, h->Nmax, h->cplx, x, s));
   }
 };
 
@@ -309,28 +317,34 @@ GemmOperand opnd(int id, int op, int ra = 0, int rb = 0, int ca = 0, int cb = 0)
 }
 GemmDim dim(int a, int b, int hi = 0) { return GemmDim{a, b, hi}; }
 
-// Blocked Householder QR of MAT_QA: 16-column panels factored in registers,
-// each followed by the fused block-reflector update of the trailing columns.
+// Blocked Householder QR of MAT_QA in pairs of 16-column panels: the first
+// panel is factored in registers and applied to its partner only, the
+// partner is factored, the pair's 32-reflector compact-WY factor is formed,
+// and one block-reflector update covers the trailing columns (half the passes
+// over the trailing matrix of 16-column blocking).
 void qr_factor(Ctx& c) {
-  const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
-  for (int p = 0; p < npan; ++p) {
-    c.chk(launch_qr_panel_reg(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, c.s));
-    c.chk(launch_apply_refl(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, MAT_QA, 0, 1, c.s));
+  const int npair = (c.h->Nmax + 2 * QR_NB - 1) / (2 * QR_NB);
+  for (int q = 0; q < npair; ++q) {
+    c.chk(launch_qr_panel_reg(c.di, c.n, c.h->Nmax, c.h->cplx, 2 * q, c.s));
+    c.chk(launch_apply_refl(c.di, c.n, c.h->Nmax, c.h->cplx, 2 * q, MAT_QA, 3, 1, c.s));
+    c.chk(launch_qr_panel_reg(c.di, c.n, c.h->Nmax, c.h->cplx, 2 * q + 1, c.s));
+    c.chk(launch_pair_t(c.di, c.n, c.h->cplx, q, c.s));
+    c.chk(launch_apply_refl2(c.di, c.n, c.h->Nmax, c.h->cplx, q, MAT_QA, 0, 1, c.s));
   }
 }
 
-// target <- Q target (form Q when target = I), blocks applied last to first.
+// target <- Q target (form Q when target = I), pairs applied last to first.
 void apply_q(Ctx& c, int target) {
-  const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
-  for (int p = npan - 1; p >= 0; --p)
-    c.chk(launch_apply_refl(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, target, 1, 0, c.s));
+  const int npair = (c.h->Nmax + 2 * QR_NB - 1) / (2 * QR_NB);
+  for (int q = npair - 1; q >= 0; --q)
+    c.chk(launch_apply_refl2(c.di, c.n, c.h->Nmax, c.h->cplx, q, target, 1, 0, c.s));
 }
 
-// target <- Q^H target, blocks applied first to last, all columns.
+// target <- Q^H target, pairs applied first to last, all columns.
 void apply_qh(Ctx& c, int target) {
-  const int npan = (c.h->Nmax + QR_NB - 1) / QR_NB;
-  for (int p = 0; p < npan; ++p)
-    c.chk(launch_apply_refl(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, p, target, 2, 1, c.s));
+  const int npair = (c.h->Nmax + 2 * QR_NB - 1) / (2 * QR_NB);
+  for (int q = 0; q < npair; ++q)
+    c.chk(launch_apply_refl2(c.di, c.n, c.h->Nmax, c.h->cplx, q, target, 2, 1, c.s));
 }
 
 // MAT_W3 <- R^{-1} MAT_W3 with R the upper triangle of MAT_QA.
@@ -344,7 +358,7 @@ void upper_solve(Ctx& c) {
              opnd(MAT_W3, 0, 1, -TRSM_ROWS * (b + 1), 0, 0),
              dim(1, -TRSM_ROWS * b, TRSM_ROWS), dim(1, 0), dim(0, TRSM_ROWS * b), -1.0, 1.0);
     }
-    c.chk(launch_trsm_diag(c.h->dinst, c.h->n, c.h->Nmax, c.h->cplx, b, c.s));
+    c.chk(launch_trsm_diag(c.di, c.n, c.h->Nmax, c.h->cplx, b, c.s));
   }
 }
 
@@ -355,11 +369,11 @@ void stabilise(Ctx& c, bool measure) {
   c.elem(EO_RESET_CHAIN);
   for (int j = 0; j < h->n_stab; ++j) c.fft(FOP_STAB_B, 0, MAT_UW, j);
   c.elem(EO_SCALE_COLS, 0, 0, MAT_UW, VEC_DW);
-  c.chk(launch_colnorm_sort(h->dinst, h->n, h->Nmax, h->cplx, MAT_UW, c.s));
+  c.chk(launch_colnorm_sort(c.di, c.n, h->Nmax, h->cplx, MAT_UW, c.s));
   c.elem(EO_GATHER_COLS, MAT_UW, 0, MAT_QA);
   c.elem(EO_GATHER_ROWS, MAT_TW, 0, MAT_W3);
   qr_factor(c);
-  c.chk(launch_diag_abs(h->dinst, h->n, h->Nmax, h->cplx, c.s));
+  c.chk(launch_diag_abs(c.di, c.n, h->Nmax, h->cplx, c.s));
   c.gemm(opnd(MAT_QA, 0), opnd(MAT_W3, 0), opnd(MAT_TW, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0,
          GF_A_UPPER);
   c.elem(EO_SCALE_ROWS_INV, 0, 0, MAT_TW, VEC_DW);
@@ -384,9 +398,9 @@ void stabilise(Ctx& c, bool measure) {
       c.elem(EO_COPY, MAT_G, 0, MAT_GS);
       c.fft(FOP_HALF, 0, MAT_GS);
       c.fft(FOP_HALF, 1, MAT_GS);
-      c.chk(launch_measure(h->dinst, h->n, h->Nmax, h->cplx, MAT_GS, c.s));
+      c.chk(launch_measure(c.di, c.n, h->Nmax, h->cplx, MAT_GS, c.s));
     } else {
-      c.chk(launch_measure(h->dinst, h->n, h->Nmax, h->cplx, MAT_G, c.s));
+      c.chk(launch_measure(c.di, c.n, h->Nmax, h->cplx, MAT_G, c.s));
     }
   }
 }
@@ -410,12 +424,16 @@ void window_logits(Ctx& c, float* z_base) {
   const Plan& p = h->plan;
   char* b = h->ws;
   const int ncm = h->Nmax / 2;
-  ConvGeom g1{0, h->net_Ls, 7, 5, 1, (long long)p.lwin_stride[0], (long long)p.lwin_stride[1]};
-  c.chk(launch_conv(CONV_F1, b + p.lwin[0], b + p.lwin[1], h->netw, g1, h->n, ncm, c.s));
-  ConvGeom g2{0, h->net_Ls, 5, 3, 1, (long long)p.lwin_stride[1], (long long)p.lwin_stride[2]};
-  c.chk(launch_conv(CONV_F2, b + p.lwin[1], b + p.lwin[2], h->netw, g2, h->n, ncm, c.s));
-  ConvGeom g3{0, h->net_Ls, 3, 1, 1, (long long)p.lwin_stride[2], (long long)p.z_stride};
-  c.chk(launch_conv(CONV_F3, b + p.lwin[2], z_base, h->netw, g3, h->n, ncm, c.s));
+  char* w0 = b + p.lwin[0] + 2 * p.lwin_stride[0] * c.off;
+  char* w1 = b + p.lwin[1] + 2 * p.lwin_stride[1] * c.off;
+  char* w2 = b + p.lwin[2] + 2 * p.lwin_stride[2] * c.off;
+  const int* Ls = h->net_Ls + c.off;
+  ConvGeom g1{0, Ls, 7, 5, 1, (long long)p.lwin_stride[0], (long long)p.lwin_stride[1]};
+  c.chk(launch_conv(CONV_F1, w0, w1, h->netw, g1, c.n, ncm, c.s));
+  ConvGeom g2{0, Ls, 5, 3, 1, (long long)p.lwin_stride[1], (long long)p.lwin_stride[2]};
+  c.chk(launch_conv(CONV_F2, w1, w2, h->netw, g2, c.n, ncm, c.s));
+  ConvGeom g3{0, Ls, 3, 1, 1, (long long)p.lwin_stride[2], (long long)p.z_stride};
+  c.chk(launch_conv(CONV_F3, w2, z_base + p.z_stride * c.off, h->netw, g3, c.n, ncm, c.s));
 }
 
 // learn_P learned m-site moves on the current slice after its single-site
@@ -429,17 +447,17 @@ void learned_moves(Ctx& c) {
   float* zc = (float*)(h->ws + p.zcur);
   float* zp = (float*)(h->ws + p.zprop);
   const int ncm = h->Nmax / 2;
-  c.chk(launch_learn_window(h->dinst, h->n, ncm, 0, c.s));
+  c.chk(launch_learn_window(c.di, c.n, ncm, 0, c.s));
   window_logits(c, zc);
   for (int j = 0; j < h->learn_P; ++j) {
-    c.chk(launch_learn_propose(h->dinst, h->n, h->cplx, j, h->learn_m, c.s));
-    c.chk(launch_learn_window(h->dinst, h->n, ncm, 1, c.s));
+    c.chk(launch_learn_propose(c.di, c.n, h->cplx, j, h->learn_m, c.s));
+    c.chk(launch_learn_window(c.di, c.n, ncm, 1, c.s));
     window_logits(c, zp);
-    c.chk(launch_learn_decide(h->dinst, h->n, h->cplx, j, c.s));
-    c.chk(launch_expand(h->dinst, h->n, h->Nmax, h->cplx, h->kcap_max, c.s));
+    c.chk(launch_learn_decide(c.di, c.n, h->cplx, j, c.s));
+    c.chk(launch_expand(c.di, c.n, h->Nmax, h->cplx, h->kcap_max, c.s));
   }
-  c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
-  c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
+  c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
+  c.chk(launch_flush_done(c.di, c.n, 1, c.s));
 }
 
 void step(Ctx& c, int64_t s, bool measure, int replay) {
@@ -457,26 +475,26 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
   for (int w = 0; w < nwin; ++w) {
     {
       TimedScope t(h, c.s, DQMC_T_WINDOW);
-      c.chk(launch_window(h->dinst, h->n, h->cplx, WINDOW, replay, c.s));
+      c.chk(launch_window(c.di, c.n, h->cplx, WINDOW, replay, c.s));
     }
     {
       TimedScope t(h, c.s, DQMC_T_EXPAND);
-      c.chk(launch_expand(h->dinst, h->n, h->Nmax, h->cplx, h->kcap_max, c.s));
+      c.chk(launch_expand(c.di, c.n, h->Nmax, h->cplx, h->kcap_max, c.s));
     }
     {
       TimedScope t(h, c.s, DQMC_T_FLUSH);
-      c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_FULL, c.s));
+      c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, GF_IF_FULL, c.s));
     }
-    c.chk(launch_flush_done(h->dinst, h->n, 0, c.s));
+    c.chk(launch_flush_done(c.di, c.n, 0, c.s));
   }
   {
     TimedScope t(h, c.s, DQMC_T_FLUSH);
-    c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
+    c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
   }
-  c.chk(launch_flush_done(h->dinst, h->n, 1, c.s));
+  c.chk(launch_flush_done(c.di, c.n, 1, c.s));
   if (h->collect_every > 0)
-    c.chk(launch_collect(h->dinst, h->n, (int8_t*)(h->ws + h->plan.ring_win), (float*)(h->ws + h->plan.ring_tg),
-                         h->plan.ring_cap, h->Nmax, h->collect_every, c.s));
+    c.chk(launch_collect(c.di, c.n, c.off, h->n, (int8_t*)(h->ws + h->plan.ring_win),
+                         (float*)(h->ws + h->plan.ring_tg), h->plan.ring_cap, h->Nmax, h->collect_every, c.s));
   if (h->learn_P > 0 && !replay) {
     TimedScope t(h, c.s, DQMC_T_LEARN);
     learned_moves(c);
@@ -494,7 +512,7 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
     TimedScope t(h, c.s, DQMC_T_STAB);
     stabilise(c, measure);
   }
-  c.chk(launch_advance(h->dinst, h->n, c.s));
+  c.chk(launch_advance(c.di, c.n, c.s));
 }
 
 dqmc_status upload_insts(dqmc_ctx* h, hipStream_t s) {
@@ -505,7 +523,7 @@ dqmc_status upload_insts(dqmc_ctx* h, hipStream_t s) {
 // Build the UDV stack and G(0) from the current fields: a downward pass
 // without updates (only the chain steps), then the working chain is reset.
 dqmc_status init_green(dqmc_ctx* h, hipStream_t s) {
-  Ctx c{h, s};
+  Ctx c{h, s, h->dinst, h->n, 0};
   c.chk(launch_init_state(h->dinst, h->n, 1, s));
   c.elem(EO_STACK_IDENTITY);
   c.elem(EO_IDENTITY, 0, 0, MAT_UW);
@@ -581,6 +599,23 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
   h->ws = (char*)dev_ws;
   h->ws_bytes = bytes;
   h->stream = (hipStream_t)stream;
+  if (n >= 2) {
+    // contiguous split with the per-step work (~N^2 per instance) halved
+    double tot = 0, acc = 0;
+    for (int i = 0; i < n; ++i) tot += 4.0 * d[i].L * d[i].L * d[i].L * d[i].L;
+    int cut = 1;
+    double best = 1e300;
+    for (int i = 1; i < n; ++i) {
+      acc += 4.0 * d[i - 1].L * d[i - 1].L * d[i - 1].L * d[i - 1].L;
+      if (std::fabs(acc - tot / 2) < best) { best = std::fabs(acc - tot / 2); cut = i; }
+    }
+    h->group_off[0] = 0; h->group_n[0] = cut;
+    h->group_off[1] = cut; h->group_n[1] = n - cut;
+    if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&h->join_ev[0], hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&h->join_ev[1], hipEventDisableTiming) == hipSuccess)
+      h->n_groups = 2;
+  }
   h->dinst = (InstDev*)(h->ws + p.insts_off);
   const size_t ss = p.cplx ? 16 : 8;
   hipStream_t s = h->stream;
@@ -720,6 +755,12 @@ dqmc_status dqmc_destroy(dqmc_handle h) {
   if (!h) return DQMC_EINVAL;
   hipStreamSynchronize(h->stream);
   for (auto e : h->ev_pool) hipEventDestroy(e);
+  if (h->aux) {
+    hipStreamSynchronize(h->aux);
+    hipStreamDestroy(h->aux);
+  }
+  for (auto e : h->join_ev)
+    if (e) hipEventDestroy(e);
   delete h;
   return DQMC_OK;
 }
@@ -755,12 +796,41 @@ dqmc_status dqmc_get_fields(dqmc_handle h, int32_t inst, int8_t* host_x) {
 
 // steps is a multiple of n_stab, so the stabilisation points stay aligned
 // across calls.
+// With two instance groups, group 0 runs on the caller's stream and group 1
+// on the handle's second stream; the groups' launches interleave on the host
+// so that the latency-bound kernels of one group (window scan, expand, QR
+// panels) overlap the bandwidth- and matrix-core-bound kernels of the other.
+// The second stream starts after the caller's prior work and the caller's
+// stream waits for it at the end.  With live timing on, one group is used so
+// that every timed launch covers all instances.
 static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay) {
-  Ctx c{h, s};
-  for (int64_t k = 0; k < steps; ++k) {
-    step(c, k, measure != 0, replay);
-    if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c.e));
+  const int groups = (h->timing || h->n_groups < 2 || !h->aux) ? 1 : h->n_groups;
+  if (groups == 1) {
+    Ctx c{h, s, h->dinst, h->n, 0};
+    for (int64_t k = 0; k < steps; ++k) {
+      step(c, k, measure != 0, replay);
+      if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c.e));
+    }
+    return DQMC_OK;
   }
+  HIPCHK(h, hipEventRecord(h->join_ev[0], s));
+  HIPCHK(h, hipStreamWaitEvent(h->aux, h->join_ev[0], 0));
+  Ctx c0{h, s, h->dinst + h->group_off[0], h->group_n[0], h->group_off[0]};
+  Ctx c1{h, h->aux, h->dinst + h->group_off[1], h->group_n[1], h->group_off[1]};
+  for (int64_t k = 0; k < steps; ++k) {
+    step(c0, k, measure != 0, replay);
+    step(c1, k, measure != 0, replay);
+    if (c0.e != hipSuccess || c1.e != hipSuccess)
+      return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c0.e != hipSuccess ? c0.e : c1.e));
+  }
+  HIPCHK(h, hipEventRecord(h->join_ev[1], h->aux));
+  HIPCHK(h, hipStreamWaitEvent(s, h->join_ev[1], 0));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_streams(dqmc_handle h, int32_t groups) {
+  if (!h || groups < 1 || groups > 2) return DQMC_EINVAL;
+  h->n_groups = (groups == 2 && h->n >= 2 && h->aux) ? 2 : 1;
   return DQMC_OK;
 }
 
@@ -838,7 +908,7 @@ dqmc_status dqmc_replay(dqmc_handle h, const uint8_t* dev_bits, int64_t bits_per
   }
   dqmc_status st = upload_insts(h, s);
   if (st == DQMC_OK) {
-    Ctx c{h, s};
+    Ctx c{h, s, h->dinst, h->n, 0};
     c.chk(launch_replay_reset(h->dinst, h->n, s));
     st = c.e == hipSuccess ? run_sweeps(h, n_sweeps, measure, s, 1) : fail(h, DQMC_EHIP, "replay reset");
   }
@@ -894,7 +964,7 @@ dqmc_status dqmc_wrap(dqmc_handle h, int32_t dir, int32_t slice, void* stream) {
   if (!h || (dir != 0 && dir != 1)) return DQMC_EINVAL;
   for (auto& d : h->hd)
     if (slice < 1 || slice > d.M) return fail(h, DQMC_EINVAL, "slice out of range");
-  Ctx c{h, pick(h, stream)};
+  Ctx c{h, pick(h, stream), h->dinst, h->n, 0};
   if (dir == 0) {
     c.fft_explicit(0, MAT_G, 0, TAB_P, +1, slice);
     c.fft_explicit(1, MAT_G, 0, TAB_M, -1, slice);
@@ -915,7 +985,7 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X, c
   HIPCHK(h, hipMemcpyAsync(d.mat[MAT_X], host_X, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(d.mat[MAT_Y], host_Y, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync((char*)d.st + offsetof(InstState, fill), &k, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  Ctx c{h, s};
+  Ctx c{h, s, h->dinst, h->n, 0};
   c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, s));
   c.chk(launch_flush_done(h->dinst, h->n, 1, s));
   if (c.e != hipSuccess) return fail(h, DQMC_EHIP, hipGetErrorString(c.e));
@@ -953,7 +1023,7 @@ dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out) {
 dqmc_status dqmc_reset_obs(dqmc_handle h) {
   if (!h) return DQMC_EINVAL;
   for (auto& d : h->hd) HIPCHK(h, hipMemsetAsync(d.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), h->stream));
-  Ctx c{h, h->stream};
+  Ctx c{h, h->stream, h->dinst, h->n, 0};
   c.chk(launch_reset_counters(h->dinst, h->n, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return DQMC_OK;

@@ -40,7 +40,7 @@ template <>
 __device__ __forceinline__ void split<cplx>(cplx v, double& re, double& im) { re = v.x; im = v.y; }
 
 template <typename S>
-__global__ void __launch_bounds__(GEMM_THREADS)
+__global__ void __launch_bounds__(GEMM_THREADS, 2)
 k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOperand C,
        GemmDim Md, GemmDim Nd, GemmDim Kd, double alpha, double beta, int flags) {
   constexpr bool CX = ST<S>::is_complex;
@@ -131,11 +131,18 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
     const int m0 = (tile % tm) * BM, n0 = (tile / tm) * BN;
     // accumulators hold transposed 16x16 blocks: operands are fed as (B, A) so
     // that a lane owns 4 columns of one row and stores coalesce along columns
-    d4 acc_r[2][2], acc_i[2][2];
+    // Complex products use three real products (Gauss): P1 = Br Ar (acc_r),
+    // P2 = Bi Ai (acc_i), P3 = (Br + Bi)(Ar + Ai) (acc_p); re = P1 - P2,
+    // im = P3 - P1 - P2.
+    d4 acc_r[2][2], acc_i[2][2], acc_p[CX ? 2 : 1][CX ? 2 : 1];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) { acc_r[i][j] = d4{0, 0, 0, 0}; acc_i[i][j] = d4{0, 0, 0, 0}; }
+      for (int j = 0; j < 2; ++j) {
+        acc_r[i][j] = d4{0, 0, 0, 0};
+        acc_i[i][j] = d4{0, 0, 0, 0};
+        if constexpr (CX) acc_p[i][j] = d4{0, 0, 0, 0};
+      }
 
     // For C = alpha (op(A) op(B)) + beta C the accumulators start at
     // (beta/alpha) C, loaded before the K loop so that the read of C overlaps
@@ -154,7 +161,7 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
             double re, im;
             split<S>(gld(pc + min(gi, M - 1) + (size_t)min(gj, NC - 1) * ld), re, im);
             acc_r[ti][tj][r] = in ? cscale * re : 0.0;
-            acc_i[ti][tj][r] = in ? cscale * im : 0.0;
+            if constexpr (CX) acc_p[ti][tj][r] = in ? cscale * (re + im) : 0.0;
           }
     }
     // upper-triangular op(A): chunks with k < m0 contribute nothing
@@ -165,6 +172,7 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
       __syncthreads();
       if (k0 + BK < K) load_chunk(m0, n0, k0 + BK);
       const int ksn = min(BK, K - k0 + 3) / 4;
+#pragma unroll 1
       for (int ks = 0; ks < ksn; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         double ar[2], br[2], ai[2], bi[2];
@@ -183,9 +191,8 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
           for (int tj = 0; tj < 2; ++tj) {
             acc_r[ti][tj] = mfma(br[tj], ar[ti], acc_r[ti][tj]);
             if constexpr (CX) {
-              acc_r[ti][tj] = mfma(-bi[tj], ai[ti], acc_r[ti][tj]);
-              acc_i[ti][tj] = mfma(bi[tj], ar[ti], acc_i[ti][tj]);
-              acc_i[ti][tj] = mfma(br[tj], ai[ti], acc_i[ti][tj]);
+              acc_i[ti][tj] = mfma(bi[tj], ai[ti], acc_i[ti][tj]);
+              acc_p[ti][tj] = mfma(br[tj] + bi[tj], ar[ti] + ai[ti], acc_p[ti][tj]);
             }
           }
       }
@@ -205,7 +212,8 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
           if (gi < M && gj < NC) {
             S* cp = pc + gi + (size_t)gj * ld;
             if constexpr (CX) {
-              cplx v = cmake(alpha * acc_r[ti][tj][r], alpha * acc_i[ti][tj][r]);
+              const double p1 = acc_r[ti][tj][r], p2 = acc_i[ti][tj][r];
+              cplx v = cmake(alpha * (p1 - p2), alpha * (acc_p[ti][tj][r] - p1 - p2));
               if (beta != 0.0 && cscale == 0.0) v = v + beta * (*cp);
               *cp = v;
             } else {
@@ -245,10 +253,13 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
   const int lr = lane & 15, lk = lane >> 4;
   for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
     const int i0 = (blk % nb32) * 32, j0 = (blk / nb32) * 32;
-    d4 ar_[2][2], ai_[2][2];   // [ti][tj] accumulators (transposed blocks)
-    // start from -G (alpha = -1): acc = X Y - G, G_new = -acc.  Every load
-    // reads a clamped, valid address and out-of-range values are zeroed
-    // afterwards, so that no load sits behind a branch (and its wait).
+    // [ti][tj] accumulators (transposed blocks).  Complex products use three
+    // real products (Gauss): P1 = Yr Xr, P2 = Yi Xi, P3 = (Yr + Yi)(Xr + Xi),
+    // re = P1 - P2, im = P3 - P1 - P2.  The accumulators start from -G
+    // (P1 at -Re G, P3 at -Re G - Im G) so that acc = X Y - G, G_new = -acc.
+    // Every load reads a clamped, valid address and out-of-range values are
+    // zeroed afterwards, so that no load sits behind a branch (and its wait).
+    d4 ar_[2][2], ai_[2][2], ap_[CX ? 2 : 1][CX ? 2 : 1];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -260,7 +271,8 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
           double re, im;
           split<S>(gld(G + min(gi, N - 1) + (size_t)min(gj, N - 1) * N), re, im);
           ar_[ti][tj][r] = in ? -re : 0.0;
-          ai_[ti][tj][r] = in ? -im : 0.0;
+          ai_[ti][tj][r] = 0.0;
+          if constexpr (CX) ap_[ti][tj][r] = in ? -re - im : 0.0;
         }
     auto frag = [&](int k, double (&xr)[2], double (&xi)[2], double (&yr)[2], double (&yi)[2]) {
       const int kk = k + lk;
@@ -277,37 +289,32 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
         yr[t] = yin ? c : 0.0; yi[t] = yin ? e : 0.0;
       }
     };
-    // fragments two k-steps ahead; independent accumulators interleaved so
+    // fragments one k-step ahead; independent accumulators interleaved so
     // that no MFMA waits on the one just issued
-    double xr[2], xi[2], yr[2], yi[2], nxr[2], nxi[2], nyr[2], nyi[2];
+    double xr[2], xi[2], yr[2], yi[2];
     frag(0, xr, xi, yr, yi);
-    frag(4, nxr, nxi, nyr, nyi);
     for (int k = 0; k < K; k += 4) {
-      double mxr[2], mxi[2], myr[2], myi[2];
-      frag(k + 8, mxr, mxi, myr, myi);
+      double nxr[2], nxi[2], nyr[2], nyi[2];
+      frag(k + 4, nxr, nxi, nyr, nyi);
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj) ar_[ti][tj] = mfma(yr[tj], xr[ti], ar_[ti][tj]);
       if constexpr (CX) {
+        double xs[2], ys[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) { xs[t] = xr[t] + xi[t]; ys[t] = yr[t] + yi[t]; }
 #pragma unroll
         for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma(yi[tj], xr[ti], ai_[ti][tj]);
+          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma(yi[tj], xi[ti], ai_[ti][tj]);
 #pragma unroll
         for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < 2; ++tj) ar_[ti][tj] = mfma(-yi[tj], xi[ti], ar_[ti][tj]);
-#pragma unroll
-        for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-          for (int tj = 0; tj < 2; ++tj) ai_[ti][tj] = mfma(yr[tj], xi[ti], ai_[ti][tj]);
+          for (int tj = 0; tj < 2; ++tj) ap_[ti][tj] = mfma(ys[tj], xs[ti], ap_[ti][tj]);
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        xr[t] = nxr[t]; xi[t] = nxi[t]; yr[t] = nyr[t]; yi[t] = nyi[t];
-        nxr[t] = mxr[t]; nxi[t] = mxi[t]; nyr[t] = myr[t]; nyi[t] = myi[t];
-      }
+      for (int t = 0; t < 2; ++t) { xr[t] = nxr[t]; xi[t] = nxi[t]; yr[t] = nyr[t]; yi[t] = nyi[t]; }
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -317,8 +324,12 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
         for (int r = 0; r < 4; ++r) {
           int gi = i0 + ti * 16 + lr, gj = j0 + tj * 16 + lk + 4 * r;
           if (gi < N && gj < N) {
-            if constexpr (CX) G[gi + (size_t)gj * N] = cmake(-ar_[ti][tj][r], -ai_[ti][tj][r]);
-            else G[gi + (size_t)gj * N] = -ar_[ti][tj][r];
+            if constexpr (CX) {
+              const double p1 = ar_[ti][tj][r], p2 = ai_[ti][tj][r];
+              gst(G + gi + (size_t)gj * N, cmake(p2 - p1, p1 + p2 - ap_[ti][tj][r]));
+            } else {
+              gst(G + gi + (size_t)gj * N, -ar_[ti][tj][r]);
+            }
           }
         }
   }

@@ -88,6 +88,11 @@ hipError_t launch_qr_panel(const InstDev* insts, int n_inst, bool cplx_, int p, 
 hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, hipStream_t s);
 // target <- (I - V op(T) V^H) target for panel p; cols 0: trailing [j0+16, N),
 // 1: [j0, N), 2: all; use_th: op(T) = T^H (apply Q^H) else T (apply Q).
+// Pairs of panels (32 reflectors): combined compact-WY factor, and the
+// block-reflector update with it (cols 0: [j0+32, N), 1: [j0, N), 2: all).
+hipError_t launch_pair_t(const InstDev* insts, int n_inst, bool cplx_, int q, hipStream_t s);
+hipError_t launch_apply_refl2(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int q, int target, int cols,
+                              int use_th, hipStream_t s);
 hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, int target, int cols,
                              int use_th, hipStream_t s);
 hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
@@ -163,9 +168,9 @@ hipError_t launch_net_loss_window(const float* z, const float* tgs, long long tg
 // Training samples: every `every`-th slice l of the downward pass (l % every
 // == 0), after the slice's single-site updates, each instance stores its
 // window of slices l-3 .. l+3 and the targets of slice l in ring slot
-// (count * n_inst + inst) % ring_cap.
-hipError_t launch_collect(const InstDev* insts, int n_inst, int8_t* ring_win, float* ring_tg, int ring_cap,
-                          int n_max, int every, hipStream_t s);
+// (count * n_total + inst) % ring_cap; insts points at instance `off`.
+hipError_t launch_collect(const InstDev* insts, int n_inst, int off, int n_total, int8_t* ring_win, float* ring_tg,
+                          int ring_cap, int n_max, int every, hipStream_t s);
 hipError_t launch_adam(float* master, const float* g, float* m, float* v, int n, float lr, int step,
                        hipStream_t s);
 // Sampler side: 7-slice input windows around the current slice (flip: with

@@ -381,17 +381,17 @@ __global__ void __launch_bounds__(256) k_net_loss_window(const float* __restrict
 }
 
 // Training sample of the current slice (downward pass, l % every == 0).
-__global__ void k_collect(const InstDev* __restrict__ insts, int n_inst, int8_t* __restrict__ ring_win,
+__global__ void k_collect(const InstDev* __restrict__ insts, int off, int n_total, int8_t* __restrict__ ring_win,
                           float* __restrict__ ring_tg, int ring_cap, int n_max, int every) {
-  const int inst = blockIdx.y;
-  const InstDev& d = insts[inst];
+  const int inst = off + blockIdx.y;   // index in the handle
+  const InstDev& d = insts[blockIdx.y];
   InstState* st = d.st;
   if (st->idle || st->init_mode) return;
   const int M = d.M, N = d.N;
   if (sched_is_up(st->phase, M)) return;
   const int l = sched_slice(st->phase, M);
   if (l % every) return;
-  const int64_t slot = (st->collect_n * n_inst + inst) % ring_cap;
+  const int64_t slot = (st->collect_n * n_total + inst) % ring_cap;
   int8_t* w = ring_win + (size_t)slot * 7 * n_max;
   float* tg = ring_tg + (size_t)slot * n_max;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 8 * N; e += gridDim.x * blockDim.x) {
@@ -845,10 +845,11 @@ hipError_t launch_net_loss_window(const float* z, const float* tgs, long long tg
   return hipGetLastError();
 }
 
-hipError_t launch_collect(const InstDev* insts, int n_inst, int8_t* ring_win, float* ring_tg, int ring_cap,
-                          int n_max, int every, hipStream_t s) {
+hipError_t launch_collect(const InstDev* insts, int n_inst, int off, int n_total, int8_t* ring_win, float* ring_tg,
+                          int ring_cap, int n_max, int every, hipStream_t s) {
   dim3 grid((8 * n_max + 255) / 256, n_inst);
-  hipLaunchKernelGGL(k_collect, grid, dim3(256), 0, s, insts, n_inst, ring_win, ring_tg, ring_cap, n_max, every);
+  hipLaunchKernelGGL(k_collect, grid, dim3(256), 0, s, insts, off, n_total, ring_win, ring_tg, ring_cap, n_max,
+                     every);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_collect_bump, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst, every);

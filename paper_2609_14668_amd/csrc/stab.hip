@@ -13,6 +13,8 @@
 // Dense products run on the MFMA GEMM; this file holds the panel
 // factorisation, the triangular block solve, the pre-pivot sort and the
 // element-wise steps.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -622,9 +624,10 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
   const int j0 = p * NBR;
   if (j0 >= N) return;
   const int nbe = min(NBR, N - j0);
-  const int cbeg = cols == 0 ? j0 + NBR : (cols == 1 ? j0 : 0);
+  const int cbeg = (cols == 0 || cols == 3) ? j0 + NBR : (cols == 1 ? j0 : 0);
+  const int cend = cols == 3 ? min(N, j0 + 2 * NBR) : N;   // 3: the partner panel of a pair only
   const int c0 = cbeg + blockIdx.x * AR_CT;
-  if (c0 >= N) return;
+  if (c0 >= cend) return;
   const S* V = matp<S>(d, MAT_V);
   const S* TB = matp<S>(d, MAT_TB);
   S* C = matp<S>(d, target);
@@ -651,7 +654,7 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int x = tid + 256 * q, r = x % RB, cc = x / RB;
-      cv[q] = gld(C + min(i0 + r, N - 1) + (size_t)min(c0 + cc, N - 1) * N);
+      cv[q] = gld(C + min(i0 + r, N - 1) + (size_t)min(c0 + cc, cend - 1) * N);
     }
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -665,7 +668,7 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const int x = tid + 256 * q, r = x % RB, cc = x / RB;
-      const bool in = i0 + r < N && c0 + cc < N;
+      const bool in = i0 + r < N && c0 + cc < cend;
       double re, im;
       split_s<S>(cv[q], re, im);
       Cr[r][cc] = in ? re : 0.0;
@@ -701,21 +704,22 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
     Tt[r][c] = use_th ? conjg(t) : t;
   }
   __syncthreads();
-  // ---- W' = op(T) W (16 x 64), written over Ws after a barrier
+  // ---- W' = op(T) W (16 x 64), written over Ws after a barrier; thread:
+  // row m = tid % 16, columns tid / 16 + 16 u
   S wp[4];
-#pragma unroll 1
-  for (int u = 0; u < 4; ++u) {
-    const int x = tid + 256 * u, m = x % NBR, c = x / NBR;
-    S acc = ST<S>::zero();
-#pragma unroll 4
-    for (int k = 0; k < NBR; ++k) acc = acc + Tt[m][k] * Ws[k][c];
-    wp[u] = acc;
-  }
-  __syncthreads();
+  {
+    const int m = tid % NBR, cb = tid / NBR;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    int x = tid + 256 * u, m = x % NBR, c = x / NBR;
-    Ws[m][c] = wp[u];
+    for (int u = 0; u < 4; ++u) wp[u] = ST<S>::zero();
+#pragma unroll 2
+    for (int k = 0; k < NBR; ++k) {
+      const S t = Tt[m][k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wp[u] = wp[u] + t * Ws[k][cb + 16 * u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Ws[m][cb + 16 * u] = wp[u];
   }
   __syncthreads();
   // ---- C -= V W': wave w updates columns 16w..16w+15, 16 rows at a time.
@@ -730,7 +734,7 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
     const int i = i0 + lr, ic = min(i, N - 1);
     S cl[4], vl[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, N - 1) * N);
+    for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, cend - 1) * N);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) vl[ks] = gld(V + ic + (size_t)(j0 + min(ks * 4 + lk, nbe - 1)) * N);
     d4 cr, ci;
@@ -758,6 +762,228 @@ __global__ void __launch_bounds__(256) k_apply_refl(const InstDev* __restrict__ 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int c = cw + lk + 4 * r;
+      if (i < N && c < cend) {
+        if constexpr (CX) gst(C + i + (size_t)c * N, cmake(-cr[r], -ci[r]));
+        else gst(C + i + (size_t)c * N, -cr[r]);
+      }
+    }
+  }
+}
+
+// Compact-WY factor of a pair of panels (2q, 2q+1), 32 reflectors:
+//   T = [[T1, T12], [0, T2]],  T12 = -T1 (V1^H V2) T2,
+// written over the two 16 x 16 blocks in MAT_TB (rows j0 .. j0+31, columns
+// 0 .. 31).  V2 is read as zero above its own panel's first row.
+constexpr int PR = 2 * NBR;
+template <typename S>
+__global__ void __launch_bounds__(256) k_pair_t(const InstDev* __restrict__ insts, int q) {
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  const int j0 = q * PR, j1 = j0 + NBR;
+  if (j0 >= N) return;
+  const int nb1 = min(NBR, N - j0), nb2 = max(0, min(NBR, N - j1));
+  const S* V = matp<S>(d, MAT_V);
+  S* TB = matp<S>(d, MAT_TB);
+  const int tid = threadIdx.x;
+  __shared__ S v1s[64][NBR + 1], v2s[64][NBR + 1];
+  __shared__ S Mm[NBR][NBR + 1], T1[NBR][NBR + 1], T2[NBR][NBR + 1], Pm[NBR][NBR + 1];
+  const int a = tid / NBR, b = tid % NBR;   // one entry of the 16 x 16 products per thread
+  S acc = ST<S>::zero();
+  if (nb2 > 0) {
+    for (int i0 = j1; i0 < N; i0 += 64) {
+      for (int x = tid; x < 64 * NBR; x += 256) {
+        const int r = x % 64, c = x / 64, i = i0 + r;
+        const bool in = i < N;
+        const S x1 = gld(V + min(i, N - 1) + (size_t)(j0 + min(c, nb1 - 1)) * N);
+        const S x2 = gld(V + min(i, N - 1) + (size_t)(j1 + min(c, nb2 - 1)) * N);
+        v1s[r][c] = (in && c < nb1) ? x1 : ST<S>::zero();
+        v2s[r][c] = (in && c < nb2) ? x2 : ST<S>::zero();
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int r = 0; r < 64; ++r) acc = acc + conjg(v1s[r][a]) * v2s[r][b];
+      __syncthreads();
+    }
+  }
+  Mm[a][b] = acc;
+  T1[a][b] = (a < nb1 && b < nb1) ? TB[(j0 + a) + (size_t)b * N] : ST<S>::zero();
+  T2[a][b] = (a < nb2 && b < nb2) ? TB[(j1 + a) + (size_t)b * N] : ST<S>::zero();
+  __syncthreads();
+  S p = ST<S>::zero();   // P = M12 T2
+  for (int k = 0; k < NBR; ++k) p = p + Mm[a][k] * T2[k][b];
+  Pm[a][b] = p;
+  __syncthreads();
+  S t12 = ST<S>::zero();   // T12 = -T1 P
+  for (int k = 0; k < NBR; ++k) t12 = t12 - T1[a][k] * Pm[k][b];
+  // only entries inside the N x N matrix (N may be below 32)
+  if (j0 + a < N && NBR + b < N) TB[(j0 + a) + (size_t)(NBR + b) * N] = (a < nb1 && b < nb2) ? t12 : ST<S>::zero();
+  if (j1 + a < N) {
+    if (NBR + b < N) TB[(j1 + a) + (size_t)(NBR + b) * N] = T2[a][b];
+    if (b < N) TB[(j1 + a) + (size_t)b * N] = ST<S>::zero();
+  }
+}
+
+// C <- (I - V op(T) V^H) C with the 32 reflectors of pair q (columns
+// j0 .. j0+31 of MAT_V, T from k_pair_t), rows [j0, N):
+//   W = V^H C (32 x 64 tile per workgroup), W' = op(T) W, C -= V W'.
+// cols: 0 -> [j0 + 32, N), 1 -> [j0, N), 2 -> [0, N).  The second panel's
+// vectors are read as zero above their own first row.
+template <typename S>
+__global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__ insts, int q, int target,
+                                                     int cols, int use_th) {
+  constexpr bool CX = ST<S>::is_complex;
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  const int j0 = q * PR;
+  if (j0 >= N) return;
+  const int nbe = min(PR, N - j0);
+  const int cbeg = cols == 0 ? j0 + PR : (cols == 1 ? j0 : 0);
+  const int c0 = cbeg + blockIdx.x * AR_CT;
+  if (c0 >= N) return;
+  const S* V = matp<S>(d, MAT_V);
+  const S* TB = matp<S>(d, MAT_TB);
+  S* C = matp<S>(d, target);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int RB = 32;
+  __shared__ double Vr[RB][PR + 1], Vi[CX ? RB : 1][PR + 1];
+  // C staging planes during W = V^H C; then W / W' (PR x AR_CT) in the same bytes
+  constexpr int CPL = RB * (AR_CT + 1);
+  constexpr int CBYTES = (CX ? 2 : 1) * CPL * 8 > PR * (AR_CT + 1) * (int)sizeof(S)
+                             ? (CX ? 2 : 1) * CPL * 8 : PR * (AR_CT + 1) * (int)sizeof(S);
+  __shared__ __attribute__((aligned(16))) char cbuf[CBYTES];
+  double* Cr = reinterpret_cast<double*>(cbuf);
+  double* Ci = Cr + CPL;
+  S* Ws = reinterpret_cast<S*>(cbuf);
+  __shared__ S Tt[PR][PR + 1];
+  constexpr int NV = RB * PR / 256, NC = RB * AR_CT / 256;
+  d4 wr[2], wi[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) { wr[t] = d4{0, 0, 0, 0}; wi[t] = d4{0, 0, 0, 0}; }
+#pragma unroll 1
+  for (int i0 = j0; i0 < N; i0 += RB) {
+    S vv[NV], cv[NC];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int x = tid + 256 * u, r = x % RB, m = x / RB;
+      vv[u] = gld(V + min(i0 + r, N - 1) + (size_t)(j0 + min(m, nbe - 1)) * N);
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int x = tid + 256 * u, r = x % RB, cc = x / RB;
+      cv[u] = gld(C + min(i0 + r, N - 1) + (size_t)min(c0 + cc, N - 1) * N);
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int x = tid + 256 * u, r = x % RB, m = x / RB;
+      const int i = i0 + r;
+      const bool in = i < N && m < nbe && i >= j0 + (m / NBR) * NBR;
+      double re, im;
+      split_s<S>(vv[u], re, im);
+      Vr[r][m] = in ? re : 0.0;
+      if constexpr (CX) Vi[r][m] = in ? im : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int x = tid + 256 * u, r = x % RB, cc = x / RB;
+      const bool in = i0 + r < N && c0 + cc < N;
+      double re, im;
+      split_s<S>(cv[u], re, im);
+      Cr[r * (AR_CT + 1) + cc] = in ? re : 0.0;
+      if constexpr (CX) Ci[r * (AR_CT + 1) + cc] = in ? im : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < RB / 4; ++ks) {
+      const int k = ks * 4 + lk;
+      const double br = Cr[k * (AR_CT + 1) + wave * 16 + lr];
+      const double bi = CX ? Ci[k * (AR_CT + 1) + wave * 16 + lr] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        // A = V^H: A[m][k] = conj(V[k][m]); B = C: B[k][c]
+        const double ar = Vr[k][t * 16 + lr];
+        wr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, wr[t], 0, 0, 0);
+        if constexpr (CX) {
+          const double ai = -Vi[k][t * 16 + lr];
+          wr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, wr[t], 0, 0, 0);
+          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, wi[t], 0, 0, 0);
+          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, wi[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // W[m = 16 t + lk + 4 r][c = 16 wave + lr] (the C planes are free now)
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = t * 16 + lk + 4 * r, c = wave * 16 + lr;
+      if constexpr (CX) Ws[m * (AR_CT + 1) + c] = cmake(wr[t][r], wi[t][r]);
+      else Ws[m * (AR_CT + 1) + c] = wr[t][r];
+    }
+  for (int x = tid; x < PR * PR; x += 256) {
+    const int r = x % PR, c = x / PR;
+    const int tr = use_th ? c : r, tc = use_th ? r : c;
+    S t = (tr < nbe && tc < nbe) ? TB[(j0 + tr) + (size_t)tc * N] : ST<S>::zero();
+    Tt[r][c] = use_th ? conjg(t) : t;
+  }
+  __syncthreads();
+  // W' = op(T) W: 32 x 64; thread: row m = tid % 32, columns tid / 32 + 8 u
+  S wp[8];
+  {
+    const int m = tid % PR, cb = tid / PR;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) wp[u] = ST<S>::zero();
+#pragma unroll 2
+    for (int k = 0; k < PR; ++k) {
+      const S t = Tt[m][k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wp[u] = wp[u] + t * Ws[k * (AR_CT + 1) + cb + 8 * u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Ws[m * (AR_CT + 1) + cb + 8 * u] = wp[u];
+  }
+  __syncthreads();
+  // C -= V W': wave w updates columns 16w .. 16w+15, 16 rows at a time, K = 32
+  const int cw = c0 + wave * 16;
+#pragma unroll 1
+  for (int i0 = j0; i0 < N; i0 += 16) {
+    const int i = i0 + lr, ic = min(i, N - 1);
+    S cl[4], vl[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, N - 1) * N);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) vl[ks] = gld(V + ic + (size_t)(j0 + min(ks * 4 + lk, nbe - 1)) * N);
+    d4 cr, ci;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double re, im;
+      split_s<S>(cl[r], re, im);
+      cr[r] = -re;
+      ci[r] = -im;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int m = ks * 4 + lk;
+      double vr, vi;
+      split_s<S>(vl[ks], vr, vi);
+      if (!(i < N && m < nbe && i >= j0 + (m / NBR) * NBR)) { vr = 0.0; vi = 0.0; }
+      double br, bi;
+      split_s<S>(Ws[m * (AR_CT + 1) + wave * 16 + lr], br, bi);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, cr, 0, 0, 0);
+      if constexpr (CX) {
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi, vi, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vr, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vi, ci, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = cw + lk + 4 * r;
       if (i < N && c < N) {
         if constexpr (CX) gst(C + i + (size_t)c * N, cmake(-cr[r], -ci[r]));
         else gst(C + i + (size_t)c * N, -cr[r]);
@@ -879,11 +1105,29 @@ hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool 
   return hipGetLastError();
 }
 
+hipError_t launch_pair_t(const InstDev* insts, int n_inst, bool cplx_, int q, hipStream_t s) {
+  if (cplx_) hipLaunchKernelGGL(k_pair_t<cplx>, dim3(1, n_inst), dim3(256), 0, s, insts, q);
+  else hipLaunchKernelGGL(k_pair_t<double>, dim3(1, n_inst), dim3(256), 0, s, insts, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_refl2(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int q, int target, int cols,
+                              int use_th, hipStream_t s) {
+  int j0 = q * PR;
+  int cbeg = cols == 0 ? j0 + PR : (cols == 1 ? j0 : 0);
+  int ncol = Nmax - cbeg;
+  if (ncol <= 0) return hipSuccess;
+  dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_apply_refl2<cplx>, grid, dim3(256), 0, s, insts, q, target, cols, use_th);
+  else hipLaunchKernelGGL(k_apply_refl2<double>, grid, dim3(256), 0, s, insts, q, target, cols, use_th);
+  return hipGetLastError();
+}
+
 hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, int target, int cols,
                              int use_th, hipStream_t s) {
   int j0 = p * NBR;
-  int cbeg = cols == 0 ? j0 + NBR : (cols == 1 ? j0 : 0);
-  int ncol = Nmax - cbeg;
+  int cbeg = (cols == 0 || cols == 3) ? j0 + NBR : (cols == 1 ? j0 : 0);
+  int ncol = (cols == 3 ? std::min(Nmax, j0 + 2 * NBR) : Nmax) - cbeg;
   if (ncol <= 0) return hipSuccess;
   dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst);
   if (cplx_) hipLaunchKernelGGL(k_apply_refl<cplx>, grid, dim3(256), 0, s, insts, p, target, cols, use_th);
