@@ -208,8 +208,10 @@ def main():
         nst = descs[0]["n_stab"]
         cand = [k for k in (16, 24, 32, 48, 64, 96, 128)]
         best, per = sim.autotune(cand, 2 * nst)
-        tuned = {"k": best, "ms_per_step": {str(k): round(v, 3) for k, v in per.items()}}
-        print("autotuned flush rank k=%d: %s" % (best, tuned["ms_per_step"]), file=sys.stderr, flush=True)
+        tuned = {"k": best[0], "flush_kernel": ("direct", "tiled")[best[1]],
+                 "ms_per_step": {"%d/%s" % (k, ("direct", "tiled")[v]): round(t, 3) for (k, v), t in per.items()}}
+        print("autotuned flush k=%d %s: %s" % (best[0], tuned["flush_kernel"], tuned["ms_per_step"]),
+              file=sys.stderr, flush=True)
     for w in range(a.warmup):
         if learned and w == a.warmup - 1:
             sim.collect(8)     # training windows from the last warm-up sweep
@@ -248,7 +250,8 @@ def main():
     fl = tim["flush"]
     if fl["ms"] > 0:
         ach = tim["flush_flops"] / (fl["ms"] * 1e-3)
-        line["roofline"] = {"bound": "mfma", "kernel": "k_flush_direct (G -= X Y)", "achieved": ach / 1e12,
+        fk = "k_gemm, 64x64 LDS tiles" if (tuned and tuned["flush_kernel"] == "tiled") else "k_flush_direct"
+        line["roofline"] = {"bound": "mfma", "kernel": "%s (flush G -= X Y)" % fk, "achieved": ach / 1e12,
                             "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
                             "traffic": None, "launches": fl["launches"],
                             "avg_launch_us": 1e3 * fl["ms"] / max(fl["launches"], 1)}

@@ -278,11 +278,17 @@ dqmc_status dqmc_net_train(dqmc_handle h, void* dev_ws, size_t bytes, int32_t st
  * are applied, never the sequence of G's or decisions.  Synchronises. */
 dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k);
 
-/* Autotuner of the flush rank: for each of the n_cand candidate ranks, run
- * `steps` slice steps (a multiple of n_stab; the chains advance as in a
- * sweep, without estimators), time them with HIP events, and keep the
- * fastest (written to *best; ms_per_step[q], nullable, gets the time per
- * step of candidate q).  Synchronises. */
+/* Flush kernel: 0 = one wave per 32 x 32 block of G with fragments read
+ * straight from memory, 1 = 64 x 64 tiles per workgroup with X and Y staged
+ * through LDS.  Mixed precision always uses its FP32 kernel. */
+dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant);
+
+/* Autotuner of the flush rank and kernel: for each of the n_cand candidate
+ * ranks and each flush kernel, run `steps` slice steps (a multiple of
+ * n_stab; the chains advance as in a sweep, without estimators), time them
+ * with HIP events, and keep the fastest pair (best[0] = rank, best[1] =
+ * kernel; ms_per_step[2 q + v], nullable, gets the time per step of rank q
+ * with kernel v, 0 where not tried).  Synchronises. */
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 

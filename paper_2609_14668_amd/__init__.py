@@ -93,7 +93,8 @@ _SIGS = {
                        _P],
     "dqmc_set_delay": [_P, ctypes.c_int32],
     "dqmc_set_streams": [_P, ctypes.c_int32],
-    "dqmc_autotune": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P],
+    "dqmc_autotune": [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P],
+    "dqmc_set_flush_kernel": [_P, ctypes.c_int32],
     "dqmc_status_string": [ctypes.c_int32],
     "dqmc_last_error": [_P],
 }
@@ -403,14 +404,20 @@ class Simulation:
     set_delay = dqmc_set_delay
 
     def dqmc_autotune(self, candidates, steps):
-        """Time `steps` slice steps per candidate flush rank and keep the
-        fastest; returns (best, {k: ms per step})."""
+        """Time `steps` slice steps per candidate flush rank and flush kernel
+        and keep the fastest; returns ((k, kernel), {(k, kernel): ms per step})."""
         c = np.ascontiguousarray(candidates, dtype=np.int32)
-        ms = np.zeros(c.size, dtype=np.float64)
-        best = ctypes.c_int32()
-        self._chk(self.lib.dqmc_autotune(self.h, int(steps), c.ctypes.data, c.size, ctypes.byref(best),
+        ms = np.zeros(2 * c.size, dtype=np.float64)
+        best = np.zeros(2, dtype=np.int32)
+        self._chk(self.lib.dqmc_autotune(self.h, int(steps), c.ctypes.data, c.size, best.ctypes.data,
                                          ms.ctypes.data), "autotune")
-        return best.value, {int(k): float(t) for k, t in zip(c, ms)}
+        per = {(int(k), v): float(ms[2 * q + v]) for q, k in enumerate(c) for v in (0, 1) if ms[2 * q + v] > 0}
+        return (int(best[0]), int(best[1])), per
+
+    def dqmc_set_flush_kernel(self, variant):
+        self._chk(self.lib.dqmc_set_flush_kernel(self.h, int(variant)), "set_flush_kernel")
+
+    set_flush_kernel = dqmc_set_flush_kernel
 
     autotune = dqmc_autotune
 

@@ -199,6 +199,7 @@ struct dqmc_ctx {
   // learned multi-site moves
   int learn_P = 0, learn_m = 0;   // moves per slice visit, sites per move
   int collect_every = 0;          // store a training sample every this many downward slices (0: off)
+  int flush_variant = 0;          // 0: wave-per-block flush, 1: LDS-tiled GEMM (FP64 only)
   // two instance groups on two streams (see run_steps)
   int n_groups = 1;
   int group_off[2] = {0, 0}, group_n[2] = {0, 0};
@@ -417,6 +418,19 @@ double wrap_pass_bytes(dqmc_ctx* h, int64_t s, bool up) {
   return b;
 }
 
+// G <- G - X Y for the instances whose pending rank passes the flag's test:
+// FP32 matrix cores for mixed precision, else the LDS-free wave-per-block
+// kernel or the LDS-tiled GEMM (chosen by the autotuner).
+void flush(Ctx& c, int flags) {
+  dqmc_ctx* h = c.h;
+  if (h->mixed || h->flush_variant == 0) {
+    c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, flags, c.s));
+  } else {
+    c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
+           GF_K_FILL | flags);
+  }
+}
+
 // Logits of the current slice of every instance from the 7-slice window in
 // lwin[0]: three valid-in-time convolutions (7 -> 5 -> 3 -> 1 slices).
 void window_logits(Ctx& c, float* z_base) {
@@ -456,7 +470,7 @@ void learned_moves(Ctx& c) {
     c.chk(launch_learn_decide(c.di, c.n, h->cplx, j, c.s));
     c.chk(launch_expand(c.di, c.n, h->Nmax, h->cplx, h->kcap_max, c.s));
   }
-  c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
+  flush(c, GF_IF_ANY);
   c.chk(launch_flush_done(c.di, c.n, 1, c.s));
 }
 
@@ -483,13 +497,13 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
     }
     {
       TimedScope t(h, c.s, DQMC_T_FLUSH);
-      c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, GF_IF_FULL, c.s));
+      flush(c, GF_IF_FULL);
     }
     c.chk(launch_flush_done(c.di, c.n, 0, c.s));
   }
   {
     TimedScope t(h, c.s, DQMC_T_FLUSH);
-    c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, c.s));
+    flush(c, GF_IF_ANY);
   }
   c.chk(launch_flush_done(c.di, c.n, 1, c.s));
   if (h->collect_every > 0)
@@ -853,6 +867,12 @@ dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k) {
   return DQMC_OK;
 }
 
+dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant) {
+  if (!h || variant < 0 || variant > 1) return DQMC_EINVAL;
+  h->flush_variant = h->mixed ? 0 : variant;
+  return DQMC_OK;
+}
+
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step) {
   if (!h || !cand || n_cand < 1 || steps < 1 || steps % h->n_stab != 0) return DQMC_EINVAL;
@@ -863,29 +883,34 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
   const bool timing = h->timing;
   h->timing = false;
   double best_ms = 1e300;
-  int32_t bk = h->hd[0].kflush;
+  int32_t bk = h->hd[0].kflush, bv = h->flush_variant;
+  const int nvar = h->mixed ? 1 : 2;
   dqmc_status st = DQMC_OK;
   for (int q = 0; q < n_cand && st == DQMC_OK; ++q) {
     st = dqmc_set_delay(h, cand[q]);
-    if (st != DQMC_OK) break;
-    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(h, DQMC_EHIP, "autotune event"); break; }
-    st = run_steps(h, steps, 0, s, 0);
-    if (st != DQMC_OK) break;
-    float ms = 0.f;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      st = fail(h, DQMC_EHIP, "autotune timing");
-      break;
+    for (int v = 0; v < 2 && st == DQMC_OK; ++v) {
+      if (v >= nvar) { if (ms_per_step) ms_per_step[2 * q + v] = 0.0; continue; }
+      h->flush_variant = v;
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(h, DQMC_EHIP, "autotune event"); break; }
+      st = run_steps(h, steps, 0, s, 0);
+      if (st != DQMC_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(h, DQMC_EHIP, "autotune timing");
+        break;
+      }
+      const double per = ms / steps;
+      if (ms_per_step) ms_per_step[2 * q + v] = per;
+      if (per < best_ms) { best_ms = per; bk = cand[q]; bv = v; }
     }
-    const double per = ms / steps;
-    if (ms_per_step) ms_per_step[q] = per;
-    if (per < best_ms) { best_ms = per; bk = cand[q]; }
   }
   h->timing = timing;
+  h->flush_variant = bv;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st != DQMC_OK) return st;
-  if (best) *best = bk;
+  if (best) { best[0] = bk; best[1] = bv; }
   return dqmc_set_delay(h, bk);
 }
 

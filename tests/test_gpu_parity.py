@@ -151,4 +151,10 @@ def test_flush_rank_does_not_change_the_chain():
     assert np.array_equal(a.fields(0), b.fields(0))
     assert np.abs(a.green(0) - b.green(0)).max() < 1e-10
     best, per = a.autotune([8, 32, 64], 20)
-    assert best in (8, 32, 64) and all(v > 0 for v in per.values())
+    assert best[0] in (8, 32, 64) and best[1] in (0, 1) and all(v > 0 for v in per.values())
+    # the tiled flush kernel gives the same chain
+    c = _sim([d])
+    c.set_flush_kernel(1)
+    c.sweep(1, measure=False)
+    assert np.array_equal(c.fields(0), b.fields(0))
+    assert np.abs(c.green(0) - b.green(0)).max() < 1e-10
