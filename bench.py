@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--proposal", default="both", choices=("plain", "learned", "both"))
     ap.add_argument("--no-timing", action="store_true", help="no per-launch HIP events (for counter runs)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the workload's flush rank")
+    ap.add_argument("--flush-kernel", choices=("direct", "tiled"), default=None,
+                    help="with --no-autotune: the flush kernel to use")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -204,6 +206,9 @@ def main():
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
     learned = a.proposal in ("learned", "both")
     tuned = None
+    if a.flush_kernel:
+        sim.set_flush_kernel(1 if a.flush_kernel == "tiled" else 0)
+        tuned = {"k": a.k, "flush_kernel": a.flush_kernel, "ms_per_step": None}
     if a.k is None and not a.no_autotune:
         nst = descs[0]["n_stab"]
         cand = [k for k in (16, 24, 32, 48, 64, 96, 128)]
@@ -250,7 +255,7 @@ def main():
     fl = tim["flush"]
     if fl["ms"] > 0:
         ach = tim["flush_flops"] / (fl["ms"] * 1e-3)
-        fk = "k_gemm, 64x64 LDS tiles" if (tuned and tuned["flush_kernel"] == "tiled") else "k_flush_direct"
+        fk = "k_gemm<S, 1>, 64x64 LDS tiles" if (tuned and tuned["flush_kernel"] == "tiled") else "k_flush_direct"
         line["roofline"] = {"bound": "mfma", "kernel": "%s (flush G -= X Y)" % fk, "achieved": ach / 1e12,
                             "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
                             "traffic": None, "launches": fl["launches"],

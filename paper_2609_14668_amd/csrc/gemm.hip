@@ -39,7 +39,9 @@ __device__ __forceinline__ void split<double>(double v, double& re, double& im) 
 template <>
 __device__ __forceinline__ void split<cplx>(cplx v, double& re, double& im) { re = v.x; im = v.y; }
 
-template <typename S>
+// ROLE only separates the flush instantiation (1) from the stabilisation
+// products (0) in profiles; the code is the same.
+template <typename S, int ROLE>
 __global__ void __launch_bounds__(GEMM_THREADS, 2)
 k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOperand C,
        GemmDim Md, GemmDim Nd, GemmDim Kd, double alpha, double beta, int flags) {
@@ -443,8 +445,14 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
   if (cap < 8) cap = 8;
   int gx = tiles < cap ? tiles : cap;
   dim3 grid(gx, n_inst);
-  if (cplx_) hipLaunchKernelGGL(k_gemm<cplx>, grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
-  else hipLaunchKernelGGL(k_gemm<double>, grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+  const bool fl = flags & GF_K_FILL;
+  if (cplx_) {
+    if (fl) hipLaunchKernelGGL((k_gemm<cplx, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+    else hipLaunchKernelGGL((k_gemm<cplx, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+  } else {
+    if (fl) hipLaunchKernelGGL((k_gemm<double, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+    else hipLaunchKernelGGL((k_gemm<double, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+  }
   return hipGetLastError();
 }
 
