@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the workload's flush rank")
     ap.add_argument("--flush-kernel", choices=("direct", "tiled"), default=None,
                     help="with --no-autotune: the flush kernel to use")
+    ap.add_argument("--groups", type=int, choices=(1, 2), default=2,
+                    help="instance groups on separate streams (1: every launch covers all instances)")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -205,6 +207,7 @@ def main():
     print("workload %s: %d instances, Nmax %d, Mmax %d, complex %s" % (a.workload, n, Nmax, Mmax,
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
     learned = a.proposal in ("learned", "both")
+    sim.set_streams(a.groups)
     tuned = None
     if a.flush_kernel:
         sim.set_flush_kernel(1 if a.flush_kernel == "tiled" else 0)
