@@ -24,6 +24,25 @@ PEAK_FP64 = 78.6e12     # MI355X dense FP64 (vector and matrix), FLOP/s
 PEAK_HBM = 8.0e12       # MI355X HBM3E, B/s
 
 
+def measured_traffic(workload, k, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on this workload and flush rank and the kernel's source
+    is unchanged since (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    src = {"k_flush_direct": "gemm.hip", "k_gemm<S, 1>": "gemm.hip"}.get(kernel)
+    if not src or not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, "paper_2609_14668_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    for line in open(path):
+        m = re.match(r"traffic k=(\d+) (.+) ([0-9.e+]+) ([0-9a-f]{40})$", line.strip())
+        if m and int(m.group(1)) == k and m.group(2) == kernel and m.group(4) == sha:
+            return float(m.group(3))
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,10 +277,13 @@ def main():
     fl = tim["flush"]
     if fl["ms"] > 0:
         ach = tim["flush_flops"] / (fl["ms"] * 1e-3)
-        fk = "k_gemm<S, 1>, 64x64 LDS tiles" if (tuned and tuned["flush_kernel"] == "tiled") else "k_flush_direct"
-        line["roofline"] = {"bound": "mfma", "kernel": "%s (flush G -= X Y)" % fk, "achieved": ach / 1e12,
-                            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP64,
-                            "traffic": None, "launches": fl["launches"],
+        fk = "k_gemm<S, 1>" if (tuned and tuned["flush_kernel"] == "tiled") else "k_flush_direct"
+        kk = tuned["k"] if tuned and tuned.get("k") else descs[0]["n_delay"]
+        line["roofline"] = {"bound": "mfma", "kernel": fk, "what": "rank-k flush G -= X Y (k=%d)" % kk,
+                            "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                            "frac": ach / PEAK_FP64,
+                            "traffic": measured_traffic(a.workload, kk, fk), "traffic_unit": "bytes per launch",
+                            "launches": fl["launches"],
                             "avg_launch_us": 1e3 * fl["ms"] / max(fl["launches"], 1)}
     wr = tim["wrap"]
     if wr["ms"] > 0:
@@ -272,7 +294,9 @@ def main():
                                  "avg_launch_us": 1e3 * wr["ms"] / max(wr["launches"], 1)}
     line["time_split_ms"] = {k: round(tim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab")}
     if descs[0]["precision"] == 1 and "roofline" in line:
-        line["roofline"]["kernel"] = "k_flush_f32 (G -= X Y, FP32 MFMA)"
+        line["roofline"]["kernel"] = "k_flush_f32"
+        line["roofline"]["what"] = "rank-k flush G -= X Y with FP32 matrix cores"
+        line["roofline"]["traffic"] = None
         line["roofline"]["peak"] = 157.3  # FP32 matrix peak for the FP32 flush
         line["roofline"]["frac"] = line["roofline"]["achieved"] / 157.3
     if descs[0]["precision"] == 1:
