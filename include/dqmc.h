@@ -301,6 +301,13 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
  * group. */
 dqmc_status dqmc_set_streams(dqmc_handle h, int32_t groups);
 
+/* HIP graphs (default on): sweeps replay one captured block of n_stab slice
+ * steps (captured on first use and again after a setting that changes the
+ * launches: proposals, collection, flush kernel or rank, groups, replay,
+ * measure).  Live timing and step counts that are not whole blocks run
+ * eagerly.  The captured block contains kernel launches only. */
+dqmc_status dqmc_set_graphs(dqmc_handle h, int32_t on);
+
 /* Matrix dimension N, slices M and whether G is complex, for instance inst. */
 dqmc_status dqmc_shape(dqmc_handle h, int32_t inst, int32_t* N, int32_t* M, int32_t* is_complex);
 

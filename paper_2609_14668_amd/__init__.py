@@ -93,6 +93,7 @@ _SIGS = {
                        _P],
     "dqmc_set_delay": [_P, ctypes.c_int32],
     "dqmc_set_streams": [_P, ctypes.c_int32],
+    "dqmc_set_graphs": [_P, ctypes.c_int32],
     "dqmc_autotune": [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P],
     "dqmc_set_flush_kernel": [_P, ctypes.c_int32],
     "dqmc_status_string": [ctypes.c_int32],
@@ -425,3 +426,8 @@ class Simulation:
         self._chk(self.lib.dqmc_set_streams(self.h, int(groups)), "set_streams")
 
     set_streams = dqmc_set_streams
+
+    def dqmc_set_graphs(self, on):
+        self._chk(self.lib.dqmc_set_graphs(self.h, int(bool(on))), "set_graphs")
+
+    set_graphs = dqmc_set_graphs

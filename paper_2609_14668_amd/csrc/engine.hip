@@ -205,6 +205,11 @@ struct dqmc_ctx {
   int group_off[2] = {0, 0}, group_n[2] = {0, 0};
   hipStream_t aux = nullptr;
   hipEvent_t join_ev[2] = {nullptr, nullptr};
+  // captured stabilisation block (see run_steps)
+  bool use_graphs = true;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;   // capture stream (the caller's may be the legacy null stream)
+  std::vector<int> gkey;
   NetW netw{};
   float *net_master = nullptr, *net_m = nullptr, *net_v = nullptr, *net_grad = nullptr;
   int* net_Ls = nullptr;
@@ -630,6 +635,10 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
         hipEventCreateWithFlags(&h->join_ev[1], hipEventDisableTiming) == hipSuccess)
       h->n_groups = 2;
   }
+  if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+    h->cap = nullptr;
+    h->use_graphs = false;
+  }
   h->dinst = (InstDev*)(h->ws + p.insts_off);
   const size_t ss = p.cplx ? 16 : 8;
   hipStream_t s = h->stream;
@@ -769,6 +778,8 @@ dqmc_status dqmc_destroy(dqmc_handle h) {
   if (!h) return DQMC_EINVAL;
   hipStreamSynchronize(h->stream);
   for (auto e : h->ev_pool) hipEventDestroy(e);
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->cap) hipStreamDestroy(h->cap);
   if (h->aux) {
     hipStreamSynchronize(h->aux);
     hipStreamDestroy(h->aux);
@@ -817,28 +828,78 @@ dqmc_status dqmc_get_fields(dqmc_handle h, int32_t inst, int8_t* host_x) {
 // The second stream starts after the caller's prior work and the caller's
 // stream waits for it at the end.  With live timing on, one group is used so
 // that every timed launch covers all instances.
-static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay) {
-  const int groups = (h->timing || h->n_groups < 2 || !h->aux) ? 1 : h->n_groups;
+static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay,
+                              int groups) {
   if (groups == 1) {
     Ctx c{h, s, h->dinst, h->n, 0};
-    for (int64_t k = 0; k < steps; ++k) {
-      step(c, k, measure != 0, replay);
-      if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c.e));
-    }
-    return DQMC_OK;
+    for (int64_t k = 0; k < steps && c.e == hipSuccess; ++k) step(c, k, measure != 0, replay);
+    return c.e;
   }
-  HIPCHK(h, hipEventRecord(h->join_ev[0], s));
-  HIPCHK(h, hipStreamWaitEvent(h->aux, h->join_ev[0], 0));
+  hipError_t e;
+  if ((e = hipEventRecord(h->join_ev[0], s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(h->aux, h->join_ev[0], 0)) != hipSuccess) return e;
   Ctx c0{h, s, h->dinst + h->group_off[0], h->group_n[0], h->group_off[0]};
   Ctx c1{h, h->aux, h->dinst + h->group_off[1], h->group_n[1], h->group_off[1]};
-  for (int64_t k = 0; k < steps; ++k) {
+  for (int64_t k = 0; k < steps && c0.e == hipSuccess && c1.e == hipSuccess; ++k) {
     step(c0, k, measure != 0, replay);
     step(c1, k, measure != 0, replay);
-    if (c0.e != hipSuccess || c1.e != hipSuccess)
-      return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(c0.e != hipSuccess ? c0.e : c1.e));
   }
-  HIPCHK(h, hipEventRecord(h->join_ev[1], h->aux));
-  HIPCHK(h, hipStreamWaitEvent(s, h->join_ev[1], 0));
+  if (c0.e != hipSuccess) return c0.e;
+  if (c1.e != hipSuccess) return c1.e;
+  if ((e = hipEventRecord(h->join_ev[1], h->aux)) != hipSuccess) return e;
+  return hipStreamWaitEvent(s, h->join_ev[1], 0);
+}
+
+// Everything a captured block of n_stab steps depends on besides device
+// memory: the launches of a step are fixed by these.
+static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, int groups) {
+  return {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant, h->kcap_max};
+}
+
+// Sweeps are replayed as HIP graphs of one stabilisation block (n_stab slice
+// steps: the launch sequence is the same for every block of every sweep, all
+// state that changes lives in device memory), captured on first use.  The
+// second instance group's stream joins the capture through an event, so the
+// graph keeps the overlap of the two groups.  The eager path serves live
+// timing and step counts that are not a whole number of blocks.
+static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay) {
+  const int groups = (h->timing || h->n_groups < 2 || !h->aux) ? 1 : h->n_groups;
+  if (!h->use_graphs || !h->cap || h->timing || steps % h->n_stab != 0) {
+    hipError_t e = issue_steps(h, steps, measure, s, replay, groups);
+    if (e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
+    return DQMC_OK;
+  }
+  const std::vector<int> key = graph_key(h, measure, replay, groups);
+  if (!h->gexec || h->gkey != key) {
+    if (h->gexec) {
+      hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    // captured on the handle's own stream: the legacy null stream cannot be
+    // captured, and recording does not execute, so no ordering with s is needed
+    HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = issue_steps(h, h->n_stab, measure, h->cap, replay, groups);
+    hipError_t e2 = hipStreamEndCapture(h->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return fail(h, DQMC_EHIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      h->gexec = nullptr;
+      return fail(h, DQMC_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    h->gkey = key;
+  }
+  for (int64_t b = 0; b < steps / h->n_stab; ++b) HIPCHK(h, hipGraphLaunch(h->gexec, s));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_graphs(dqmc_handle h, int32_t on) {
+  if (!h) return DQMC_EINVAL;
+  h->use_graphs = on != 0;
   return DQMC_OK;
 }
 
@@ -891,6 +952,8 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
     for (int v = 0; v < 2 && st == DQMC_OK; ++v) {
       if (v >= nvar) { if (ms_per_step) ms_per_step[2 * q + v] = 0.0; continue; }
       h->flush_variant = v;
+      st = run_steps(h, h->n_stab, 0, s, 0);   // untimed: captures this configuration's graph
+      if (st != DQMC_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) { st = fail(h, DQMC_EHIP, "autotune event"); break; }
       st = run_steps(h, steps, 0, s, 0);
       if (st != DQMC_OK) break;

@@ -158,3 +158,25 @@ def test_flush_rank_does_not_change_the_chain():
     c.sweep(1, measure=False)
     assert np.array_equal(c.fields(0), b.fields(0))
     assert np.abs(c.green(0) - b.green(0)).max() < 1e-10
+
+
+@pytest.mark.parametrize("groups", [1, 2])
+def test_graph_replay_matches_eager(groups):
+    """Sweeps replayed from the captured block equal eager sweeps (fields,
+    G, estimators), over several replays with eager work in between, with
+    and without the second instance group."""
+    descs = [workloads.desc(4, 3.8, 2.0, theta=(0.4 * i, 1.1), k=16, n_stab=10, seed=120 + i) for i in range(3)]
+    a, b = _sim(descs), _sim(descs)
+    a.set_graphs(False)
+    for sim in (a, b):
+        sim.set_streams(groups)
+    for _ in range(3):
+        a.sweep(1, measure=True)
+        b.sweep(1, measure=True)
+        for i in range(3):
+            assert a.stats(i)["accepted"] == b.stats(i)["accepted"]
+    for i in range(3):
+        assert np.array_equal(a.fields(i), b.fields(i))
+        assert np.abs(a.green(i) - b.green(i)).max() < 1e-12
+        oa, ob = a.measure(i), b.measure(i)
+        assert oa["n_meas"] == ob["n_meas"] and abs(oa["D"] - ob["D"]) < 1e-12
