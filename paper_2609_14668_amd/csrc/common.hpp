@@ -170,6 +170,10 @@ enum ObsId : int {
   OBS_PHASE_RE, OBS_PHASE_IM, OBS_COUNT
 };
 
+// Rows of N elements in an instance's buffer for the partial products of a
+// row-split block-reflector update (chunks x reflectors <= RSPLIT_ROWS).
+constexpr int RSPLIT_ROWS = 256;
+
 // Device-visible descriptor of one instance.
 struct InstDev {
   int32_t L, N, Nc, M;
@@ -203,6 +207,7 @@ struct InstDev {
   float* zcur;              // logits of slice l at the current fields (Nc x 16)
   float* zprop;             // logits of slice l at the proposed fields
   double* wcoef;            // window: c_k, then x/y window vectors
+  char* rsplit;             // row-split reflector updates: RSPLIT_ROWS x N partial products
   InstState* st;
   double* obs;              // running sums [OBS_COUNT]
   double* series;           // per-sweep means [max_series x OBS_COUNT]

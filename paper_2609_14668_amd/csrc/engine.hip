@@ -50,7 +50,7 @@ bool is_twisted(const dqmc_instance_desc& d) {
 }
 
 struct Offs {
-  size_t st, obs, series, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn;
+  size_t st, obs, series, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn, rsplit;
   size_t vec[VEC_COUNT];
   size_t mat[MAT_COUNT];
   size_t stackU, stackT, stackD;
@@ -123,6 +123,7 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.wcoef = o; o = al(o + ss * (WINDOW + 2 * WINDOW * WINDOW));
     f.targets = o; o = al(o + sizeof(float) * (size_t)M * N);
     f.learn = o; o = al(o + sizeof(LearnState));
+    f.rsplit = o; o = al(o + ss * (size_t)RSPLIT_ROWS * N);
     for (int v = 0; v < VEC_COUNT; ++v) { f.vec[v] = o; o = al(o + sizeof(double) * 2 * N); }
     const size_t mb = ss * (size_t)N * N;
     for (int m = 0; m < MAT_COUNT; ++m) {
@@ -353,19 +354,30 @@ void apply_qh(Ctx& c, int target) {
     c.chk(launch_apply_refl2(c.di, c.n, c.h->Nmax, c.h->cplx, q, target, 2, 1, c.s));
 }
 
-// MAT_W3 <- R^{-1} MAT_W3 with R the upper triangle of MAT_QA.
+// MAT_W3 <- R^{-1} MAT_W3 with R the upper triangle of MAT_QA, recursively
+// over 32-row blocks counted from the bottom (block b = rows
+// [N - 32 (b + 1), N - 32 b), clipped at 0 for smaller instances of a batch):
+// solve the lower half, subtract its contribution from the upper half with
+// one GEMM, solve the upper half.  The large updates come first and fill the
+// GPU even for a single instance.
+void upper_solve_blocks(Ctx& c, int b0, int b1) {
+  if (b1 - b0 == 1) {
+    c.chk(launch_trsm_diag(c.di, c.n, c.h->Nmax, c.h->cplx, b0, c.s));
+    return;
+  }
+  const int mid = (b0 + b1) / 2, T = TRSM_ROWS;
+  upper_solve_blocks(c, b0, mid);
+  // W3[top rows] -= R[top rows, lower cols] W3[lower rows];
+  // top = [N - T b1, N - T mid), lower = [N - T mid, N - T b0)
+  c.gemm(opnd(MAT_QA, 0, 1, -T * b1, 1, -T * mid), opnd(MAT_W3, 0, 1, -T * mid, 0, 0),
+         opnd(MAT_W3, 0, 1, -T * b1, 0, 0), dim(1, -T * mid, T * (b1 - mid)), dim(1, 0),
+         dim(1, -T * b0, T * (mid - b0)), -1.0, 1.0);
+  upper_solve_blocks(c, mid, b1);
+}
+
 void upper_solve(Ctx& c) {
   const int nblk = (c.h->Nmax + TRSM_ROWS - 1) / TRSM_ROWS;
-  for (int b = 0; b < nblk; ++b) {
-    if (b > 0) {
-      // rows [i0, i1), i1 = N - 32 b: W3[i0:i1, :] -= R[i0:i1, i1:] W3[i1:, :]
-      c.gemm(opnd(MAT_QA, 0, 1, -TRSM_ROWS * (b + 1), 1, -TRSM_ROWS * b),
-             opnd(MAT_W3, 0, 1, -TRSM_ROWS * b, 0, 0),
-             opnd(MAT_W3, 0, 1, -TRSM_ROWS * (b + 1), 0, 0),
-             dim(1, -TRSM_ROWS * b, TRSM_ROWS), dim(1, 0), dim(0, TRSM_ROWS * b), -1.0, 1.0);
-    }
-    c.chk(launch_trsm_diag(c.di, c.n, c.h->Nmax, c.h->cplx, b, c.s));
-  }
+  upper_solve_blocks(c, 0, nblk);
 }
 
 // One checkpoint: advance the working UDV chain by n_stab slices, recompute
@@ -684,6 +696,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.zcur = (float*)(b + p.zcur) + p.z_stride * i;
     dv.zprop = (float*)(b + p.zprop) + p.z_stride * i;
     dv.wcoef = (double*)(b + f.wcoef);
+    dv.rsplit = b + f.rsplit;
     dv.st = (InstState*)(b + f.st);
     dv.obs = (double*)(b + f.obs);
     dv.series = (double*)(b + f.series);

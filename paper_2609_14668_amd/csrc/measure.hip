@@ -23,6 +23,60 @@ __device__ __forceinline__ double bsum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// Pair sums over i != j within each sublattice,
+//   pG = sum Re(G_ij G_ji),  pK = sum Re(G_ij G_ji) cos(2 pi (n1_j - n1_i) / L),
+// one workgroup per (sublattice, strip of PB rows i); the strip is walked in
+// PB x PB tiles, G[i, j] and G[j, i] both read down columns (coalesced) into
+// LDS.  The partials go to VEC_NORM (two per strip) and are summed in strip
+// order by k_measure.
+constexpr int PB = 32;
+template <typename S>
+__global__ void __launch_bounds__(MT) k_measure_pairs(const InstDev* __restrict__ insts, int mat) {
+  const InstDev& d = insts[blockIdx.y];
+  InstState* st = d.st;
+  if (st->init_mode || st->idle) return;
+  const int N = d.N, Nc = d.Nc, L = d.L;
+  const int nb = (Nc + PB - 1) / PB;
+  if ((int)blockIdx.x >= 2 * nb) return;
+  const int sub = blockIdx.x & 1, I0 = (blockIdx.x >> 1) * PB, base = sub * Nc;
+  const S* G = matp<S>(d, mat);
+  __shared__ S Aij[PB][PB + 1], Aji[PB][PB + 1];
+  __shared__ double cosL[64];
+  __shared__ double red[4];
+  const double twopiL = 2.0 * M_PI / L;
+  for (int m = threadIdx.x; m < L; m += MT) cosL[m] = cos(twopiL * m);
+  const int r = threadIdx.x % PB, c0 = threadIdx.x / PB;   // 8 column groups
+  double pG = 0, pK = 0;
+  for (int J0 = 0; J0 < Nc; J0 += PB) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PB / 8; ++u) {
+      const int cc = c0 + 8 * u;
+      const int i = min(I0 + r, Nc - 1), j = min(J0 + cc, Nc - 1);
+      const int jr = min(J0 + r, Nc - 1), ic = min(I0 + cc, Nc - 1);
+      Aij[r][cc] = gld(G + (base + i) + (size_t)(base + j) * N);     // G[I0 + r, J0 + cc]
+      Aji[r][cc] = gld(G + (base + jr) + (size_t)(base + ic) * N);   // G[J0 + r, I0 + cc]
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PB / 8; ++u) {
+      const int a = r, b = c0 + 8 * u;
+      const int ii = I0 + a, jj = J0 + b;
+      if (ii < Nc && jj < Nc && ii != jj) {
+        const double re = real_part(Aij[a][b] * Aji[b][a]);
+        pG += re;
+        pK += re * cosL[((jj % L) - (ii % L) + L) % L];
+      }
+    }
+  }
+  pG = bsum(pG, red);
+  pK = bsum(pK, red);
+  if (threadIdx.x == 0) {
+    d.vec[VEC_NORM][2 * blockIdx.x] = pG;
+    d.vec[VEC_NORM][2 * blockIdx.x + 1] = pK;
+  }
+}
+
 template <typename S>
 __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ insts, int mat) {
   const InstDev& d = insts[blockIdx.y];
@@ -49,17 +103,12 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
     zc[sub] += z * cos(twopiL * n1);
     zs[sub] += z * sin(twopiL * n1);
   }
-  // pair terms within each sublattice, i != j
+  // pair terms within each sublattice (i != j): partial sums of k_measure_pairs
   double pG = 0, pK = 0;
-  for (size_t x = threadIdx.x; x < (size_t)2 * Nc * Nc; x += MT) {
-    int sub = (int)(x / ((size_t)Nc * Nc));
-    size_t y = x - (size_t)sub * Nc * Nc;
-    int ii = (int)(y % Nc), jj = (int)(y / Nc);
-    if (ii == jj) continue;
-    int i = sub * Nc + ii, j = sub * Nc + jj;
-    double re = real_part(G[i + (size_t)j * N] * G[j + (size_t)i * N]);
-    pG += re;
-    pK += re * cos(twopiL * ((jj % L) - (ii % L)));
+  const int nstrip = 2 * ((Nc + PB - 1) / PB);
+  for (int x = threadIdx.x; x < nstrip; x += MT) {
+    pG += d.vec[VEC_NORM][2 * x];
+    pK += d.vec[VEC_NORM][2 * x + 1];
   }
   // Tr(K G): K[A(r), B(r+delta)] = -t e^{+i Phi_delta}, Gauge-I phases
   const double ph[3] = {0.0, (d.theta1 - d.theta2) / L, -d.theta2 / L};
@@ -109,7 +158,10 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
 }  // namespace
 
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s) {
-  (void)Nmax;
+  const int ncm = Nmax / 2;
+  dim3 grid(2 * ((ncm + PB - 1) / PB), n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_measure_pairs<cplx>, grid, dim3(MT), 0, s, insts, mat);
+  else hipLaunchKernelGGL(k_measure_pairs<double>, grid, dim3(MT), 0, s, insts, mat);
   if (cplx_) hipLaunchKernelGGL(k_measure<cplx>, dim3(1, n_inst), dim3(MT), 0, s, insts, mat);
   else hipLaunchKernelGGL(k_measure<double>, dim3(1, n_inst), dim3(MT), 0, s, insts, mat);
   return hipGetLastError();

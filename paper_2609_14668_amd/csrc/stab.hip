@@ -191,24 +191,38 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
 
 // ---- pre-pivoting: column norms, then a stable descending sort --------------------------
 template <typename S>
-__global__ void __launch_bounds__(256) k_colnorm_sort(const InstDev* __restrict__ insts, int mat) {
+__global__ void __launch_bounds__(256) k_colnorm(const InstDev* __restrict__ insts, int mat) {
   const InstDev& d = insts[blockIdx.y];
   if (d.st->idle) return;
   const int N = d.N;
   const S* A = matp<S>(d, mat);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.st->drift_last = 0.0;
+  // one wave per column, 16 columns per workgroup
+  for (int u = 0; u < 4; ++u) {
+    const int j = blockIdx.x * 16 + wave * 4 + u;
+    if (j >= N) break;
+    double s = 0.0;
+    for (int i = lane; i < N; i += 64) s += absq(gld(A + i + (size_t)j * N));
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) d.vec[VEC_NORM][j] = s;
+  }
+}
+
+// Pivot order of the pre-pivoted QR: columns by descending norm (ties by
+// ascending index), one workgroup per instance, bitonic sort in LDS.
+__global__ void __launch_bounds__(256) k_sort_cols(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
   __shared__ double key[4096];
   __shared__ int idx[4096];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) d.st->drift_last = 0.0;
-  for (int j = wave; j < N; j += 4) {
-    double s = 0.0;
-    for (int i = lane; i < N; i += 64) s += absq(A[i + (size_t)j * N]);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) { key[j] = s; idx[j] = j; }
-  }
   int P = 1;
   while (P < N) P <<= 1;
-  for (int j = N + threadIdx.x; j < P; j += 256) { key[j] = -1.0; idx[j] = j; }
+  for (int j = threadIdx.x; j < P; j += 256) {
+    key[j] = j < N ? d.vec[VEC_NORM][j] : -1.0;
+    idx[j] = j;
+  }
   __syncthreads();
   // bitonic sort: descending key, ascending index among equal keys
   for (int k = 2; k <= P; k <<= 1) {
@@ -407,13 +421,13 @@ __global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ i
 // NBR panel columns for the whole factorisation, so the column loop touches no
 // global memory; per column one reduction (through an LDS transpose) gives
 // ||x||^2 and x^H A[j+1:, c] for the later columns.
-constexpr int PT = 256;
-constexpr int PW = PT / 64;
+// PT = 256 threads for N <= 1024; 512 for larger N, so that the register
+// panel stays within the per-wave budget (two waves per SIMD) without spills.
 constexpr int NBR = 16;
 
-template <typename S>
+template <typename S, int PT>
 struct PanelShared {
-  S xbuf[PW][NBR + 1][65];
+  S xbuf[PT / 64][NBR + 1][65];
   S tot[NBR + 1];
   S rowj[NBR];
   S tau_s[NBR];
@@ -421,21 +435,23 @@ struct PanelShared {
   S scal;
 };
 
-// Sum acc[0..nval) over all threads of the block into sh.tot.
-template <typename S>
-__device__ __forceinline__ void panel_reduce(PanelShared<S>& sh, const S* acc, int nval) {
+// Sum acc[0..nval) (nval <= 16) over all threads of the block into sh.tot.
+template <typename S, int PT>
+__device__ __forceinline__ void panel_reduce(PanelShared<S, PT>& sh, const S* acc, int nval) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int c = 0; c <= NBR; ++c)
     if (c < nval) sh.xbuf[wave][c][lane] = acc[c];
   __syncthreads();
-  // two levels: 16 threads per value each add 16 partials, then one adds 16
+  // two levels: SUBS = PT / 16 threads per value each add 16 partials, then
+  // one thread adds the SUBS sums
+  constexpr int SUBS = PT / 16;
   S t = ST<S>::zero();
-  const int c = tid >> 4, sub = tid & 15;
+  const int c = tid / SUBS, sub = tid % SUBS;
   if (c < nval) {
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      int x = sub * 16 + u;            // partial index 0..255 = wave*64 + lane
+      int x = sub * 16 + u;            // partial index 0..PT-1 = wave*64 + lane
       t = t + sh.xbuf[x >> 6][c][x & 63];
     }
   }
@@ -445,7 +461,7 @@ __device__ __forceinline__ void panel_reduce(PanelShared<S>& sh, const S* acc, i
   if (tid < nval) {
     S u2 = ST<S>::zero();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) u2 = u2 + sh.xbuf[0][tid][u];
+    for (int u = 0; u < SUBS; ++u) u2 = u2 + sh.xbuf[0][tid][u];
     sh.tot[tid] = u2;
   }
   __syncthreads();
@@ -453,9 +469,9 @@ __device__ __forceinline__ void panel_reduce(PanelShared<S>& sh, const S* acc, i
 
 // Column JJ of the panel (compile-time, so the register array is indexed
 // with constants only).
-template <typename S, int RPT, int JJ>
+template <typename S, int RPT, int PT, int JJ>
 struct PanelColumn {
-  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S>& sh, int j0, int N, int nbe) {
+  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S, PT>& sh, int j0, int N, int nbe) {
     if constexpr (JJ < NBR) {
       if (JJ < nbe) {
         const int tid = threadIdx.x;
@@ -479,7 +495,7 @@ struct PanelColumn {
 #pragma unroll
           for (int c = JJ; c < NBR; ++c) sh.rowj[c] = a[0][c];
         }
-        panel_reduce<S>(sh, acc, nc + 1);
+        panel_reduce<S, PT>(sh, acc, nc + 1);
         if (tid == 0) {
           S alpha = sh.rowj[JJ];
           double xn2 = real_part(sh.tot[0]);
@@ -521,15 +537,15 @@ struct PanelColumn {
         }
         __syncthreads();
       }
-      PanelColumn<S, RPT, JJ + 1>::run(a, sh, j0, N, nbe);
+      PanelColumn<S, RPT, PT, JJ + 1>::run(a, sh, j0, N, nbe);
     }
   }
 };
 
 // Column JJ of the compact-WY factor T from the register-held V.
-template <typename S, int RPT, int JJ>
+template <typename S, int RPT, int PT, int JJ>
 struct PanelT {
-  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S>& sh, int j0, int N, int nbe) {
+  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S, PT>& sh, int j0, int N, int nbe) {
     if constexpr (JJ < NBR) {
       if (JJ < nbe) {
         const int tid = threadIdx.x;
@@ -546,7 +562,7 @@ struct PanelT {
             for (int m = 0; m < JJ; ++m) acc[m] = acc[m] + conjg(a[q][m]) * vj;   // i > j0 + m
           }
         }
-        panel_reduce<S>(sh, acc, JJ);
+        panel_reduce<S, PT>(sh, acc, JJ);
         if (tid < JJ) {
           S s2 = ST<S>::zero();
           for (int m = tid; m < JJ; ++m) s2 = s2 + (m == tid ? sh.tau_s[m] : sh.Tm[tid][m]) * sh.tot[m];
@@ -554,12 +570,12 @@ struct PanelT {
         }
         __syncthreads();
       }
-      PanelT<S, RPT, JJ + 1>::run(a, sh, j0, N, nbe);
+      PanelT<S, RPT, PT, JJ + 1>::run(a, sh, j0, N, nbe);
     }
   }
 };
 
-template <typename S, int RPT>
+template <typename S, int RPT, int PT>
 __global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__ insts, int p) {
   const InstDev& d = insts[blockIdx.y];
   if (d.st->idle) return;
@@ -572,7 +588,7 @@ __global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__
   S* TB = matp<S>(d, MAT_TB);
   double* tauv = d.vec[VEC_TAU];
   const int tid = threadIdx.x;
-  __shared__ PanelShared<S> sh;
+  __shared__ PanelShared<S, PT> sh;
 
   S a[RPT][NBR];
 #pragma unroll
@@ -581,7 +597,7 @@ __global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__
 #pragma unroll
     for (int c = 0; c < NBR; ++c) a[q][c] = (i < N && c < nbe) ? A[i + (size_t)(j0 + c) * N] : ST<S>::zero();
   }
-  PanelColumn<S, RPT, 0>::run(a, sh, j0, N, nbe);
+  PanelColumn<S, RPT, PT, 0>::run(a, sh, j0, N, nbe);
   // write back R (upper part) and the Householder vectors, plus explicit V
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -600,7 +616,7 @@ __global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__
   if (tid < nbe) tauv[2 * (j0 + tid)] = real_part(sh.tau_s[tid]), tauv[2 * (j0 + tid) + 1] = imag_part(sh.tau_s[tid]);
   for (int r = tid; r < NBR * (NBR + 1); r += PT) (&sh.Tm[0][0])[r] = ST<S>::zero();
   __syncthreads();
-  PanelT<S, RPT, 1>::run(a, sh, j0, N, nbe);
+  PanelT<S, RPT, PT, 1>::run(a, sh, j0, N, nbe);
   for (int x = tid; x < nbe * nbe; x += PT) {
     int r = x % nbe, c = x / nbe;
     TB[(j0 + r) + (size_t)c * N] = r == c ? sh.tau_s[r] : sh.Tm[r][c];
@@ -786,27 +802,45 @@ __global__ void __launch_bounds__(256) k_pair_t(const InstDev* __restrict__ inst
   const S* V = matp<S>(d, MAT_V);
   S* TB = matp<S>(d, MAT_TB);
   const int tid = threadIdx.x;
-  __shared__ S v1s[64][NBR + 1], v2s[64][NBR + 1];
+  constexpr bool CX = ST<S>::is_complex;
+  __shared__ S part[4][NBR][NBR + 1];
   __shared__ S Mm[NBR][NBR + 1], T1[NBR][NBR + 1], T2[NBR][NBR + 1], Pm[NBR][NBR + 1];
   const int a = tid / NBR, b = tid % NBR;   // one entry of the 16 x 16 products per thread
-  S acc = ST<S>::zero();
-  if (nb2 > 0) {
-    for (int i0 = j1; i0 < N; i0 += 64) {
-      for (int x = tid; x < 64 * NBR; x += 256) {
-        const int r = x % 64, c = x / 64, i = i0 + r;
-        const bool in = i < N;
-        const S x1 = gld(V + min(i, N - 1) + (size_t)(j0 + min(c, nb1 - 1)) * N);
-        const S x2 = gld(V + min(i, N - 1) + (size_t)(j1 + min(c, nb2 - 1)) * N);
-        v1s[r][c] = (in && c < nb1) ? x1 : ST<S>::zero();
-        v2s[r][c] = (in && c < nb2) ? x2 : ST<S>::zero();
-      }
-      __syncthreads();
+  // M12 = V1^H V2 on the matrix cores: wave w takes rows j1 + 4 (w + 4 s) .. + 3;
+  // lane (lr, lk) feeds A[a = lr][k = lk] = conj(V1[i][a]) and B[k = lk][b = lr] = V2[i][b]
+  {
+    const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+    d4 mr = d4{0, 0, 0, 0}, mi = d4{0, 0, 0, 0};
+    if (nb2 > 0) {
+      const S* v1 = V + (size_t)(j0 + min(lr, nb1 - 1)) * N;
+      const S* v2 = V + (size_t)(j1 + min(lr, nb2 - 1)) * N;
+      const bool ca = lr < nb1, cb = lr < nb2;
 #pragma unroll 4
-      for (int r = 0; r < 64; ++r) acc = acc + conjg(v1s[r][a]) * v2s[r][b];
-      __syncthreads();
+      for (int i0 = j1 + 4 * wave; i0 < N; i0 += 16) {
+        const int i = i0 + lk, ic = min(i, N - 1);
+        const S x1 = gld(v1 + ic), x2 = gld(v2 + ic);
+        double ar, ai, br, bi;
+        split_s<S>(x1, ar, ai);
+        split_s<S>(x2, br, bi);
+        if (!(i < N && ca)) { ar = 0.0; ai = 0.0; }
+        if (!(i < N && cb)) { br = 0.0; bi = 0.0; }
+        mr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, mr, 0, 0, 0);
+        if constexpr (CX) {
+          mr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, mr, 0, 0, 0);
+          mi = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, mi, 0, 0, 0);
+          mi = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, mi, 0, 0, 0);
+        }
+      }
+    }
+    // lane holds M[a = lk + 4 r][b = lr]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if constexpr (CX) part[wave][lk + 4 * r][lr] = cmake(mr[r], mi[r]);
+      else part[wave][lk + 4 * r][lr] = mr[r];
     }
   }
-  Mm[a][b] = acc;
+  __syncthreads();
+  Mm[a][b] = part[0][a][b] + part[1][a][b] + part[2][a][b] + part[3][a][b];
   T1[a][b] = (a < nb1 && b < nb1) ? TB[(j0 + a) + (size_t)b * N] : ST<S>::zero();
   T2[a][b] = (a < nb2 && b < nb2) ? TB[(j1 + a) + (size_t)b * N] : ST<S>::zero();
   __syncthreads();
@@ -992,6 +1026,223 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
   }
 }
 
+// ---- Row-split block-reflector update --------------------------------------------------------
+// For batches too small to fill the GPU with column tiles alone (one large
+// instance), the rows [j0, N) of the update C <- (I - V op(T) V^H) C are cut
+// into nsplit chunks (multiples of 32 rows).  Phase 1: each (column tile,
+// chunk) workgroup writes its partial W = V^H C (NR x 64) to the instance's
+// split buffer.  Phase 2: each (column tile, chunk) workgroup sums the
+// partials in chunk order (deterministic), forms W' = op(T) W, and updates
+// its chunk's rows of C.  NR = 16 (one panel) or 32 (a pair of panels; the
+// second panel's vectors are read as zero above its own first row).
+struct ReflRange {
+  int j0, nbe, cbeg, cend;
+};
+template <int NR>
+__device__ __forceinline__ ReflRange refl_range(int N, int blk, int cols) {
+  ReflRange g;
+  g.j0 = blk * NR;
+  g.nbe = min(NR, N - g.j0);
+  g.cbeg = cols == 2 ? 0 : (cols == 1 ? g.j0 : g.j0 + NR);
+  g.cend = cols == 3 ? min(N, g.j0 + 2 * NBR) : N;
+  return g;
+}
+__device__ __forceinline__ int refl_chunk(int N, int j0, int nsplit) {
+  return ((((N - j0) + nsplit - 1) / nsplit) + 31) & ~31;
+}
+
+template <typename S, int NR>
+__global__ void __launch_bounds__(256) k_refl_w(const InstDev* __restrict__ insts, int blk, int target, int cols,
+                                                int nsplit) {
+  constexpr bool CX = ST<S>::is_complex;
+  constexpr int NT = NR / 16;
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  const ReflRange g = refl_range<NR>(N, blk, cols);
+  if (g.j0 >= N) return;
+  const int c0 = g.cbeg + blockIdx.x * AR_CT;
+  if (c0 >= g.cend) return;
+  const int chunk = refl_chunk(N, g.j0, nsplit);
+  const int r0 = g.j0 + blockIdx.z * chunk, r1 = min(N, r0 + chunk);
+  const S* V = matp<S>(d, MAT_V);
+  const S* C = matp<S>(d, target);
+  S* Wp = reinterpret_cast<S*>(d.rsplit) + (size_t)blockIdx.z * NR * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int RB = 32;
+  __shared__ double Vr[RB][NR + 1], Vi[CX ? RB : 1][NR + 1];
+  __shared__ double Cr[RB][AR_CT + 1], Ci[CX ? RB : 1][AR_CT + 1];
+  constexpr int NV = RB * NR / 256, NC = RB * AR_CT / 256;
+  d4 wr[NT], wi[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) { wr[t] = d4{0, 0, 0, 0}; wi[t] = d4{0, 0, 0, 0}; }
+#pragma unroll 1
+  for (int i0 = r0; i0 < r1; i0 += RB) {
+    S vv[NV], cv[NC];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int x = tid + 256 * u, r = x % RB, m = x / RB;
+      vv[u] = gld(V + min(i0 + r, N - 1) + (size_t)(g.j0 + min(m, g.nbe - 1)) * N);
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int x = tid + 256 * u, r = x % RB, cc = x / RB;
+      cv[u] = gld(C + min(i0 + r, N - 1) + (size_t)min(c0 + cc, g.cend - 1) * N);
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int x = tid + 256 * u, r = x % RB, m = x / RB;
+      const int i = i0 + r;
+      const bool in = i < r1 && m < g.nbe && i >= g.j0 + (m / NBR) * NBR;
+      double re, im;
+      split_s<S>(vv[u], re, im);
+      Vr[r][m] = in ? re : 0.0;
+      if constexpr (CX) Vi[r][m] = in ? im : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int x = tid + 256 * u, r = x % RB, cc = x / RB;
+      const bool in = i0 + r < r1 && c0 + cc < g.cend;
+      double re, im;
+      split_s<S>(cv[u], re, im);
+      Cr[r][cc] = in ? re : 0.0;
+      if constexpr (CX) Ci[r][cc] = in ? im : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < RB / 4; ++ks) {
+      const int k = ks * 4 + lk;
+      const double br = Cr[k][wave * 16 + lr];
+      const double bi = CX ? Ci[k][wave * 16 + lr] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        // A = V^H: A[m][k] = conj(V[k][m]); B = C: B[k][c]
+        const double ar = Vr[k][t * 16 + lr];
+        wr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, wr[t], 0, 0, 0);
+        if constexpr (CX) {
+          const double ai = Vi[k][t * 16 + lr];
+          wr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, wr[t], 0, 0, 0);
+          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, wi[t], 0, 0, 0);
+          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, wi[t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // lane holds W[m = 16 t + lk + 4 r][c = 16 wave + lr]; an empty chunk stores zeros
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = t * 16 + lk + 4 * r, c = c0 + wave * 16 + lr;
+      if (c < g.cend) {
+        if constexpr (CX) gst(Wp + (size_t)m * N + c, cmake(wr[t][r], wi[t][r]));
+        else gst(Wp + (size_t)m * N + c, wr[t][r]);
+      }
+    }
+}
+
+template <typename S, int NR>
+__global__ void __launch_bounds__(256) k_refl_c(const InstDev* __restrict__ insts, int blk, int target, int cols,
+                                                int use_th, int nsplit) {
+  constexpr bool CX = ST<S>::is_complex;
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  const ReflRange g = refl_range<NR>(N, blk, cols);
+  if (g.j0 >= N) return;
+  const int c0 = g.cbeg + blockIdx.x * AR_CT;
+  if (c0 >= g.cend) return;
+  const int chunk = refl_chunk(N, g.j0, nsplit);
+  const int r0 = g.j0 + blockIdx.z * chunk, r1 = min(N, r0 + chunk);
+  const S* V = matp<S>(d, MAT_V);
+  const S* TB = matp<S>(d, MAT_TB);
+  const S* Wp = reinterpret_cast<const S*>(d.rsplit);
+  S* C = matp<S>(d, target);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  __shared__ S Ws[NR][AR_CT + 1];
+  __shared__ S Tt[NR][NR + 1];
+  // W = sum of the chunk partials, in chunk order
+  for (int x = tid; x < NR * AR_CT; x += 256) {
+    const int m = x / AR_CT, cc = x % AR_CT;
+    const int c = min(c0 + cc, g.cend - 1);
+    S acc = ST<S>::zero();
+    for (int z = 0; z < nsplit; ++z) acc = acc + gld(Wp + (size_t)(z * NR + m) * N + c);
+    Ws[m][cc] = acc;
+  }
+  for (int x = tid; x < NR * NR; x += 256) {
+    const int r = x % NR, c = x / NR;
+    const int tr = use_th ? c : r, tc = use_th ? r : c;
+    S t = (tr < g.nbe && tc < g.nbe) ? TB[(g.j0 + tr) + (size_t)tc * N] : ST<S>::zero();
+    Tt[r][c] = use_th ? conjg(t) : t;
+  }
+  __syncthreads();
+  // W' = op(T) W: thread row m = tid % NR, columns tid / NR + (256 / NR) u
+  {
+    constexpr int NU = AR_CT * NR / 256, CS = 256 / NR;
+    const int m = tid % NR, cb = tid / NR;
+    S wp[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) wp[u] = ST<S>::zero();
+#pragma unroll 2
+    for (int k = 0; k < NR; ++k) {
+      const S t = Tt[m][k];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) wp[u] = wp[u] + t * Ws[k][cb + CS * u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NU; ++u) Ws[m][cb + CS * u] = wp[u];
+  }
+  __syncthreads();
+  // C -= V W' on rows [r0, r1): wave w updates columns 16w .. 16w+15, 16 rows at a time
+  constexpr int NK = NR / 4;
+  const int cw = c0 + wave * 16;
+#pragma unroll 1
+  for (int i0 = r0; i0 < r1; i0 += 16) {
+    const int i = i0 + lr, ic = min(i, N - 1);
+    S cl[4], vl[NK];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, g.cend - 1) * N);
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) vl[ks] = gld(V + ic + (size_t)(g.j0 + min(ks * 4 + lk, g.nbe - 1)) * N);
+    d4 cr, ci;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double re, im;
+      split_s<S>(cl[r], re, im);
+      cr[r] = -re;
+      ci[r] = -im;
+    }
+#pragma unroll
+    for (int ks = 0; ks < NK; ++ks) {
+      const int m = ks * 4 + lk;
+      double vr, vi;
+      split_s<S>(vl[ks], vr, vi);
+      if (!(i < r1 && m < g.nbe && i >= g.j0 + (m / NBR) * NBR)) { vr = 0.0; vi = 0.0; }
+      double br, bi;
+      split_s<S>(Ws[m][wave * 16 + lr], br, bi);
+      // acc^T += W'^T V^T: A-operand W'[m][c] as (c, m), B-operand V[i][m] as (m, i)
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, cr, 0, 0, 0);
+      if constexpr (CX) {
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi, vi, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vr, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vi, ci, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = cw + lk + 4 * r;
+      if (i < r1 && c < g.cend) {
+        if constexpr (CX) gst(C + i + (size_t)c * N, cmake(-cr[r], -ci[r]));
+        else gst(C + i + (size_t)c * N, -cr[r]);
+      }
+    }
+  }
+}
+
 template <typename S>
 __global__ void k_diag_abs(const InstDev* __restrict__ insts) {
   const InstDev& d = insts[blockIdx.y];
@@ -1056,9 +1307,10 @@ hipError_t launch_elem(const InstDev* insts, int n_inst, int Nmax, bool cplx_, E
 }
 
 hipError_t launch_colnorm_sort(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s) {
-  (void)Nmax;
-  if (cplx_) hipLaunchKernelGGL(k_colnorm_sort<cplx>, dim3(1, n_inst), dim3(256), 0, s, insts, mat);
-  else hipLaunchKernelGGL(k_colnorm_sort<double>, dim3(1, n_inst), dim3(256), 0, s, insts, mat);
+  dim3 grid((Nmax + 15) / 16, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_colnorm<cplx>, grid, dim3(256), 0, s, insts, mat);
+  else hipLaunchKernelGGL(k_colnorm<double>, grid, dim3(256), 0, s, insts, mat);
+  hipLaunchKernelGGL(k_sort_cols, dim3(1, n_inst), dim3(256), 0, s, insts);
   return hipGetLastError();
 }
 
@@ -1090,17 +1342,25 @@ hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cpl
 }
 
 hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, hipStream_t s) {
-  int rpt = (Nmax + PT - 1) / PT;
-#define DQMC_QRP(R)                                                                                          \
-  if (cplx_) hipLaunchKernelGGL((k_qr_panel_reg<cplx, R>), dim3(1, n_inst), dim3(PT), 0, s, insts, p);      \
-  else hipLaunchKernelGGL((k_qr_panel_reg<double, R>), dim3(1, n_inst), dim3(PT), 0, s, insts, p);
-  if (rpt <= 1) { DQMC_QRP(1) }
-  else if (rpt <= 2) { DQMC_QRP(2) }
-  else if (rpt <= 3) { DQMC_QRP(3) }
-  else if (rpt <= 4) { DQMC_QRP(4) }
-  else if (rpt <= 8) { DQMC_QRP(8) }
-  else if (rpt <= 16) { DQMC_QRP(16) }
-  else return hipErrorInvalidValue;
+#define DQMC_QRP(R, T)                                                                                        \
+  if (cplx_) hipLaunchKernelGGL((k_qr_panel_reg<cplx, R, T>), dim3(1, n_inst), dim3(T), 0, s, insts, p);      \
+  else hipLaunchKernelGGL((k_qr_panel_reg<double, R, T>), dim3(1, n_inst), dim3(T), 0, s, insts, p);
+  // only rows [16 p, N) take part: the register count follows the panel's rows
+  const int rows = Nmax - p * NBR;
+  if (rows <= 0) return hipSuccess;
+  if (rows <= 1024) {
+    const int rpt = (rows + 255) / 256;
+    if (rpt <= 1) { DQMC_QRP(1, 256) }
+    else if (rpt <= 2) { DQMC_QRP(2, 256) }
+    else if (rpt <= 3) { DQMC_QRP(3, 256) }
+    else { DQMC_QRP(4, 256) }
+  } else {
+    const int rpt = (rows + 511) / 512;
+    if (rpt <= 3) { DQMC_QRP(3, 512) }
+    else if (rpt <= 4) { DQMC_QRP(4, 512) }
+    else if (rpt <= 8) { DQMC_QRP(8, 512) }
+    else return hipErrorInvalidValue;
+  }
 #undef DQMC_QRP
   return hipGetLastError();
 }
@@ -1111,12 +1371,40 @@ hipError_t launch_pair_t(const InstDev* insts, int n_inst, bool cplx_, int q, hi
   return hipGetLastError();
 }
 
+// Row chunks for a block-reflector update: 1 (fused kernel) when the column
+// tiles of all instances fill the GPU; else enough chunks of at least 128 rows
+// for about two workgroups per compute unit.
+static int refl_split(int n_inst, int ncol, int rows, int nr) {
+  const int tiles = ((ncol + AR_CT - 1) / AR_CT) * n_inst;
+  if (tiles >= 256) return 1;
+  int ns = (512 + tiles - 1) / tiles;
+  ns = std::min(ns, rows / 128);
+  ns = std::min(ns, RSPLIT_ROWS / nr);
+  return std::max(ns, 1);
+}
+
+template <int NR>
+static hipError_t launch_refl_split(const InstDev* insts, int n_inst, bool cplx_, int blk, int target, int cols,
+                                    int use_th, int ncol, int ns, hipStream_t s) {
+  dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst, ns);
+  if (cplx_) {
+    hipLaunchKernelGGL((k_refl_w<cplx, NR>), grid, dim3(256), 0, s, insts, blk, target, cols, ns);
+    hipLaunchKernelGGL((k_refl_c<cplx, NR>), grid, dim3(256), 0, s, insts, blk, target, cols, use_th, ns);
+  } else {
+    hipLaunchKernelGGL((k_refl_w<double, NR>), grid, dim3(256), 0, s, insts, blk, target, cols, ns);
+    hipLaunchKernelGGL((k_refl_c<double, NR>), grid, dim3(256), 0, s, insts, blk, target, cols, use_th, ns);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_apply_refl2(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int q, int target, int cols,
                               int use_th, hipStream_t s) {
   int j0 = q * PR;
   int cbeg = cols == 0 ? j0 + PR : (cols == 1 ? j0 : 0);
   int ncol = Nmax - cbeg;
-  if (ncol <= 0) return hipSuccess;
+  if (ncol <= 0 || j0 >= Nmax) return hipSuccess;
+  const int ns = refl_split(n_inst, ncol, Nmax - j0, PR);
+  if (ns > 1) return launch_refl_split<PR>(insts, n_inst, cplx_, q, target, cols, use_th, ncol, ns, s);
   dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst);
   if (cplx_) hipLaunchKernelGGL(k_apply_refl2<cplx>, grid, dim3(256), 0, s, insts, q, target, cols, use_th);
   else hipLaunchKernelGGL(k_apply_refl2<double>, grid, dim3(256), 0, s, insts, q, target, cols, use_th);
@@ -1128,7 +1416,9 @@ hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cp
   int j0 = p * NBR;
   int cbeg = (cols == 0 || cols == 3) ? j0 + NBR : (cols == 1 ? j0 : 0);
   int ncol = (cols == 3 ? std::min(Nmax, j0 + 2 * NBR) : Nmax) - cbeg;
-  if (ncol <= 0) return hipSuccess;
+  if (ncol <= 0 || j0 >= Nmax) return hipSuccess;
+  const int ns = refl_split(n_inst, ncol, Nmax - j0, NBR);
+  if (ns > 1) return launch_refl_split<NBR>(insts, n_inst, cplx_, p, target, cols, use_th, ncol, ns, s);
   dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst);
   if (cplx_) hipLaunchKernelGGL(k_apply_refl<cplx>, grid, dim3(256), 0, s, insts, p, target, cols, use_th);
   else hipLaunchKernelGGL(k_apply_refl<double>, grid, dim3(256), 0, s, insts, p, target, cols, use_th);

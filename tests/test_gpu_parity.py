@@ -67,7 +67,8 @@ def test_flush_matches_numpy(L, th, k):
     assert np.abs(sim.green(0) - ref).max() / np.abs(ref).max() < 1e-13
 
 
-@pytest.mark.parametrize("L,th,beta", [(3, (0, 0), 3.0), (4, (0.6, 1.3), 2.0), (6, (0, 0), 2.0), (42, (0, 0), 1.0)])
+@pytest.mark.parametrize("L,th,beta", [(3, (0, 0), 3.0), (4, (0.6, 1.3), 2.0), (6, (0, 0), 2.0), (12, (0.4, 1.9), 1.0),
+                                         (42, (0, 0), 1.0)])
 def test_initial_green_matches_oracle(L, th, beta):
     d = workloads.desc(L, 3.8, beta, theta=th, n_stab=5 if L > 20 else 10)
     sim = _sim([d])
