@@ -419,73 +419,117 @@ __global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ i
 
 // Register-resident panel: thread t owns rows j0 + t + PT*q (q < RPT) of the
 // NBR panel columns for the whole factorisation, so the column loop touches no
-// global memory; per column one reduction (through an LDS transpose) gives
-// ||x||^2 and x^H A[j+1:, c] for the later columns.
-// PT = 256 threads for N <= 1024; 512 for larger N, so that the register
-// panel stays within the per-wave budget (two waves per SIMD) without spills.
+// global memory.  Per column one block-wide sum of 16 values (||x||^2 and
+// x^H A[j+1:, c] for the later columns) with a single barrier: a butterfly
+// transpose-sum across the 64 lanes of each wave, per-wave partials in LDS
+// (double-buffered, so the next column may write while this one is read),
+// and every thread adds the partials and forms the reflector itself.
+// PT = 256 threads for up to 1024 rows, else 512 (two waves per SIMD).
 constexpr int NBR = 16;
 
 template <typename S, int PT>
 struct PanelShared {
-  S xbuf[PT / 64][NBR + 1][65];
-  S tot[NBR + 1];
-  S rowj[NBR];
+  S part[2][PT / 64][NBR];   // per-wave sums of the 16 values
+  S totw[PT / 64][NBR];      // block totals, one copy per wave (read by that wave only)
+  S rowj[2][NBR];            // the pivot row j of the panel
   S tau_s[NBR];
   S Tm[NBR][NBR + 1];
-  S scal;
 };
 
-// Sum acc[0..nval) (nval <= 16) over all threads of the block into sh.tot.
-template <typename S, int PT>
-__device__ __forceinline__ void panel_reduce(PanelShared<S, PT>& sh, const S* acc, int nval) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+template <typename S>
+__device__ __forceinline__ S shfl_x(S v, int m) {
+  if constexpr (ST<S>::is_complex) return cmake(__shfl_xor(v.x, m), __shfl_xor(v.y, m));
+  else return __shfl_xor(v, m);
+}
+
+// Wave-wide sums of acc[0..16): after the call lane l holds the sum of value
+// (l >> 2) & 15 (17 exchanges instead of 16 x 6).
+template <typename S>
+__device__ __forceinline__ S wave_transpose_sum(const S (&acc)[NBR]) {
+  const int lane = threadIdx.x & 63;
+  S b8[8], b4[4], b2[2];
+  {
+    const bool hi = lane & 32;
 #pragma unroll
-  for (int c = 0; c <= NBR; ++c)
-    if (c < nval) sh.xbuf[wave][c][lane] = acc[c];
-  __syncthreads();
-  // two levels: SUBS = PT / 16 threads per value each add 16 partials, then
-  // one thread adds the SUBS sums
-  constexpr int SUBS = PT / 16;
-  S t = ST<S>::zero();
-  const int c = tid / SUBS, sub = tid % SUBS;
-  if (c < nval) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      int x = sub * 16 + u;            // partial index 0..PT-1 = wave*64 + lane
-      t = t + sh.xbuf[x >> 6][c][x & 63];
+    for (int v = 0; v < 8; ++v) {
+      const S send = hi ? acc[v] : acc[v + 8], keep = hi ? acc[v + 8] : acc[v];
+      b8[v] = keep + shfl_x(send, 32);
     }
   }
-  __syncthreads();
-  if (c < nval) sh.xbuf[0][c][sub] = t;
-  __syncthreads();
-  if (tid < nval) {
-    S u2 = ST<S>::zero();
+  {
+    const bool hi = lane & 16;
 #pragma unroll
-    for (int u = 0; u < SUBS; ++u) u2 = u2 + sh.xbuf[0][tid][u];
-    sh.tot[tid] = u2;
+    for (int v = 0; v < 4; ++v) {
+      const S send = hi ? b8[v] : b8[v + 4], keep = hi ? b8[v + 4] : b8[v];
+      b4[v] = keep + shfl_x(send, 16);
+    }
   }
+  {
+    const bool hi = lane & 8;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const S send = hi ? b4[v] : b4[v + 2], keep = hi ? b4[v + 2] : b4[v];
+      b2[v] = keep + shfl_x(send, 8);
+    }
+  }
+  const bool hi = lane & 4;
+  S b1 = (hi ? b2[1] : b2[0]) + shfl_x(hi ? b2[0] : b2[1], 4);
+  b1 = b1 + shfl_x(b1, 2);
+  b1 = b1 + shfl_x(b1, 1);
+  return b1;
+}
+
+// Publish the wave sums of acc into sh.part[buf] and wait for every wave.
+template <typename S, int PT>
+__device__ __forceinline__ void panel_publish(PanelShared<S, PT>& sh, const S (&acc)[NBR], int buf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const S v = wave_transpose_sum<S>(acc);
+  if ((lane & 3) == 0) sh.part[buf][wave][(lane >> 2) & 15] = v;
   __syncthreads();
 }
 
+// Block totals of the 16 published values into this wave's copy of totw:
+// lanes 0..15 add the per-wave sums of one value each.  Only this wave reads
+// its copy afterwards, and the LDS operations of one wave complete in order,
+// so no further barrier is needed.
+template <typename S, int PT>
+__device__ __forceinline__ void panel_totals(PanelShared<S, PT>& sh, int buf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < NBR) {
+    S t = sh.part[buf][0][lane];
+#pragma unroll
+    for (int w = 1; w < PT / 64; ++w) t = t + sh.part[buf][w][lane];
+    sh.totw[wave][lane] = t;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Component-wise select (a struct-valued ?: can demote a register array to
+// scratch memory).
+__device__ __forceinline__ double psel(bool p, double a, double b) { return p ? a : b; }
+__device__ __forceinline__ cplx psel(bool p, cplx a, cplx b) { return cmake(p ? a.x : b.x, p ? a.y : b.y); }
+
 // Column JJ of the panel (compile-time, so the register array is indexed
-// with constants only).
+// with constants and only the later columns are touched).  One barrier per
+// column; every thread forms the reflector from the same shared values.
 template <typename S, int RPT, int PT, int JJ>
 struct PanelColumn {
   static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S, PT>& sh, int j0, int N, int nbe) {
     if constexpr (JJ < NBR) {
       if (JJ < nbe) {
+        constexpr int buf = JJ & 1;
         const int tid = threadIdx.x;
         const int j = j0 + JJ;
-        const int nc = nbe - JJ - 1;
-        S acc[NBR + 1];
+        // acc[0] = ||x||^2 below the diagonal, acc[c - JJ] = x^H A[j+1:, c]
+        S acc[NBR];
 #pragma unroll
-        for (int c = 0; c <= NBR; ++c) acc[c] = ST<S>::zero();
+        for (int c = 0; c < NBR; ++c) acc[c] = ST<S>::zero();
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int i = j0 + tid + PT * q;
           if (i > j && i < N) {
-            S x = a[q][JJ];
-            S cx = conjg(x);
+            const S x = a[q][JJ];
+            const S cx = conjg(x);
             acc[0] = acc[0] + ST<S>::from_re(absq(x));
 #pragma unroll
             for (int c = JJ + 1; c < NBR; ++c) acc[c - JJ] = acc[c - JJ] + cx * a[q][c];
@@ -493,82 +537,81 @@ struct PanelColumn {
         }
         if (tid == JJ) {
 #pragma unroll
-          for (int c = JJ; c < NBR; ++c) sh.rowj[c] = a[0][c];
+          for (int c = JJ; c < NBR; ++c) sh.rowj[buf][c] = a[0][c];
         }
-        panel_reduce<S, PT>(sh, acc, nc + 1);
-        if (tid == 0) {
-          S alpha = sh.rowj[JJ];
-          double xn2 = real_part(sh.tot[0]);
-          S tau, scal;
-          if (xn2 == 0.0 && imag_part(alpha) == 0.0) {
-            tau = ST<S>::zero();
-            scal = ST<S>::one();
-          } else {
-            double nrm = sqrt(absq(alpha) + xn2);
-            double beta = real_part(alpha) >= 0.0 ? -nrm : nrm;
-            S bS = ST<S>::from_re(beta);
-            tau = cdiv(bS - alpha, bS);
-            scal = cdiv(ST<S>::one(), alpha - bS);
-            sh.rowj[JJ] = bS;
-          }
-          sh.tau_s[JJ] = tau;
-          sh.scal = scal;
+        panel_publish<S, PT>(sh, acc, buf);
+        panel_totals<S, PT>(sh, buf);
+        const S* tot = sh.totw[tid >> 6];
+        const S alpha = sh.rowj[buf][JJ];
+        const double xn2 = real_part(tot[0]);
+        S tau, scal, bnew = alpha;
+        if (xn2 == 0.0 && imag_part(alpha) == 0.0) {
+          tau = ST<S>::zero();
+          scal = ST<S>::one();
+        } else {
+          const double nrm = sqrt(absq(alpha) + xn2);
+          const double beta = real_part(alpha) >= 0.0 ? -nrm : nrm;
+          const S bS = ST<S>::from_re(beta);
+          tau = cdiv(bS - alpha, bS);
+          scal = cdiv(ST<S>::one(), alpha - bS);
+          bnew = bS;
         }
-        __syncthreads();
-        const S scal = sh.scal, cscal = conjg(scal);
-        const S ctau = conjg(sh.tau_s[JJ]);
+        if (tid == 0) sh.tau_s[JJ] = tau;
+        const S cscal = conjg(scal), ctau = conjg(tau);
         S w[NBR];
 #pragma unroll
-        for (int c = JJ + 1; c < NBR; ++c) w[c] = sh.rowj[c] + cscal * sh.tot[c - JJ];
+        for (int c = JJ + 1; c < NBR; ++c) w[c] = sh.rowj[buf][c] + cscal * tot[c - JJ];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int i = j0 + tid + PT * q;
           if (i == j) {
-            a[q][JJ] = sh.rowj[JJ];
+            a[q][JJ] = bnew;
 #pragma unroll
             for (int c = JJ + 1; c < NBR; ++c) a[q][c] = a[q][c] - ctau * w[c];
           } else if (i > j && i < N) {
-            S vi = a[q][JJ] * scal;
+            const S vi = a[q][JJ] * scal;
             a[q][JJ] = vi;
-            S f = ctau * vi;
+            const S f = ctau * vi;
 #pragma unroll
             for (int c = JJ + 1; c < NBR; ++c) a[q][c] = a[q][c] - f * w[c];
           }
         }
-        __syncthreads();
       }
       PanelColumn<S, RPT, PT, JJ + 1>::run(a, sh, j0, N, nbe);
     }
   }
 };
 
-// Column JJ of the compact-WY factor T from the register-held V.
+// Column JJ of the compact-WY factor T from the register-held V:
+// T[0:JJ, JJ] = -tau_JJ T[0:JJ, 0:JJ] (V[:, 0:JJ]^H v_JJ).
 template <typename S, int RPT, int PT, int JJ>
 struct PanelT {
   static __device__ __forceinline__ void run(S (&a)[RPT][NBR], PanelShared<S, PT>& sh, int j0, int N, int nbe) {
     if constexpr (JJ < NBR) {
       if (JJ < nbe) {
+        constexpr int buf = JJ & 1;
         const int tid = threadIdx.x;
         const int j = j0 + JJ;
-        S acc[NBR + 1];
+        S acc[NBR];
 #pragma unroll
-        for (int m = 0; m <= NBR; ++m) acc[m] = ST<S>::zero();
+        for (int m = 0; m < NBR; ++m) acc[m] = ST<S>::zero();
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
           const int i = j0 + tid + PT * q;
           if (i >= j && i < N) {
-            S vj = i == j ? ST<S>::one() : a[q][JJ];
+            const S vj = i == j ? ST<S>::one() : a[q][JJ];
 #pragma unroll
             for (int m = 0; m < JJ; ++m) acc[m] = acc[m] + conjg(a[q][m]) * vj;   // i > j0 + m
           }
         }
-        panel_reduce<S, PT>(sh, acc, JJ);
+        panel_publish<S, PT>(sh, acc, buf);
+        panel_totals<S, PT>(sh, buf);
+        const S* tot = sh.totw[tid >> 6];
         if (tid < JJ) {
           S s2 = ST<S>::zero();
-          for (int m = tid; m < JJ; ++m) s2 = s2 + (m == tid ? sh.tau_s[m] : sh.Tm[tid][m]) * sh.tot[m];
+          for (int m = tid; m < JJ; ++m) s2 = s2 + (m == tid ? sh.tau_s[m] : sh.Tm[tid][m]) * tot[m];
           sh.Tm[tid][JJ] = -(sh.tau_s[JJ] * s2);
         }
-        __syncthreads();
       }
       PanelT<S, RPT, PT, JJ + 1>::run(a, sh, j0, N, nbe);
     }
@@ -590,13 +633,21 @@ __global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__
   const int tid = threadIdx.x;
   __shared__ PanelShared<S, PT> sh;
 
+  // clamped loads issued back to back, masked afterwards
   S a[RPT][NBR];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int i = j0 + tid + PT * q;
 #pragma unroll
-    for (int c = 0; c < NBR; ++c) a[q][c] = (i < N && c < nbe) ? A[i + (size_t)(j0 + c) * N] : ST<S>::zero();
+    for (int c = 0; c < NBR; ++c) a[q][c] = gld(A + min(i, N - 1) + (size_t)(j0 + min(c, nbe - 1)) * N);
   }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = j0 + tid + PT * q;
+#pragma unroll
+    for (int c = 0; c < NBR; ++c) a[q][c] = psel(i < N && c < nbe, a[q][c], ST<S>::zero());
+  }
+  for (int r = tid; r < NBR * (NBR + 1); r += PT) (&sh.Tm[0][0])[r] = ST<S>::zero();
   PanelColumn<S, RPT, PT, 0>::run(a, sh, j0, N, nbe);
   // write back R (upper part) and the Householder vectors, plus explicit V
 #pragma unroll
@@ -613,10 +664,10 @@ __global__ void __launch_bounds__(PT) k_qr_panel_reg(const InstDev* __restrict__
       }
     }
   }
+  __syncthreads();   // tau_s of the last column; part/totw free for the T pass
   if (tid < nbe) tauv[2 * (j0 + tid)] = real_part(sh.tau_s[tid]), tauv[2 * (j0 + tid) + 1] = imag_part(sh.tau_s[tid]);
-  for (int r = tid; r < NBR * (NBR + 1); r += PT) (&sh.Tm[0][0])[r] = ST<S>::zero();
-  __syncthreads();
   PanelT<S, RPT, PT, 1>::run(a, sh, j0, N, nbe);
+  __syncthreads();   // the last column of Tm
   for (int x = tid; x < nbe * nbe; x += PT) {
     int r = x % nbe, c = x / nbe;
     TB[(j0 + r) + (size_t)c * N] = r == c ? sh.tau_s[r] : sh.Tm[r][c];
@@ -1358,8 +1409,13 @@ hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool 
     const int rpt = (rows + 511) / 512;
     if (rpt <= 3) { DQMC_QRP(3, 512) }
     else if (rpt <= 4) { DQMC_QRP(4, 512) }
-    else if (rpt <= 8) { DQMC_QRP(8, 512) }
-    else return hipErrorInvalidValue;
+    else if (rpt > 8) return hipErrorInvalidValue;
+    else if (cplx_) hipLaunchKernelGGL((k_qr_panel_reg<cplx, 8, 512>), dim3(1, n_inst), dim3(512), 0, s, insts, p);
+    // real panels: the smallest register array that holds the rows
+    else if (rpt == 5) hipLaunchKernelGGL((k_qr_panel_reg<double, 5, 512>), dim3(1, n_inst), dim3(512), 0, s, insts, p);
+    else if (rpt == 6) hipLaunchKernelGGL((k_qr_panel_reg<double, 6, 512>), dim3(1, n_inst), dim3(512), 0, s, insts, p);
+    else if (rpt == 7) hipLaunchKernelGGL((k_qr_panel_reg<double, 7, 512>), dim3(1, n_inst), dim3(512), 0, s, insts, p);
+    else hipLaunchKernelGGL((k_qr_panel_reg<double, 8, 512>), dim3(1, n_inst), dim3(512), 0, s, insts, p);
   }
 #undef DQMC_QRP
   return hipGetLastError();
