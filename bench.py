@@ -288,7 +288,9 @@ def main():
     wr = tim["wrap"]
     if wr["ms"] > 0:
         ach = tim["wrap_bytes"] / (wr["ms"] * 1e-3)
-        line["roofline_wrap"] = {"bound": "hbm", "kernel": "k_fft_apply (wrap)", "achieved": ach / 1e9,
+        ls = {x["L"] for x in descs}
+        wk = ("k_fft_reg" if max(ls) <= 24 else ("k_fft_apply" if min(ls) > 24 else "k_fft_reg + k_fft_apply"))
+        line["roofline_wrap"] = {"bound": "hbm", "kernel": wk + " (wrap)", "achieved": ach / 1e9,
                                  "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
                                  "traffic": None, "launches": wr["launches"],
                                  "avg_launch_us": 1e3 * wr["ms"] / max(wr["launches"], 1)}

@@ -321,6 +321,196 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
   }
 }
 
+// ---- register-resident line transforms (compile-time L <= 24) ---------------------------
+// Each thread transforms whole lines of L points in registers with a
+// compile-time mixed-radix Cooley-Tukey split, so a wrap side needs three
+// passes over LDS (axis 0 forward; axis 1 forward, 2x2 block, axis 1 inverse
+// with both sublattices of one momentum column in one thread; axis 0
+// inverse) and three barriers, instead of one barrier per radix stage.
+constexpr int rfac(int n) {
+  if (n <= 4) return n;
+  if (n % 4 == 0) return 4;
+  for (int p : {2, 3, 5, 7, 11, 13})
+    if (n % p == 0) return p;
+  return n;
+}
+
+template <int L, bool INV, typename C>
+__device__ __forceinline__ C twid(const C* roots, int m) {
+  const C w = roots[m];
+  return INV ? conjg(w) : w;
+}
+
+// X = DFT_N(x), W_N = exp(-+2 pi i / N) = W_L^(L/N) with W_L^m = roots[m]
+// (conjugated for the inverse).  n = Q n1 + n2, k = k1 + P k2:
+//   X[k1 + P k2] = sum_n2 W_Q^(n2 k2) W_N^(n2 k1) sum_n1 x[Q n1 + n2] W_P^(n1 k1).
+template <int L, int N, bool INV, typename C>
+__device__ __forceinline__ void rdft(const C (&x)[N], C (&X)[N], const C* roots) {
+  constexpr int P = rfac(N);
+  if constexpr (P == N) {
+    if constexpr (N == 1) {
+      X[0] = x[0];
+    } else if constexpr (N <= 4) {
+      C v[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = x[i];
+      small_dft<N>(v, INV ? +1 : -1);
+#pragma unroll
+      for (int i = 0; i < N; ++i) X[i] = v[i];
+    } else {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        C acc = x[0];
+#pragma unroll
+        for (int n = 1; n < N; ++n) acc = acc + x[n] * twid<L, INV>(roots, (L / N) * ((n * k) % N));
+        X[k] = acc;
+      }
+    }
+  } else {
+    constexpr int Q = N / P;
+    C y[Q][P];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      C t[P], T[P];
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) t[n1] = x[Q * n1 + n2];
+      rdft<L, P, INV>(t, T, roots);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1)
+        y[n2][k1] = (n2 * k1 == 0) ? T[k1] : T[k1] * twid<L, INV>(roots, (L / N) * ((n2 * k1) % N));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      C t[Q], T[Q];
+#pragma unroll
+      for (int n2 = 0; n2 < Q; ++n2) t[n2] = y[n2][k1];
+      rdft<L, Q, INV>(t, T, roots);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) X[k1 + P * k2] = T[k2];
+    }
+  }
+}
+
+// Transform the line at p[0], p[st], ..., p[(L-1) st] in place.
+template <int L, bool INV, typename C>
+__device__ __forceinline__ void line_dft(C* p, int st, const C* roots) {
+  C x[L], X[L];
+#pragma unroll
+  for (int n = 0; n < L; ++n) x[n] = p[n * st];
+  rdft<L, L, INV>(x, X, roots);
+#pragma unroll
+  for (int n = 0; n < L; ++n) p[n * st] = X[n];
+}
+
+template <typename S, int LC, typename C>
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_reg(const InstDev* __restrict__ insts, FftArgs a) {
+  typedef real_of<C> RT;
+  constexpr int L = LC, Nc = L * L, N = 2 * Nc;
+  constexpr int NV = FFT_THREADS / (2 * L);   // vectors per workgroup
+  __shared__ C buf[NV * N];
+  __shared__ C roots[L];
+  const InstDev& d = insts[blockIdx.y];
+  if (d.L != LC) return;
+  Resolved rs = resolve(d, a);
+  if (!rs.active) return;
+  constexpr int nvec = ST<S>::is_complex ? N : N / 2;
+  const int v0 = blockIdx.x * NV;
+  if (v0 >= nvec) return;
+  const int nvl = min(NV, nvec - v0);
+  const int tid = threadIdx.x;
+  if (tid < L) roots[tid] = to_c<C>(d.roots[tid]);
+  S* Mx = matp<S>(d, a.mat);
+  const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
+  const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
+  const bool rows = a.side != 0;
+  // load (+ pre diagonal): clamped loads issued in groups, then masked
+  const int tot = nvl * N;
+  constexpr int LU = 8;
+  for (int e0 = tid; e0 < tot; e0 += LU * FFT_THREADS) {
+    S raw[LU][ST<S>::is_complex ? 1 : 2];
+    int8_t xr[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = min(e0 + u * FFT_THREADS, tot - 1);
+      int vv, r;
+      if (!rows) { vv = e / N; r = e - vv * N; }
+      else { vv = e % nvl; r = e / nvl; }
+      const int q = v0 + vv;
+      if constexpr (ST<S>::is_complex) {
+        raw[u][0] = gld(rows ? Mx + (size_t)r * N + q : Mx + (size_t)q * N + r);
+      } else {
+        raw[u][0] = gld(rows ? Mx + (size_t)r * N + 2 * q : Mx + (size_t)(2 * q) * N + r);
+        raw[u][1] = gld(rows ? Mx + (size_t)r * N + 2 * q + 1 : Mx + (size_t)(2 * q + 1) * N + r);
+      }
+      xr[u] = rs.pre ? xs[r] : (int8_t)1;
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = e0 + u * FFT_THREADS;
+      if (e < tot) {
+        int vv, r;
+        if (!rows) { vv = e / N; r = e - vv * N; }
+        else { vv = e % nvl; r = e / nvl; }
+        C val;
+        if constexpr (ST<S>::is_complex) val = mkc<C>(raw[u][0].x, rows ? -raw[u][0].y : raw[u][0].y);
+        else val = mkc<C>(raw[u][0], raw[u][1]);
+        if (rs.pre) val = val * ((rs.pre * xr[u]) > 0 ? ep : em);
+        buf[vv * N + r] = val;
+      }
+    }
+  }
+  __syncthreads();
+  // axis 0, forward: line (vector, sublattice, n2) per thread, L consecutive points
+  if (tid < nvl * 2 * L) line_dft<L, false>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
+  __syncthreads();
+  // axis 1 for momentum column k1 of both sublattices: forward, 2x2 block, inverse
+  if (tid < nvl * L) {
+    const int vv = tid / L, k1 = tid % L;
+    C* pa = buf + vv * N + k1;
+    C* pb = pa + Nc;
+    line_dft<L, false>(pa, L, roots);
+    C xb[L], Xb[L];
+#pragma unroll
+    for (int n = 0; n < L; ++n) xb[n] = pb[n * L];
+    rdft<L, L, false>(xb, Xb, roots);
+    const cplx* T = d.tab + (size_t)rs.tab * Nc * 4;
+#pragma unroll
+    for (int k2 = 0; k2 < L; ++k2) {
+      const int k = k1 + L * k2;
+      const C t00 = to_c<C>(T[4 * k]), t01 = to_c<C>(T[4 * k + 1]), t10 = to_c<C>(T[4 * k + 2]),
+              t11 = to_c<C>(T[4 * k + 3]);
+      const C qa = pa[k2 * L], qb = Xb[k2];
+      pa[k2 * L] = t00 * qa + t01 * qb;
+      Xb[k2] = t10 * qa + t11 * qb;
+    }
+    rdft<L, L, true>(Xb, xb, roots);
+#pragma unroll
+    for (int n = 0; n < L; ++n) pb[n * L] = xb[n];
+    line_dft<L, true>(pa, L, roots);
+  }
+  __syncthreads();
+  // axis 0, inverse
+  if (tid < nvl * 2 * L) line_dft<L, true>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
+  __syncthreads();
+  // store (+ post diagonal)
+  for (int e = tid; e < tot; e += FFT_THREADS) {
+    int vv, r;
+    if (!rows) { vv = e / N; r = e - vv * N; }
+    else { vv = e % nvl; r = e / nvl; }
+    const int q = v0 + vv;
+    C val = buf[vv * N + r];
+    if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
+    const double vx = (double)val.x, vy = (double)val.y;
+    if constexpr (ST<S>::is_complex) {
+      if (rows) gst(Mx + (size_t)r * N + q, cmake(vx, -vy));
+      else gst(Mx + (size_t)q * N + r, cmake(vx, vy));
+    } else {
+      if (!rows) { gst(Mx + (size_t)(2 * q) * N + r, vx); gst(Mx + (size_t)(2 * q + 1) * N + r, vy); }
+      else { gst(Mx + (size_t)r * N + 2 * q, vx); gst(Mx + (size_t)r * N + 2 * q + 1, vy); }
+    }
+  }
+}
+
 }  // namespace
 
 int fft_vectors_per_block(int N, size_t lds_budget, size_t elem_bytes) {
@@ -349,12 +539,20 @@ namespace {
 template <typename S, int LC, typename C>
 void launch_fixed(const InstDev* insts, int n_inst, const FftArgs& a, size_t lds_budget, hipStream_t s) {
   constexpr int N = 2 * LC * LC;
-  int nv = fft_vectors_per_block(N, lds_budget, sizeof(C));
-  int nvec = ST<S>::is_complex ? N : N / 2;
-  dim3 grid((nvec + nv - 1) / nv, n_inst);
-  size_t lds = 2 * (size_t)nv * N * sizeof(C);
-  constexpr int R = 13;  // unused by the fixed path
-  hipLaunchKernelGGL((k_fft_apply<S, R, LC, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 0);
+  if constexpr (LC <= 24) {
+    // register line transforms: NV vectors per workgroup, LDS sized at compile time
+    (void)lds_budget;
+    constexpr int NV = FFT_THREADS / (2 * LC);
+    constexpr int nvec = ST<S>::is_complex ? N : N / 2;
+    hipLaunchKernelGGL((k_fft_reg<S, LC, C>), dim3((nvec + NV - 1) / NV, n_inst), dim3(FFT_THREADS), 0, s, insts, a);
+  } else {
+    int nv = fft_vectors_per_block(N, lds_budget, sizeof(C));
+    int nvec = ST<S>::is_complex ? N : N / 2;
+    dim3 grid((nvec + nv - 1) / nv, n_inst);
+    size_t lds = 2 * (size_t)nv * N * sizeof(C);
+    constexpr int R = 13;  // unused by the fixed path
+    hipLaunchKernelGGL((k_fft_apply<S, R, LC, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 0);
+  }
 }
 
 template <typename S, typename C>
