@@ -789,16 +789,16 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
 
 dqmc_status dqmc_destroy(dqmc_handle h) {
   if (!h) return DQMC_EINVAL;
-  hipStreamSynchronize(h->stream);
-  for (auto e : h->ev_pool) hipEventDestroy(e);
-  if (h->gexec) hipGraphExecDestroy(h->gexec);
-  if (h->cap) hipStreamDestroy(h->cap);
+  (void)hipStreamSynchronize(h->stream);
+  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->aux) {
-    hipStreamSynchronize(h->aux);
-    hipStreamDestroy(h->aux);
+    (void)hipStreamSynchronize(h->aux);
+    (void)hipStreamDestroy(h->aux);
   }
   for (auto e : h->join_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   delete h;
   return DQMC_OK;
 }
@@ -885,7 +885,7 @@ static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipS
   const std::vector<int> key = graph_key(h, measure, replay, groups);
   if (!h->gexec || h->gkey != key) {
     if (h->gexec) {
-      hipGraphExecDestroy(h->gexec);
+      (void)hipGraphExecDestroy(h->gexec);
       h->gexec = nullptr;
     }
     hipGraph_t g = nullptr;
@@ -895,11 +895,11 @@ static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipS
     hipError_t e = issue_steps(h, h->n_stab, measure, h->cap, replay, groups);
     hipError_t e2 = hipStreamEndCapture(h->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return fail(h, DQMC_EHIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
     }
     e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       h->gexec = nullptr;
       return fail(h, DQMC_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -983,8 +983,8 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
   }
   h->timing = timing;
   h->flush_variant = bv;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != DQMC_OK) return st;
   if (best) { best[0] = bk; best[1] = bv; }
   return dqmc_set_delay(h, bk);
