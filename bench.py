@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the workload's flush rank")
     ap.add_argument("--flush-kernel", choices=("direct", "tiled"), default=None,
                     help="with --no-autotune: the flush kernel to use")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every step eagerly (counter collection does not follow graph launches)")
     ap.add_argument("--groups", type=int, choices=(1, 2), default=2,
                     help="instance groups on separate streams (1: every launch covers all instances)")
     ap.add_argument("--learn-per-slice", type=int, default=4)
@@ -227,6 +229,8 @@ def main():
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
     learned = a.proposal in ("learned", "both")
     sim.set_streams(a.groups)
+    if a.no_graphs:
+        sim.set_graphs(False)
     tuned = None
     if a.flush_kernel:
         sim.set_flush_kernel(1 if a.flush_kernel == "tiled" else 0)

@@ -39,14 +39,34 @@ __device__ __forceinline__ void split<double>(double v, double& re, double& im) 
 template <>
 __device__ __forceinline__ void split<cplx>(cplx v, double& re, double& im) { re = v.x; im = v.y; }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
+// dispatch order.  Map the dispatch index so that all workgroups of an
+// instance sit on one XCD: instance xcd + 8 q is served by the slots
+// q * gx .. q * gx + gx - 1 of that XCD, and its operands stay in one L2
+// instead of being fetched into all eight.  The grid's y extent is the
+// instance count rounded up to a multiple of 8; slots past the last instance
+// return.  Only the placement depends on the dispatch order, not the result.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ void xcd_slot(int n_inst, int& inst, int& bx) {
+  const int gx = gridDim.x;
+  const int lin = blockIdx.x + gx * blockIdx.y;
+  const int xcd = lin % N_XCD, slot = lin / N_XCD;
+  inst = xcd + N_XCD * (slot / gx);
+  bx = slot % gx;
+  if (inst >= n_inst) inst = -1;
+}
+
 // ROLE only separates the flush instantiation (1) from the stabilisation
 // products (0) in profiles; the code is the same.
 template <typename S, int ROLE>
 __global__ void __launch_bounds__(GEMM_THREADS, 2)
-k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOperand C,
+k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand B, GemmOperand C,
        GemmDim Md, GemmDim Nd, GemmDim Kd, double alpha, double beta, int flags) {
   constexpr bool CX = ST<S>::is_complex;
-  const InstDev& d = insts[blockIdx.y];
+  int inst, bx;
+  xcd_slot(n_inst, inst, bx);
+  if (inst < 0) return;
+  const InstDev& d = insts[inst];
   const int Nn = d.N;
   const InstState& st = *d.st;
   if (st.idle) return;
@@ -129,7 +149,7 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
     }
   };
 
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gridDim.x) {
     const int m0 = (tile % tm) * BM, n0 = (tile / tm) * BN;
     // accumulators hold transposed 16x16 blocks: operands are fed as (B, A) so
     // that a lane owns 4 columns of one row and stores coalesce along columns
@@ -237,9 +257,12 @@ k_gemm(const InstDev* __restrict__ insts, GemmOperand A, GemmOperand B, GemmOper
 // current one is multiplied.
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_flush_direct(const InstDev* __restrict__ insts, int flags) {
+k_flush_direct(const InstDev* __restrict__ insts, int n_inst, int flags) {
   constexpr bool CX = ST<S>::is_complex;
-  const InstDev& d = insts[blockIdx.y];
+  int inst, bx;
+  xcd_slot(n_inst, inst, bx);
+  if (inst < 0) return;
+  const InstDev& d = insts[inst];
   const InstState& st = *d.st;
   if (st.idle || st.init_mode) return;
   if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
@@ -253,7 +276,7 @@ k_flush_direct(const InstDev* __restrict__ insts, int flags) {
   const int nb32 = (N + 31) / 32;
   const int nblk = nb32 * nb32;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+  for (int blk = bx * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
     const int i0 = (blk % nb32) * 32, j0 = (blk / nb32) * 32;
     // [ti][tj] accumulators (transposed blocks).  Complex products use three
     // real products (Gauss): P1 = Yr Xr, P2 = Yi Xi, P3 = (Yr + Yi)(Xr + Xi),
@@ -349,9 +372,12 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_flush_f32(const InstDev* __restrict__ insts, int flags) {
+k_flush_f32(const InstDev* __restrict__ insts, int n_inst, int flags) {
   constexpr bool CX = ST<S>::is_complex;
-  const InstDev& d = insts[blockIdx.y];
+  int inst, bx;
+  xcd_slot(n_inst, inst, bx);
+  if (inst < 0) return;
+  const InstDev& d = insts[inst];
   const InstState& st = *d.st;
   if (st.idle || st.init_mode) return;
   if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
@@ -365,7 +391,7 @@ k_flush_f32(const InstDev* __restrict__ insts, int flags) {
   const int nb32 = (N + 31) / 32;
   const int nblk = nb32 * nb32;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+  for (int blk = bx * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
     const int i0 = (blk % nb32) * 32, j0 = (blk / nb32) * 32;
     f4 ar_[2][2], ai_[2][2];
 #pragma unroll
@@ -444,14 +470,14 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
   int cap = 4096 / (n_inst > 0 ? n_inst : 1);
   if (cap < 8) cap = 8;
   int gx = tiles < cap ? tiles : cap;
-  dim3 grid(gx, n_inst);
+  dim3 grid(gx, (n_inst + N_XCD - 1) / N_XCD * N_XCD);
   const bool fl = flags & GF_K_FILL;
   if (cplx_) {
-    if (fl) hipLaunchKernelGGL((k_gemm<cplx, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
-    else hipLaunchKernelGGL((k_gemm<cplx, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+    if (fl) hipLaunchKernelGGL((k_gemm<cplx, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
+    else hipLaunchKernelGGL((k_gemm<cplx, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
   } else {
-    if (fl) hipLaunchKernelGGL((k_gemm<double, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
-    else hipLaunchKernelGGL((k_gemm<double, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, A, B, C, M, Nn, K, alpha, beta, flags);
+    if (fl) hipLaunchKernelGGL((k_gemm<double, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
+    else hipLaunchKernelGGL((k_gemm<double, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
   }
   return hipGetLastError();
 }
@@ -462,13 +488,13 @@ hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool 
   int blocks = (nb32 * nb32 + 3) / 4;
   int cap = 8192 / (n_inst > 0 ? n_inst : 1);
   if (cap < 16) cap = 16;
-  dim3 grid(blocks < cap ? blocks : cap, n_inst);
+  dim3 grid(blocks < cap ? blocks : cap, (n_inst + N_XCD - 1) / N_XCD * N_XCD);
   if (single) {
-    if (cplx_) hipLaunchKernelGGL(k_flush_f32<cplx>, grid, dim3(256), 0, s, insts, flags);
-    else hipLaunchKernelGGL(k_flush_f32<double>, grid, dim3(256), 0, s, insts, flags);
+    if (cplx_) hipLaunchKernelGGL(k_flush_f32<cplx>, grid, dim3(256), 0, s, insts, n_inst, flags);
+    else hipLaunchKernelGGL(k_flush_f32<double>, grid, dim3(256), 0, s, insts, n_inst, flags);
     return hipGetLastError();
   }
-  if (cplx_) hipLaunchKernelGGL(k_flush_direct<cplx>, grid, dim3(256), 0, s, insts, flags);
-  else hipLaunchKernelGGL(k_flush_direct<double>, grid, dim3(256), 0, s, insts, flags);
+  if (cplx_) hipLaunchKernelGGL(k_flush_direct<cplx>, grid, dim3(256), 0, s, insts, n_inst, flags);
+  else hipLaunchKernelGGL(k_flush_direct<double>, grid, dim3(256), 0, s, insts, n_inst, flags);
   return hipGetLastError();
 }
