@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the workload's flush rank")
     ap.add_argument("--flush-kernel", choices=("direct", "tiled"), default=None,
                     help="with --no-autotune: the flush kernel to use")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every step eagerly (counter collection does not follow graph launches)")
     ap.add_argument("--groups", type=int, choices=(1, 2), default=2,
@@ -212,8 +214,24 @@ def timed_leg(sim, steps, label, learn_m=0, events=True):
             "drift": max(s["drift_max"] for s in st1)}
 
 
+def copy_calibration():
+    """A plain device copy of known size: what FETCH_SIZE and WRITE_SIZE read
+    for it converts their counts of other kernels to bytes."""
+    import torch
+    n = 256 * 1024 * 1024
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("copied %d bytes x3" % n, flush=True)
+
+
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: the chains are independent and would be sharded "
               "across GPUs with no communication; run with --gpus 1", file=sys.stderr)
