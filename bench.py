@@ -63,7 +63,7 @@ def parse():
                     help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every step eagerly (counter collection does not follow graph launches)")
-    ap.add_argument("--groups", type=int, choices=(1, 2), default=2,
+    ap.add_argument("--groups", type=int, choices=(1, 2, 3, 4), default=3,
                     help="instance groups on separate streams (1: every launch covers all instances)")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)

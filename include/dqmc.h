@@ -292,13 +292,14 @@ dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant);
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 
-/* Instance groups: with 2 (the default for two or more instances) the
- * instances are split in two contiguous groups of about equal work, group 0
- * running on the call's stream and group 1 on a second stream of the handle,
- * so that the latency-bound kernels of one group overlap the others'; the
- * call's stream waits for both before the call returns.  1 runs every
- * instance in the same launches.  Live timing (dqmc_set_timing) runs one
- * group. */
+/* Instance groups: groups in [1, 4] (3 is the default, fewer with fewer
+ * instances).  The instances are split into that many contiguous groups of
+ * about equal work (fewer if there are fewer instances), group 0 running on
+ * the call's stream and the others on streams of the handle, so that the
+ * latency-bound kernels of one group overlap the others'; the call's stream
+ * waits for all of them before the call returns.  1 runs every instance in
+ * the same launches.  Live timing (dqmc_set_timing) runs one group.
+ * DQMC_EINVAL for groups outside [1, 4]. */
 dqmc_status dqmc_set_streams(dqmc_handle h, int32_t groups);
 
 /* HIP graphs (default on): sweeps replay one captured block of n_stab slice

@@ -162,7 +162,7 @@ def test_flush_rank_does_not_change_the_chain():
     assert np.abs(c.green(0) - b.green(0)).max() < 1e-10
 
 
-@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("groups", [1, 2, 3])
 def test_graph_replay_matches_eager(groups):
     """Sweeps replayed from the captured block equal eager sweeps (fields,
     G, estimators), over several replays with eager work in between, with
@@ -182,3 +182,20 @@ def test_graph_replay_matches_eager(groups):
         assert np.abs(a.green(i) - b.green(i)).max() < 1e-12
         oa, ob = a.measure(i), b.measure(i)
         assert oa["n_meas"] == ob["n_meas"] and abs(oa["D"] - ob["D"]) < 1e-12
+
+
+def test_instance_groups_do_not_change_the_chain():
+    """The chains are independent, so splitting them over one or four
+    streams gives the same fields, G and estimators."""
+    descs = [workloads.desc(3 + i % 3, 3.8, 2.0, theta=(0.3 * i, 0.9), k=16, n_stab=10, seed=140 + i)
+             for i in range(5)]
+    a, b = _sim(descs), _sim(descs)
+    a.set_streams(1)
+    b.set_streams(4)
+    for _ in range(2):
+        a.sweep(1, measure=True)
+        b.sweep(1, measure=True)
+    for i in range(5):
+        assert np.array_equal(a.fields(i), b.fields(i))
+        assert np.abs(a.green(i) - b.green(i)).max() < 1e-12
+        assert a.measure(i)["D"] == pytest.approx(b.measure(i)["D"], abs=1e-12)
