@@ -80,6 +80,8 @@ def make_descs(name, k=None):
         return workloads.plain_L3()
     if name == "plain_L42":
         return workloads.plain_L42()
+    if name == "plain_L42x4":
+        return workloads.plain_L42(n_chains=4)
     if name == "mixed_L30":
         return workloads.mixed_L30(precision=1)
     if name == "fp64_L30":

@@ -11,7 +11,7 @@ L up to 42, Sec. III-IV) at dtau = 0.1 and a stabilisation interval of 10:
                of (Theta1, Theta2) in [0, 2pi)^2, 4 chains per twist, plus 16
                L=12 instances (beta=12) in the same batch
   mixed_L30    L=30 (N=1800), U=3.73, beta=30, twist (0.3 pi, 0.7 pi), k=64
-  plain_L42    L=42 (N=3528), U=3.73, beta=42, PBC, FP64 real
+  plain_L42    L=42 (N=3528), U=3.73, beta=42, PBC, FP64 real (plain_L42x4: four chains)
 """
 import math
 
@@ -73,8 +73,8 @@ def mixed_L30(precision=1):
     return [desc(30, 3.73, 30.0, theta=(0.3 * math.pi, 0.7 * math.pi), k=64, precision=precision)]
 
 
-def plain_L42():
-    return [desc(42, 3.73, 42.0, k=64)]
+def plain_L42(n_chains=1):
+    return [desc(42, 3.73, 42.0, k=64, seed=1 + i) for i in range(n_chains)]
 
 
 # The paper's Table III/IV points used for a physics pin (PBC, HS in the spin
