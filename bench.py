@@ -63,8 +63,9 @@ def parse():
                     help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every step eagerly (counter collection does not follow graph launches)")
-    ap.add_argument("--groups", type=int, choices=(1, 2, 3, 4), default=3,
-                    help="instance groups on separate streams (1: every launch covers all instances)")
+    ap.add_argument("--groups", type=int, choices=(1, 2, 3, 4), default=None,
+                    help="instance groups on separate streams (1: every launch covers all instances; "
+                         "default: the library's choice for the batch size)")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -248,7 +249,8 @@ def main():
     print("workload %s: %d instances, Nmax %d, Mmax %d, complex %s" % (a.workload, n, Nmax, Mmax,
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
     learned = a.proposal in ("learned", "both")
-    sim.set_streams(a.groups)
+    if a.groups:
+        sim.set_streams(a.groups)
     if a.no_graphs:
         sim.set_graphs(False)
     tuned = None

@@ -292,8 +292,8 @@ dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant);
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 
-/* Instance groups: groups in [1, 4] (3 is the default, fewer with fewer
- * instances).  The instances are split into that many contiguous groups of
+/* Instance groups: groups in [1, 4] (default: 3 for 24 or more instances, 2
+ * for 8 or more, else 1).  The instances are split into that many contiguous groups of
  * about equal work (fewer if there are fewer instances), group 0 running on
  * the call's stream and the others on streams of the handle, so that the
  * latency-bound kernels of one group overlap the others'; the call's stream

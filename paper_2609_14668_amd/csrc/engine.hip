@@ -676,7 +676,11 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     h->n_aux = g + 1;
   }
   if (h->n_aux > 0 && hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess) h->fork_ev = nullptr;
-  split_groups(h, 3);   // measured best on the L=18 batch (3.39 s per sweep; 2: 3.53 s, 4: 3.48 s)
+  // Groups pay off when the batch has many instances whose latency-bound
+  // kernels are small: 80 instances (64 L=18 + 16 L=12) run a sweep in 3.39 s
+  // with 3 groups (2: 3.53 s, 4: 3.48 s), but four L=42 chains take 65 s
+  // with 3 groups against 40.5 s in one.
+  split_groups(h, n >= 24 ? 3 : (n >= 8 ? 2 : 1));
   if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
     h->cap = nullptr;
     h->use_graphs = false;
