@@ -1,8 +1,9 @@
 """The L=18 twisted batch at its full size (64 complex128 L=18 chains on a 4x4
 twist grid, four per twist, plus 16 L=12 chains: N = 648 and 288, M = 180 and
-120) in the launch configuration that the benchmark times: two instance
-groups on two streams, stabilisation blocks replayed as HIP graphs, the flush
-rank and kernel picked by the autotuner.
+120) in the launch configuration that the benchmark times: the library's
+default instance groups for this batch (three, on three streams),
+stabilisation blocks replayed as HIP graphs, the flush rank and kernel picked
+by the autotuner.
 
 Sampled outputs are checked against the oracle where it can compute them one
 by one at this size (the scratch G of an L=18 and an L=12 instance from
@@ -46,7 +47,6 @@ def batch():
     descs = workloads.twist_L18()
     assert len(descs) == 80 and descs[L18]["L"] == 18 and descs[L12]["L"] == 12
     sim = Simulation(descs)
-    sim.set_streams(2)
     sim.set_graphs(True)
     best, _ = sim.autotune([24, 64], 2 * descs[0]["n_stab"])
     print("autotuned flush rank %d, kernel %s" % (best[0], ("direct", "tiled")[best[1]]), flush=True)
