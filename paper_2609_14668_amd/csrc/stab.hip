@@ -944,9 +944,15 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
   S* Ws = reinterpret_cast<S*>(cbuf);
   __shared__ S Tt[PR][PR + 1];
   constexpr int NV = RB * PR / 256, NC = RB * AR_CT / 256;
-  d4 wr[2], wi[2];
+  // complex products with three real ones: P1 = ar br (wr), P2 = ai bi (wi),
+  // P3 = (ar + ai)(br + bi) (wq); re = P1 - P2, im = P3 - P1 - P2
+  d4 wr[2], wi[2], wq[CX ? 2 : 1];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) { wr[t] = d4{0, 0, 0, 0}; wi[t] = d4{0, 0, 0, 0}; }
+  for (int t = 0; t < 2; ++t) {
+    wr[t] = d4{0, 0, 0, 0};
+    wi[t] = d4{0, 0, 0, 0};
+    if constexpr (CX) wq[t] = d4{0, 0, 0, 0};
+  }
 #pragma unroll 1
   for (int i0 = j0; i0 < N; i0 += RB) {
     S vv[NV], cv[NC];
@@ -987,14 +993,13 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
       const double bi = CX ? Ci[k * (AR_CT + 1) + wave * 16 + lr] : 0.0;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        // A = V^H: A[m][k] = conj(V[k][m]); B = C: B[k][c]
+        // A = V^H: A[m][k] = conj(V[k][m]) = (ar, ai); B = C: B[k][c] = (br, bi)
         const double ar = Vr[k][t * 16 + lr];
         wr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, wr[t], 0, 0, 0);
         if constexpr (CX) {
           const double ai = -Vi[k][t * 16 + lr];
-          wr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, wr[t], 0, 0, 0);
-          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, wi[t], 0, 0, 0);
-          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, wi[t], 0, 0, 0);
+          wi[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, wi[t], 0, 0, 0);
+          wq[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, br + bi, wq[t], 0, 0, 0);
         }
       }
     }
@@ -1006,7 +1011,7 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = t * 16 + lk + 4 * r, c = wave * 16 + lr;
-      if constexpr (CX) Ws[m * (AR_CT + 1) + c] = cmake(wr[t][r], wi[t][r]);
+      if constexpr (CX) Ws[m * (AR_CT + 1) + c] = cmake(wr[t][r] - wi[t][r], wq[t][r] - wr[t][r] - wi[t][r]);
       else Ws[m * (AR_CT + 1) + c] = wr[t][r];
     }
   for (int x = tid; x < PR * PR; x += 256) {
@@ -1043,13 +1048,17 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
     for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, N - 1) * N);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) vl[ks] = gld(V + ic + (size_t)(j0 + min(ks * 4 + lk, nbe - 1)) * N);
-    d4 cr, ci;
+    // (W' V)(c, i) with three real products: Q1 = br vr (q1), Q2 = bi vi (q2),
+    // Q3 = (br + bi)(vr + vi) (q3), started at -C so that
+    // C - W'V = -((q1 - q2) + i (q3 - q1 - q2)) with q1 = -Cre, q3 = -Cre - Cim
+    d4 q1, q2, q3;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double re, im;
       split_s<S>(cl[r], re, im);
-      cr[r] = -re;
-      ci[r] = -im;
+      q1[r] = -re;
+      q2[r] = 0.0;
+      q3[r] = -re - im;
     }
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
@@ -1059,19 +1068,18 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
       if (!(i < N && m < nbe && i >= j0 + (m / NBR) * NBR)) { vr = 0.0; vi = 0.0; }
       double br, bi;
       split_s<S>(Ws[m * (AR_CT + 1) + wave * 16 + lr], br, bi);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, cr, 0, 0, 0);
+      q1 = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, q1, 0, 0, 0);
       if constexpr (CX) {
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi, vi, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vr, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vi, ci, 0, 0, 0);
+        q2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vi, q2, 0, 0, 0);
+        q3 = __builtin_amdgcn_mfma_f64_16x16x4f64(br + bi, vr + vi, q3, 0, 0, 0);
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = cw + lk + 4 * r;
       if (i < N && c < N) {
-        if constexpr (CX) gst(C + i + (size_t)c * N, cmake(-cr[r], -ci[r]));
-        else gst(C + i + (size_t)c * N, -cr[r]);
+        if constexpr (CX) gst(C + i + (size_t)c * N, cmake(-(q1[r] - q2[r]), -(q3[r] - q1[r] - q2[r])));
+        else gst(C + i + (size_t)c * N, -q1[r]);
       }
     }
   }
