@@ -83,7 +83,7 @@ enum ElemOp : int {
 struct ElemArgs { int op, a, b, c, v; };
 hipError_t launch_elem(const InstDev* insts, int n_inst, int Nmax, bool cplx_, ElemArgs e, hipStream_t s);
 hipError_t launch_colnorm_sort(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
-hipError_t launch_qr_panel(const InstDev* insts, int n_inst, bool cplx_, int p, int nb, hipStream_t s);
+
 // 16-column panel held in registers (rows per thread chosen from Nmax)
 hipError_t launch_qr_panel_reg(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, hipStream_t s);
 // target <- (I - V op(T) V^H) target for panel p; cols 0: trailing [j0+16, N),

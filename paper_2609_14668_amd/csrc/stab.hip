@@ -244,179 +244,6 @@ __global__ void __launch_bounds__(256) k_sort_cols(const InstDev* __restrict__ i
   for (int j = threadIdx.x; j < N; j += 256) d.perm[j] = idx[j];
 }
 
-// ---- Householder panel factorisation (one workgroup per instance) ---------------------------
-// Columns [j0, j0 + nbe) of MAT_QA: H_j = I - tau_j v_j v_j^H with v_j[j] = 1,
-// H_j^H applied from the left; beta = -sign(Re alpha) ||(alpha, x)||.
-// Writes explicit V (MAT_V) and the compact-WY factor T (MAT_TB), so that
-// H_j0 ... H_{j0+nbe-1} = I - V T V^H.
-constexpr int QR_T = 128;
-constexpr int QR_W = QR_T / 64;
-constexpr int NBMAX = 32;
-
-template <typename S>
-__device__ __forceinline__ S wave_sum(S v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    if constexpr (ST<S>::is_complex) { v.x += __shfl_xor(v.x, off); v.y += __shfl_xor(v.y, off); }
-    else v += __shfl_xor(v, off);
-  }
-  return v;
-}
-
-// Rows are owned by a fixed thread (row i by thread (i - j0) % QR_T) for the
-// whole panel, so a thread only rereads what it wrote itself; per column one
-// fused reduction gives ||x||^2 and the dots x^H A[:, c] of all later panel
-// columns, from which w_c = v^H A[j:, c] = A[j, c] + conj(scal) x^H A[j+1:, c].
-template <typename S>
-__global__ void __launch_bounds__(QR_T) k_qr_panel(const InstDev* __restrict__ insts, int p, int nb) {
-  const InstDev& d = insts[blockIdx.y];
-  if (d.st->idle) return;
-  const int N = d.N;
-  const int j0 = p * nb;
-  if (j0 >= N) return;
-  const int nbe = min(nb, N - j0);
-  S* A = matp<S>(d, MAT_QA);
-  S* V = matp<S>(d, MAT_V);
-  S* TB = matp<S>(d, MAT_TB);
-  double* tauv = d.vec[VEC_TAU];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // per-wave transpose buffer: lane partials of every reduced value
-  __shared__ S xbuf[QR_W][NBMAX + 1][65];
-  __shared__ S part[QR_W][NBMAX + 1];
-  __shared__ S tot[NBMAX + 1];
-  __shared__ S rowj[NBMAX + 1];
-  __shared__ S tau_s[NBMAX];
-  __shared__ S Tm[NBMAX][NBMAX + 1];
-  __shared__ S sh_scal;
-
-  for (int jj = 0; jj < nbe; ++jj) {
-    const int j = j0 + jj;
-    const int nc = nbe - jj - 1;
-    // fused pass: slot 0 = ||x||^2 (x = A[j+1:, j]), slot 1 + c = x^H A[j+1:, j+1+c]
-    S acc[NBMAX + 1];
-#pragma unroll
-    for (int c = 0; c <= NBMAX; ++c) acc[c] = ST<S>::zero();
-    // row j of the panel: alpha = A[j, j], then A[j, j+1+c]
-    if (tid <= nc) rowj[tid] = A[j + (size_t)(j + tid) * N];
-    for (int i = j0 + tid; i < N; i += QR_T) {
-      if (i <= j) continue;
-      S x = A[i + (size_t)j * N];
-      S cx = conjg(x);
-      acc[0] = acc[0] + ST<S>::from_re(absq(x));
-#pragma unroll
-      for (int c = 0; c < NBMAX; ++c)
-        if (c < nc) acc[1 + c] = acc[1 + c] + cx * A[i + (size_t)(j + 1 + c) * N];
-    }
-#pragma unroll
-    for (int c = 0; c <= NBMAX; ++c)
-      if (c <= nc) xbuf[wave][c][lane] = acc[c];
-    __syncthreads();
-    if (lane <= nc) {
-      S t = xbuf[wave][lane][0];
-      for (int l = 1; l < 64; ++l) t = t + xbuf[wave][lane][l];
-      part[wave][lane] = t;
-    }
-    __syncthreads();
-    if (tid <= nc) {
-      S t = part[0][tid];
-      for (int w = 1; w < QR_W; ++w) t = t + part[w][tid];
-      tot[tid] = t;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      S alpha = rowj[0];
-      double xn2 = real_part(tot[0]);
-      S tau, scal;
-      if (xn2 == 0.0 && imag_part(alpha) == 0.0) {
-        tau = ST<S>::zero();
-        scal = ST<S>::one();
-      } else {
-        double nrm = sqrt(absq(alpha) + xn2);
-        double beta = real_part(alpha) >= 0.0 ? -nrm : nrm;
-        S bS = ST<S>::from_re(beta);
-        tau = cdiv(bS - alpha, bS);
-        scal = cdiv(ST<S>::one(), alpha - bS);
-        A[j + (size_t)j * N] = bS;
-      }
-      tau_s[jj] = tau;
-      sh_scal = scal;
-    }
-    __syncthreads();
-    const S scal = sh_scal;
-    const S ctau = conjg(tau_s[jj]);
-    const S cscal = conjg(scal);
-    // row j of the later panel columns (v_j = 1)
-    if (tid < nc) {
-      S w = rowj[1 + tid] + cscal * tot[1 + tid];
-      A[j + (size_t)(j + 1 + tid) * N] = rowj[1 + tid] - ctau * w;
-    }
-    // rows below j: v_i = scal x_i, A[i, c] -= conj(tau) v_i w_c
-    for (int i = j0 + tid; i < N; i += QR_T) {
-      if (i <= j) continue;
-      S vi = A[i + (size_t)j * N] * scal;
-      A[i + (size_t)j * N] = vi;
-      S f = ctau * vi;
-#pragma unroll 4
-      for (int c = 0; c < nc; ++c) {
-        size_t o = i + (size_t)(j + 1 + c) * N;
-        A[o] = A[o] - f * (rowj[1 + c] + cscal * tot[1 + c]);
-      }
-    }
-    __syncthreads();
-  }
-  // explicit V and tau
-  for (int jj = 0; jj < nbe; ++jj) {
-    const int j = j0 + jj;
-    for (int i = j0 + tid; i < N; i += QR_T) {
-      S v = i < j ? ST<S>::zero() : (i == j ? ST<S>::one() : A[i + (size_t)j * N]);
-      V[i + (size_t)j * N] = v;
-    }
-  }
-  if (tid < nbe) tauv[2 * (j0 + tid)] = real_part(tau_s[tid]), tauv[2 * (j0 + tid) + 1] = imag_part(tau_s[tid]);
-  for (int r = tid; r < NBMAX * (NBMAX + 1); r += QR_T) (&Tm[0][0])[r] = ST<S>::zero();
-  __syncthreads();
-  // T (forward, columnwise): T[jj][jj] = tau_jj, T[0:jj, jj] = -tau_jj T[0:jj, 0:jj] V[:, 0:jj]^H v_jj
-  for (int jj = 1; jj < nbe; ++jj) {
-    const int j = j0 + jj;
-    S acc[NBMAX];
-#pragma unroll
-    for (int m = 0; m < NBMAX; ++m) acc[m] = ST<S>::zero();
-    for (int i = j0 + tid; i < N; i += QR_T) {
-      if (i < j) continue;
-      S vj = V[i + (size_t)j * N];
-#pragma unroll
-      for (int m = 0; m < NBMAX; ++m)
-        if (m < jj) acc[m] = acc[m] + conjg(V[i + (size_t)(j0 + m) * N]) * vj;
-    }
-#pragma unroll
-    for (int m = 0; m < NBMAX; ++m)
-      if (m < jj) xbuf[wave][m][lane] = acc[m];
-    __syncthreads();
-    if (lane < jj) {
-      S t = xbuf[wave][lane][0];
-      for (int l = 1; l < 64; ++l) t = t + xbuf[wave][lane][l];
-      part[wave][lane] = t;
-    }
-    __syncthreads();
-    if (tid < jj) {
-      S t = part[0][tid];
-      for (int w = 1; w < QR_W; ++w) t = t + part[w][tid];
-      tot[tid] = t;
-    }
-    __syncthreads();
-    // column jj of T from the rows above (sequential dependence only on earlier columns)
-    if (tid < jj) {
-      S s2 = ST<S>::zero();
-      for (int m = tid; m < jj; ++m) s2 = s2 + (m == tid ? tau_s[m] : Tm[tid][m]) * tot[m];
-      Tm[tid][jj] = -(tau_s[jj] * s2);
-    }
-    __syncthreads();
-  }
-  for (int x = tid; x < nbe * nbe; x += QR_T) {
-    int r = x % nbe, c = x / nbe;
-    TB[(j0 + r) + (size_t)c * N] = r == c ? tau_s[r] : Tm[r][c];
-  }
-}
-
 // Register-resident panel: thread t owns rows j0 + t + PT*q (q < RPT) of the
 // NBR panel columns for the whole factorisation, so the column loop touches no
 // global memory.  Per column one block-wide sum of 16 values (||x||^2 and
@@ -1370,19 +1197,6 @@ hipError_t launch_colnorm_sort(const InstDev* insts, int n_inst, int Nmax, bool 
   if (cplx_) hipLaunchKernelGGL(k_colnorm<cplx>, grid, dim3(256), 0, s, insts, mat);
   else hipLaunchKernelGGL(k_colnorm<double>, grid, dim3(256), 0, s, insts, mat);
   hipLaunchKernelGGL(k_sort_cols, dim3(1, n_inst), dim3(256), 0, s, insts);
-  return hipGetLastError();
-}
-
-hipError_t launch_qr_panel(const InstDev* insts, int n_inst, bool cplx_, int p, int nb, hipStream_t s) {
-  if (nb == NBR) {
-    // register-resident panel; rows per thread from the largest instance
-    int Nmax = 0;
-    (void)Nmax;
-    return hipErrorInvalidValue;  // replaced by launch_qr_panel_reg
-  }
-  if (nb > NBMAX) return hipErrorInvalidValue;
-  if (cplx_) hipLaunchKernelGGL(k_qr_panel<cplx>, dim3(1, n_inst), dim3(QR_T), 0, s, insts, p, nb);
-  else hipLaunchKernelGGL(k_qr_panel<double>, dim3(1, n_inst), dim3(QR_T), 0, s, insts, p, nb);
   return hipGetLastError();
 }
 
