@@ -463,30 +463,32 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_reg(const InstDev* __restri
   // axis 0, forward: line (vector, sublattice, n2) per thread, L consecutive points
   if (tid < nvl * 2 * L) line_dft<L, false>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
   __syncthreads();
-  // axis 1 for momentum column k1 of both sublattices: forward, 2x2 block, inverse
-  if (tid < nvl * L) {
-    const int vv = tid / L, k1 = tid % L;
-    C* pa = buf + vv * N + k1;
-    C* pb = pa + Nc;
-    line_dft<L, false>(pa, L, roots);
-    C xb[L], Xb[L];
-#pragma unroll
-    for (int n = 0; n < L; ++n) xb[n] = pb[n * L];
-    rdft<L, L, false>(xb, Xb, roots);
-    const cplx* T = d.tab + (size_t)rs.tab * Nc * 4;
+  // axis 1, forward: line (vector, sublattice, k1) per thread
+  const bool b_act = tid < nvl * 2 * L;
+  const int bv = tid / (2 * L), bs = (tid % (2 * L)) / L, bk1 = tid % L;
+  C* pb_own = buf + bv * N + bs * Nc + bk1;
+  if (b_act) line_dft<L, false>(pb_own, L, roots);
+  __syncthreads();
+  // 2x2 block per momentum: the thread of sublattice s forms row s of the
+  // block from both lines of its column, then transforms it back
+  C y[L];
+  if (b_act) {
+    const C* pa = buf + bv * N + bk1;
+    const C* pbb = pa + Nc;
+    const cplx* T = d.tab + (size_t)rs.tab * Nc * 4 + 2 * bs;   // row bs: (t_s0, t_s1)
 #pragma unroll
     for (int k2 = 0; k2 < L; ++k2) {
-      const int k = k1 + L * k2;
-      const C t00 = to_c<C>(T[4 * k]), t01 = to_c<C>(T[4 * k + 1]), t10 = to_c<C>(T[4 * k + 2]),
-              t11 = to_c<C>(T[4 * k + 3]);
-      const C qa = pa[k2 * L], qb = Xb[k2];
-      pa[k2 * L] = t00 * qa + t01 * qb;
-      Xb[k2] = t10 * qa + t11 * qb;
+      const int k = bk1 + L * k2;
+      const C t0 = to_c<C>(T[4 * k]), t1 = to_c<C>(T[4 * k + 1]);
+      y[k2] = t0 * pa[k2 * L] + t1 * pbb[k2 * L];
     }
-    rdft<L, L, true>(Xb, xb, roots);
+  }
+  __syncthreads();   // both lines read before either is overwritten
+  if (b_act) {
+    C x[L];
+    rdft<L, L, true>(y, x, roots);
 #pragma unroll
-    for (int n = 0; n < L; ++n) pb[n * L] = xb[n];
-    line_dft<L, true>(pa, L, roots);
+    for (int n = 0; n < L; ++n) pb_own[n * L] = x[n];
   }
   __syncthreads();
   // axis 0, inverse
