@@ -46,7 +46,7 @@ def measured_traffic(workload, k, kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="twist_L18")
     ap.add_argument("--k", type=int, default=None, help="flush rank override")
