@@ -868,13 +868,14 @@ dqmc_status dqmc_get_fields(dqmc_handle h, int32_t inst, int8_t* host_x) {
 
 // steps is a multiple of n_stab, so the stabilisation points stay aligned
 // across calls.
-// With two instance groups, group 0 runs on the caller's stream and group 1
-// on the handle's second stream; the groups' launches interleave on the host
-// so that the latency-bound kernels of one group (window scan, expand, QR
-// panels) overlap the bandwidth- and matrix-core-bound kernels of the other.
-// The second stream starts after the caller's prior work and the caller's
-// stream waits for it at the end.  With live timing on, one group is used so
-// that every timed launch covers all instances.
+// With several instance groups, group 0 runs on the caller's stream and
+// group g > 0 on the handle's stream g - 1; the groups' launches interleave on
+// the host so that the latency-bound kernels of one group (window scan,
+// expand, QR panels) overlap the bandwidth- and matrix-core-bound kernels of
+// the others.  The handle's streams start after the caller's prior work (fork
+// event) and the caller's stream waits for each of them at the end (join
+// events).  With live timing on, one group is used so that every timed launch
+// covers all instances.
 static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay,
                               int groups) {
   if (groups == 1) {
@@ -914,8 +915,8 @@ static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, in
 // Sweeps are replayed as HIP graphs of one stabilisation block (n_stab slice
 // steps: the launch sequence is the same for every block of every sweep, all
 // state that changes lives in device memory), captured on first use.  The
-// second instance group's stream joins the capture through an event, so the
-// graph keeps the overlap of the two groups.  The eager path serves live
+// streams of the other instance groups join the capture through the fork
+// event, so the graph keeps the overlap of the groups.  The eager path serves live
 // timing and step counts that are not a whole number of blocks.
 static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay) {
   const int groups = h->timing ? 1 : h->n_groups;

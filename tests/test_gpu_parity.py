@@ -166,7 +166,7 @@ def test_flush_rank_does_not_change_the_chain():
 def test_graph_replay_matches_eager(groups):
     """Sweeps replayed from the captured block equal eager sweeps (fields,
     G, estimators), over several replays with eager work in between, with
-    and without the second instance group."""
+    with one, two and three instance groups."""
     descs = [workloads.desc(4, 3.8, 2.0, theta=(0.4 * i, 1.1), k=16, n_stab=10, seed=120 + i) for i in range(3)]
     a, b = _sim(descs), _sim(descs)
     a.set_graphs(False)
