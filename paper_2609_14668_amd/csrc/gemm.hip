@@ -46,8 +46,18 @@ __device__ __forceinline__ void split<cplx>(cplx v, double& re, double& im) { re
 // instead of being fetched into all eight.  The grid's y extent is the
 // instance count rounded up to a multiple of 8; slots past the last instance
 // return.  Only the placement depends on the dispatch order, not the result.
+// With fewer instances than XCDs the placement would leave XCDs idle, so the
+// plain mapping (instance = blockIdx.y) is used and the grid is not padded.
 constexpr int N_XCD = 8;
+__host__ __device__ __forceinline__ int xcd_grid_y(int n_inst) {
+  return n_inst >= N_XCD ? (n_inst + N_XCD - 1) / N_XCD * N_XCD : n_inst;
+}
 __device__ __forceinline__ void xcd_slot(int n_inst, int& inst, int& bx) {
+  if (n_inst < N_XCD) {
+    inst = blockIdx.y;
+    bx = blockIdx.x;
+    return;
+  }
   const int gx = gridDim.x;
   const int lin = blockIdx.x + gx * blockIdx.y;
   const int xcd = lin % N_XCD, slot = lin / N_XCD;
@@ -470,7 +480,7 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
   int cap = 4096 / (n_inst > 0 ? n_inst : 1);
   if (cap < 8) cap = 8;
   int gx = tiles < cap ? tiles : cap;
-  dim3 grid(gx, (n_inst + N_XCD - 1) / N_XCD * N_XCD);
+  dim3 grid(gx, xcd_grid_y(n_inst));
   const bool fl = flags & GF_K_FILL;
   if (cplx_) {
     if (fl) hipLaunchKernelGGL((k_gemm<cplx, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
@@ -488,7 +498,7 @@ hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool 
   int blocks = (nb32 * nb32 + 3) / 4;
   int cap = 8192 / (n_inst > 0 ? n_inst : 1);
   if (cap < 16) cap = 16;
-  dim3 grid(blocks < cap ? blocks : cap, (n_inst + N_XCD - 1) / N_XCD * N_XCD);
+  dim3 grid(blocks < cap ? blocks : cap, xcd_grid_y(n_inst));
   if (single) {
     if (cplx_) hipLaunchKernelGGL(k_flush_f32<cplx>, grid, dim3(256), 0, s, insts, n_inst, flags);
     else hipLaunchKernelGGL(k_flush_f32<double>, grid, dim3(256), 0, s, insts, n_inst, flags);
