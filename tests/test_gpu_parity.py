@@ -199,3 +199,23 @@ def test_instance_groups_do_not_change_the_chain():
         assert np.array_equal(a.fields(i), b.fields(i))
         assert np.abs(a.green(i) - b.green(i)).max() < 1e-12
         assert a.measure(i)["D"] == pytest.approx(b.measure(i)["D"], abs=1e-12)
+
+
+def test_flush_every_instance_of_an_uneven_batch():
+    """Nine instances (the instance dimension of the grid is padded to 16 and
+    the instances are spread unevenly over the XCD slots): a flush on each
+    instance in turn matches G - X Y and leaves the others unchanged."""
+    descs = [workloads.desc(3, 3.7, 1.0, theta=(0.3 * i, 0.7), n_stab=5, seed=160 + i) for i in range(9)]
+    sim = _sim(descs)
+    N, _, cx = sim.shapes[0]
+    k = 8
+    G = [_rand_g(N, cx, 200 + i) for i in range(9)]
+    for i in range(9):
+        sim.set_green(i, G[i])
+    for i in range(9):
+        X = _rand_g(N, cx, 300 + i)[:, :k]
+        Y = _rand_g(N, cx, 400 + i)[:k, :]
+        sim.flush_test(i, X, Y)
+        G[i] = G[i] - X @ Y
+        for j in range(9):
+            assert np.abs(sim.green(j) - G[j]).max() / np.abs(G[j]).max() < 1e-13, (i, j)
