@@ -74,59 +74,72 @@ def energy_u0(lat, beta):
 
 
 # ---- brute force over HS configurations ---------------------------------------------
-def brute_force(model, batch=4096):
-    """Exact Z and weighted averages of D, <H_0>, S_zz(Gamma), S_zz(b1/L) by
-    summing W(X) over all 2^(N M) configurations (eq. ConfgWeight)."""
+def config_estimators(model, X):
+    """Per-configuration weights and Wick estimators for a batch of HS
+    configurations X (B x M x N, entries +-1): both spins propagated densely,
+    G^sigma = (1 + B^sigma_M..B^sigma_1)^{-1} (G at l = M), and for each
+    configuration W = 2^{-N M} det(1 + B^up..) det(1 + B^dn..)
+    (eq. ConfgWeight) together with D, <H_0> = Tr(K G^up) + Tr(K G^dn) summed
+    with the sign of a hopping term (c_i^+ c_j -> -G_ji), and
+    S_zz(k) = (1/2N_c) sum_sub sum_ij e^{-i k r_i} e^{+i k r_j} <s_i s_j> at
+    k = 0 and k = b1/L (eqs. SzSzCrF, SpinStrucF) from the contraction of
+    the whole same-sublattice block with plane waves."""
     M, N, Nc, L = model.M, model.N, model.Nc, model.L
-    nf = M * N
-    if nf > 20:
-        raise ValueError("too many fields for brute force")
-    lat = model.lat
+    X = np.asarray(X, dtype=float).reshape(-1, M, N)
     K = model.K
     pos = np.array([[I % L, I // L] for I in range(Nc)])
     ph = np.exp(2j * np.pi * pos[:, 0] / L)
+    B = len(X)
+    dets, Gs = [], []
+    for spin in (0, 1):
+        sgn = 1.0 if spin == 0 else -1.0
+        P = np.broadcast_to(np.eye(N, dtype=complex), (B, N, N)).copy()
+        for l in range(M):
+            v = np.exp(sgn * model.lam * X[:, l, :])
+            P = v[:, :, None] * (model.Ep[None] @ P)
+        A = np.eye(N)[None] + P
+        dets.append(np.linalg.det(A))
+        Gs.append(np.linalg.inv(A))
+    W = dets[0] * dets[1] * 2.0 ** (-M * N)
+    nu = 1 - np.einsum("bii->bi", Gs[0])
+    nd = 1 - np.einsum("bii->bi", Gs[1])
+    D = np.mean(nu * nd, axis=1)
+    H0 = -(np.einsum("ij,bji->b", K, Gs[0]) + np.einsum("ij,bji->b", K, Gs[1]))
+    sz = nu - nd
+    SS = 0.25 * (sz[:, :, None] * sz[:, None, :]
+                 + (np.eye(N)[None] - np.transpose(Gs[0], (0, 2, 1))) * Gs[0]
+                 + (np.eye(N)[None] - np.transpose(Gs[1], (0, 2, 1))) * Gs[1])
+    SzzG = np.zeros(B, dtype=complex)
+    Szzdk = np.zeros(B, dtype=complex)
+    for sub in (0, 1):
+        blk = SS[:, sub * Nc:(sub + 1) * Nc, sub * Nc:(sub + 1) * Nc]
+        SzzG += blk.sum(axis=(1, 2))
+        Szzdk += np.einsum("bij,i,j->b", blk, ph.conj(), ph)
+    SzzG /= 2 * Nc
+    Szzdk /= 2 * Nc
+    return {"W": W, "D": D, "H0": H0, "SzzG": SzzG, "Szzdk": Szzdk, "Gup": Gs[0], "Gdn": Gs[1]}
+
+
+def brute_force(model, batch=4096):
+    """Exact Z and weighted averages of D, <H_0>, S_zz(Gamma), S_zz(b1/L) by
+    summing W(X) over all 2^(N M) configurations (eq. ConfgWeight)."""
+    M, N = model.M, model.N
+    nf = M * N
+    if nf > 20:
+        raise ValueError("too many fields for brute force")
     tot = {"Z": 0.0, "D": 0.0, "H0": 0.0, "SzzG": 0.0, "Szzdk": 0.0}
     wmin = np.inf
     max_imag = 0.0
     allcfg = np.array(list(itertools.product((1, -1), repeat=nf)), dtype=float)
     for s0 in range(0, len(allcfg), batch):
-        X = allcfg[s0:s0 + batch].reshape(-1, M, N)
-        B = len(X)
-        dets, Gs = [], []
-        for spin in (0, 1):
-            sgn = 1.0 if spin == 0 else -1.0
-            P = np.broadcast_to(np.eye(N, dtype=complex), (B, N, N)).copy()
-            for l in range(M):
-                v = np.exp(sgn * model.lam * X[:, l, :])
-                P = v[:, :, None] * (model.Ep[None] @ P)
-            A = np.eye(N)[None] + P
-            dets.append(np.linalg.det(A))
-            Gs.append(np.linalg.inv(A))
-        W = dets[0] * dets[1] * 2.0 ** (-nf)
+        c = config_estimators(model, allcfg[s0:s0 + batch])
+        W = c["W"]
         max_imag = max(max_imag, float(np.max(np.abs(W.imag) / np.abs(W))))
         W = W.real
         wmin = min(wmin, float(W.min()))
-        nu = 1 - np.einsum("bii->bi", Gs[0])
-        nd = 1 - np.einsum("bii->bi", Gs[1])
-        D = np.mean(nu * nd, axis=1)
-        H0 = -(np.einsum("ij,bji->b", K, Gs[0]) + np.einsum("ij,bji->b", K, Gs[1]))
-        sz = nu - nd
-        SS = 0.25 * (sz[:, :, None] * sz[:, None, :]
-                     + (np.eye(N)[None] - np.transpose(Gs[0], (0, 2, 1))) * Gs[0]
-                     + (np.eye(N)[None] - np.transpose(Gs[1], (0, 2, 1))) * Gs[1])
-        SzzG = np.zeros(B, dtype=complex)
-        Szzdk = np.zeros(B, dtype=complex)
-        for sub in (0, 1):
-            blk = SS[:, sub * Nc:(sub + 1) * Nc, sub * Nc:(sub + 1) * Nc]
-            SzzG += blk.sum(axis=(1, 2))
-            Szzdk += np.einsum("bij,i,j->b", blk, ph.conj(), ph)
-        SzzG /= 2 * Nc
-        Szzdk /= 2 * Nc
         tot["Z"] += W.sum()
-        tot["D"] += (W * D).sum().real
-        tot["H0"] += (W * H0).sum().real
-        tot["SzzG"] += (W * SzzG).sum().real
-        tot["Szzdk"] += (W * Szzdk).sum().real
+        for k in ("D", "H0", "SzzG", "Szzdk"):
+            tot[k] += (W * c[k]).sum().real
     Z = tot["Z"]
     return {"Z": Z, "D": tot["D"] / Z, "H0": tot["H0"] / Z, "SzzG": tot["SzzG"] / Z,
             "Szzdk": tot["Szzdk"] / Z, "wmin": wmin, "w_max_rel_imag": max_imag}

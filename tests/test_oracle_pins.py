@@ -261,11 +261,25 @@ def test_markov_chain_reproduces_exact_diagonalisation():
     for _ in range(3000):
         n0 = len(ch.samples)
         ch.sweep(src)
-        per_sweep.append({k: np.mean([s[k] for s in ch.samples[n0:]]) for k in ("D", "ekin", "Szz_G")})
-    for key, ref in (("D", ed["D"]), ("ekin", ed["H0"] / m.N), ("Szz_G", ed["SzzG"])):
+        per_sweep.append({k: np.mean([s[k] for s in ch.samples[n0:]])
+                          for k in ("D", "ekin", "Szz_G", "Szz_dk")})
+    for key, ref in (("D", ed["D"]), ("ekin", ed["H0"] / m.N), ("Szz_G", ed["SzzG"]),
+                     ("Szz_dk", ed["Szzdk"])):
         x = np.array([p[key] for p in per_sweep])
         mu, err = stats.mean_err(x)
         assert abs(mu - ref) < 4 * err, (key, mu, ref, err)
+    # R_m2 = 1 - <S_zz(b1/L)> / <S_zz(Gamma)> (eq. CrfRatio): a ratio of means,
+    # its error from a jackknife over 50 blocks of sweeps
+    a = np.array([p["Szz_dk"] for p in per_sweep])
+    b = np.array([p["Szz_G"] for p in per_sweep])
+    nb = 50
+    a_b = a[: len(a) // nb * nb].reshape(nb, -1).mean(axis=1)
+    b_b = b[: len(b) // nb * nb].reshape(nb, -1).mean(axis=1)
+    r = 1.0 - a_b.mean() / b_b.mean()
+    jk = np.array([1.0 - (a_b.sum() - a_b[j]) / (b_b.sum() - b_b[j]) for j in range(nb)])
+    err = np.sqrt((nb - 1) / nb * np.sum((jk - jk.mean()) ** 2))
+    ref = 1.0 - ed["Szzdk"] / ed["SzzG"]
+    assert abs(r - ref) < 4 * err, ("Rm2", r, ref, err)
 
 
 # ---- statistics helpers ---------------------------------------------------------------------
