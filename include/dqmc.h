@@ -39,9 +39,12 @@
  * NULL selects the handle's stream.
  *
  * Errors: every call returns a dqmc_status; nothing is thrown.  Argument
- * errors return without side effects.  DQMC_ENUMERIC reports a non-finite or
- * zero acceptance ratio seen on the device; the handle remains usable for
- * dqmc_get_stats and dqmc_destroy.  dqmc_last_error gives a message.
+ * errors return without side effects.  DQMC_ENUMERIC reports, from
+ * dqmc_measure and dqmc_get_stats (which still fill their output), that the
+ * device saw a non-finite or zero acceptance ratio or a recomputation whose
+ * drift max |G_wrap - G_scratch| exceeded the tolerance (dqmc_set_drift_tol);
+ * dqmc_stats.numeric_err says which (bit 1 ratio, bit 2 drift).  The handle
+ * remains usable.  dqmc_last_error gives a message.
  */
 #ifndef DQMC_H
 #define DQMC_H
@@ -88,17 +91,38 @@ typedef struct {
   uint64_t seed;        /* Philox key */
 } dqmc_instance_desc;
 
-/* Means over all measurements since creation or the last dqmc_reset_obs. */
+/* Equal-time estimators (Sec. II C, Sec. IV C), means over all measurements
+ * since creation or the last dqmc_reset_obs.  A measurement is taken on the
+ * recomputed G at every stabilisation point of both passes (on
+ * exp(-dtau K/2) G exp(+dtau K/2) for sym_measure = 1, the symmetric Trotter
+ * split of Sec. II B), by Wick's theorem from G_up and G_dn = P (1 - G_up^dagger) P:
+ *   n       <n_up + n_dn> per site (1 at half filling);
+ *   D       double occupancy (1/N_s) sum_i <n_i,up n_i,dn>;
+ *   ekin    <H_0> / N_s;  e = ekin + U D, the energy per site of Sec. IV C;
+ *   Szz_G, Szz_dk  S_zz(k) of eq. SpinStrucF at k = 0 and k = b1/L, built from
+ *           the intra-sublattice correlation C_zz(r) of eq. SzSzCrF;
+ *   m2      S_zz(Gamma) / (2 N_c);
+ *   Rm2     1 - Szz_dk / Szz_G from the means (eq. CrfRatio);
+ *   phase_cos, phase_sin  mean of exp(i arg det(1 + B_M..B_1)) of spin up.
+ *           The weight det_up det_dn is real and non-negative (det_dn is the
+ *           complex conjugate of det_up up to a positive factor, Sec. II B);
+ *           the phase of det_up alone is tracked per accepted flip and
+ *           re-anchored from the UDV factors at every recomputation. */
 typedef struct {
   double n, D, ekin, e, Szz_G, Szz_dk, m2, Rm2, phase_cos, phase_sin;
   int64_t n_meas;
 } dqmc_obs;
 
+/* Counters since creation or the last dqmc_reset_obs (sweeps: since creation).
+ * drift_last: max |G_wrap - G_scratch| of the most recent recomputation of G,
+ * drift_max: the largest so far.  phase_re/im: current exp(i arg det_up);
+ * phase_drift: largest |tracked - anchored| phase at a recomputation. */
 typedef struct {
   int64_t proposals, accepted, flushes, sweeps;
   double drift_max, drift_last;
   int32_t numeric_err;
   int64_t learn_proposals, learn_accepted;  /* learned multi-site moves */
+  double phase_re, phase_im, phase_drift;
 } dqmc_stats;
 
 /* Bytes of device workspace for n instances (ws: output). */
@@ -117,8 +141,14 @@ dqmc_status dqmc_destroy(dqmc_handle h);
 dqmc_status dqmc_set_fields(dqmc_handle h, int32_t inst, const int8_t* host_x);
 dqmc_status dqmc_get_fields(dqmc_handle h, int32_t inst, int8_t* host_x);
 
-/* n_sweeps full sweeps of every instance; estimators are accumulated at every
- * recomputation of G when measure != 0.  Asynchronous on the stream. */
+/* n_sweeps full sweeps of every instance (Sec. III: an upward pass l = 1..M,
+ * wrap then single-site updates of slice l, and a downward pass l = M..1,
+ * updates then wrap; G recomputed from the UDV chains after every n_stab
+ * slices, eq. GrFMat); estimators are accumulated at every recomputation of
+ * G when measure != 0.  Instances with fewer slices than the largest M of
+ * the handle sweep proportionally more often in the same call.  Asynchronous
+ * on the stream; errors of the device side surface as DQMC_ENUMERIC from
+ * dqmc_measure / dqmc_get_stats. */
 dqmc_status dqmc_sweep(dqmc_handle h, int32_t n_sweeps, int32_t measure, void* stream);
 
 /* Replay mode: the Metropolis decision for proposal n of instance i is
@@ -130,8 +160,13 @@ dqmc_status dqmc_sweep(dqmc_handle h, int32_t n_sweeps, int32_t measure, void* s
 dqmc_status dqmc_replay(dqmc_handle h, const uint8_t* dev_bits, int64_t bits_per_inst,
                         double* dev_ratios, int32_t n_sweeps, int32_t measure, void* stream);
 
-/* G of instance inst, spin 0 (up) or 1 (down: P (1 - G_up^dagger) P with
- * P = diag(+1 on A, -1 on B)), row-major; synchronises. */
+/* G of instance inst, the equal-time Green's function of eq. GrFMat,
+ * G_ij = <c_i c_j^dagger> = (1 + B_l..B_1 B_M..B_{l+1})^{-1} at the current
+ * slice l of the instance's sweep (l = 0 between sweeps), spin 0 (up) or 1
+ * (down: P (1 - G_up^dagger) P with P = diag(+1 on A, -1 on B), the
+ * particle-hole partner of Sec. II B in the original basis).  host_out:
+ * N x N row-major, real doubles or interleaved (re, im) for twisted
+ * handles; caller-allocated.  Synchronises the handle's stream. */
 dqmc_status dqmc_get_green(dqmc_handle h, int32_t inst, int32_t spin, double* host_out);
 /* Overwrite G (spin up) of instance inst (row-major, same element format). */
 dqmc_status dqmc_set_green(dqmc_handle h, int32_t inst, const double* host_in);
@@ -148,13 +183,23 @@ dqmc_status dqmc_wrap(dqmc_handle h, int32_t dir, int32_t slice, void* stream);
 dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
                             const double* host_Y, int32_t k);
 
-dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out);  /* synchronises */
+/* Estimator means of instance inst (see dqmc_obs); synchronises.
+ * DQMC_ENUMERIC (out still filled) if the instance hit a numerical error. */
+dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out);
+/* Restart the estimator means and the counters of dqmc_stats (proposals,
+ * accepted, flushes, drifts, learned moves) and clear numeric_err. */
 dqmc_status dqmc_reset_obs(dqmc_handle h);
 /* Per-sweep means of the estimators in the order of dqmc_obs (10 doubles per
  * sweep), most recent max_sweeps at most, oldest first; *n_out = sweeps written. */
 dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32_t max_sweeps,
                             int32_t* n_out);
-dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out);  /* synchronises */
+/* Counters of instance inst; synchronises.  DQMC_ENUMERIC (out still
+ * filled) if numeric_err is set. */
+dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out);
+/* Tolerance of the recomputation drift max |G_wrap - G_scratch| of every
+ * instance (default 1e-4): a larger drift sets numeric_err bit 2.
+ * DQMC_EINVAL unless tol > 0.  Synchronises. */
+dqmc_status dqmc_set_drift_tol(dqmc_handle h, double tol);
 
 /* Live kernel timing with HIP events on the handle's stream.  While enabled,
  * every launch of the classes below is bracketed by an event pair; times are

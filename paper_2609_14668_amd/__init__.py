@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64), ("flushes", ctypes.c_int64),
                 ("sweeps", ctypes.c_int64), ("drift_max", ctypes.c_double), ("drift_last", ctypes.c_double),
                 ("numeric_err", ctypes.c_int32), ("learn_proposals", ctypes.c_int64),
-                ("learn_accepted", ctypes.c_int64)]
+                ("learn_accepted", ctypes.c_int64), ("phase_re", ctypes.c_double), ("phase_im", ctypes.c_double),
+                ("phase_drift", ctypes.c_double)]
 
 
 TIMING_CLASSES = ("wrap", "window", "expand", "flush", "stab", "measure", "learn")
@@ -71,6 +72,7 @@ _SIGS = {
     "dqmc_reset_obs": [_P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
+    "dqmc_set_drift_tol": [_P, ctypes.c_double],
     "dqmc_shape": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                    ctypes.POINTER(ctypes.c_int32)],
     "dqmc_set_timing": [_P, ctypes.c_int32],
@@ -272,12 +274,21 @@ class Simulation:
 
     series = dqmc_get_series
 
-    def dqmc_get_stats(self, inst=0):
+    def dqmc_get_stats(self, inst=0, check=False):
+        """Counters of one instance.  DQMC_ENUMERIC still fills them: it is
+        raised only with check=True, else reported in numeric_err."""
         s = Stats()
-        self._chk(self.lib.dqmc_get_stats(self.h, inst, ctypes.byref(s)), "stats")
+        st = self.lib.dqmc_get_stats(self.h, inst, ctypes.byref(s))
+        if st != DQMC_OK and (check or st != -4):
+            self._chk(st, "stats")
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     stats = dqmc_get_stats
+
+    def dqmc_set_drift_tol(self, tol):
+        self._chk(self.lib.dqmc_set_drift_tol(self.h, float(tol)), "set_drift_tol")
+
+    set_drift_tol = dqmc_set_drift_tol
 
     def dqmc_set_timing(self, on=True):
         self._chk(self.lib.dqmc_set_timing(self.h, int(bool(on))), "set_timing")

@@ -148,7 +148,17 @@ struct InstState {
   int64_t series_base;   // sweep index at the last reset of the estimators
   int64_t learn_props, learn_acc;  // learned multi-site moves proposed / accepted
   int64_t collect_n;               // training samples stored by this instance
+  // phase of det(1 + B_M .. B_1) of spin up: updated by r_up / |r_up| at every
+  // accepted flip (by the phase of the block determinant for a multi-site
+  // move) and re-anchored from the UDV factors at every recomputation
+  double ph_re, ph_im;
+  double phw_re, phw_im;           // phase of det U of the working UDV chain
+  double ph_drift;                 // max |tracked - anchored| phase over recomputations
+  double drift_acc;                // running max of the recomputation in progress
 };
+// numeric_err bits
+constexpr int NUMERR_RATIO = 1;    // non-finite or zero acceptance ratio
+constexpr int NUMERR_DRIFT = 2;    // drift max |G_wrap - G_scratch| above the tolerance
 
 // One learned multi-site proposal in flight (at most LEARN_MMAX sites).
 // Coefficient tables hold S-typed values (two doubles per complex entry).
@@ -159,6 +169,7 @@ struct LearnState {
   int32_t valid;                               // 0: the block ratio was not usable
   double logq;                                 // log q(S | X)
   double R;                                    // block weight ratio R_S
+  double ph[2];                                // phase of prod_k r_k (the block determinant of spin up)
   double c[LEARN_MMAX][2];                     // Delta_k / r_k
   double xw[LEARN_MMAX][LEARN_MMAX][2];        // x_k at S positions a > k
   double yw[LEARN_MMAX][LEARN_MMAX][2];        // y_k at S positions b > k
@@ -185,6 +196,7 @@ struct InstDev {
   int32_t fft_fixed;        // 1: a compile-time FFT plan exists for L
   int32_t mixed;            // 1: wraps and flushes in single precision
   double lam;               // HS coupling lambda
+  double drift_tol;         // recomputation drift above this sets NUMERR_DRIFT
   double U, dtau, t;
   double theta1, theta2;
   uint64_t seed;
@@ -193,6 +205,7 @@ struct InstDev {
   char* stackU;             // slot c at stackU + c*mat_bytes
   char* stackT;
   double* stackD;           // slot c at stackD + c*N
+  double* stackPh;          // slot c: phase of det U at stackPh[2c], stackPh[2c+1]
   size_t mat_bytes;
   int8_t* fields;           // M x N, x_{l,i} at fields[(l-1)*N + i]
   const cplx* tab;          // 4 tables x Nc x (2x2): exp(-dtau h)/Nc, exp(+dtau h)/Nc, half steps

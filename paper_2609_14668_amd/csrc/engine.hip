@@ -31,6 +31,9 @@ constexpr int TRSM_ROWS = 32;
 constexpr int GROUPS_MAX = 4;   // instance groups on separate streams
 constexpr int MAX_SERIES = 4096;
 constexpr int MAX_DELAY = 192;
+// Default tolerance of max |G_wrap - G_scratch| at a recomputation.  FP64
+// sweeps of the workloads here stay below 1e-6 (L = 3 .. 42, n_stab = 10).
+constexpr double DRIFT_TOL_DEFAULT = 1e-4;
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -54,7 +57,7 @@ struct Offs {
   size_t st, obs, series, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn, rsplit;
   size_t vec[VEC_COUNT];
   size_t mat[MAT_COUNT];
-  size_t stackU, stackT, stackD;
+  size_t stackU, stackT, stackD, stackPh;
   size_t end;
 };
 
@@ -136,6 +139,7 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.stackU = o; o = al(o + mb * (C + 1));
     f.stackT = o; o = al(o + mb * (C + 1));
     f.stackD = o; o = al(o + sizeof(double) * N * (C + 1));
+    f.stackPh = o; o = al(o + sizeof(double) * 2 * (C + 1));
     f.end = o;
     p.offs.push_back(f);
   }
@@ -236,6 +240,13 @@ namespace {
 dqmc_status fail(dqmc_ctx* h, dqmc_status s, const std::string& msg) {
   if (h) h->err = msg;
   return s;
+}
+
+std::string numeric_message(int bits) {
+  std::string m;
+  if (bits & NUMERR_RATIO) m += "non-finite or zero acceptance ratio";
+  if (bits & NUMERR_DRIFT) m += std::string(m.empty() ? "" : "; ") + "recomputation drift above the tolerance";
+  return m;
 }
 
 #define HIPCHK(h, x)                                                                  \
@@ -394,6 +405,7 @@ void stabilise(Ctx& c, bool measure) {
   c.elem(EO_GATHER_COLS, MAT_UW, 0, MAT_QA);
   c.elem(EO_GATHER_ROWS, MAT_TW, 0, MAT_W3);
   qr_factor(c);
+  c.chk(launch_detphase(c.di, c.n, h->cplx, 0, c.s));
   c.chk(launch_diag_abs(c.di, c.n, h->Nmax, h->cplx, c.s));
   c.gemm(opnd(MAT_QA, 0), opnd(MAT_W3, 0), opnd(MAT_TW, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0,
          GF_A_UPPER);
@@ -406,15 +418,19 @@ void stabilise(Ctx& c, bool measure) {
   c.elem(EO_BUILD_Y, MAT_W1, MAT_W2, MAT_QA);
   c.elem(EO_BUILD_RHS, 0, 0, MAT_W3);
   qr_factor(c);
+  c.chk(launch_detphase(c.di, c.n, h->cplx, 1, c.s));
   apply_qh(c, MAT_W3);
   upper_solve(c);
   c.elem(EO_SCALE_ROWS_DLB, 0, 0, MAT_W3);
   c.gemm(opnd(MAT_LU, 0), opnd(MAT_W3, 0), opnd(MAT_GS, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
   c.elem(EO_DRIFT_REPLACE);
+  c.chk(launch_stab_finish(c.di, c.n, c.s));
   c.elem(EO_STACK_STORE);
   if (measure) {
+    // instances with sym_measure = 1 measure on the half-step G~, the others
+    // on G (the half-step launches skip them; MAT_GS holds a copy of G)
     bool sym = false;
-    for (auto& d : h->desc) sym = sym || d.sym_measure;
+    for (int i = c.off; i < c.off + c.n; ++i) sym = sym || h->desc[i].sym_measure;
     if (sym) {
       c.elem(EO_COPY, MAT_G, 0, MAT_GS);
       c.fft(FOP_HALF, 0, MAT_GS);
@@ -583,7 +599,7 @@ const char* dqmc_status_string(dqmc_status s) {
     case DQMC_EINVAL: return "invalid argument";
     case DQMC_ENOMEM: return "workspace too small";
     case DQMC_EHIP: return "HIP runtime error";
-    case DQMC_ENUMERIC: return "numerical failure (non-finite or zero ratio)";
+    case DQMC_ENUMERIC: return "numerical failure (non-finite or zero ratio, or drift above the tolerance)";
     case DQMC_ESTATE: return "invalid state";
     case DQMC_EUNSUPPORTED: return "unsupported size or option";
   }
@@ -716,6 +732,8 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.stackU = b + f.stackU;
     dv.stackT = b + f.stackT;
     dv.stackD = (double*)(b + f.stackD);
+    dv.stackPh = (double*)(b + f.stackPh);
+    dv.drift_tol = DRIFT_TOL_DEFAULT;
     dv.mat_bytes = ss * (size_t)dv.N * dv.N;
     dv.fields = (int8_t*)(b + f.fields);
     dv.tab = (const cplx*)(b + f.tab);
@@ -1160,7 +1178,7 @@ dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out) {
     out->phase_cos = obs[OBS_PHASE_RE] / n;
     out->phase_sin = obs[OBS_PHASE_IM] / n;
   }
-  if (st.numeric_err) return fail(h, DQMC_ENUMERIC, "non-finite or zero ratio encountered");
+  if (st.numeric_err) return fail(h, DQMC_ENUMERIC, numeric_message(st.numeric_err));
   return DQMC_OK;
 }
 
@@ -1245,6 +1263,19 @@ dqmc_status dqmc_get_stats(dqmc_handle h, int32_t inst, dqmc_stats* out) {
   out->numeric_err = st.numeric_err;
   out->learn_proposals = st.learn_props;
   out->learn_accepted = st.learn_acc;
+  out->phase_re = st.ph_re;
+  out->phase_im = st.ph_im;
+  out->phase_drift = st.ph_drift;
+  if (st.numeric_err) return fail(h, DQMC_ENUMERIC, numeric_message(st.numeric_err));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_drift_tol(dqmc_handle h, double tol) {
+  if (!h || !(tol > 0.0)) return DQMC_EINVAL;
+  for (auto& d : h->hd) d.drift_tol = tol;
+  dqmc_status st = upload_insts(h, h->stream);
+  if (st != DQMC_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   return DQMC_OK;
 }
 

@@ -58,7 +58,8 @@ __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) 
       }
       return r;
     }
-    case FOP_HALF:  // G~ = e^{-dtau K/2} G e^{+dtau K/2}
+    case FOP_HALF:  // G~ = e^{-dtau K/2} G e^{+dtau K/2} (instances that measure on it)
+      if (!d.sym_measure) return r;
       r.active = 1; r.slice = 0;
       r.tab = (a.side == 0) ? TAB_HP : TAB_HM;
       return r;

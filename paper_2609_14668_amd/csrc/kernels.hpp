@@ -95,6 +95,10 @@ hipError_t launch_apply_refl2(const InstDev* insts, int n_inst, int Nmax, bool c
                               int use_th, hipStream_t s);
 hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int p, int target, int cols,
                              int use_th, hipStream_t s);
+// drift of the recomputation just made: drift_last, drift_max, tolerance check
+hipError_t launch_stab_finish(const InstDev* insts, int n_inst, hipStream_t s);
+// phase of det U of the chain step (mode 0) / anchored phase of det(1 + B..B) (mode 1)
+hipError_t launch_detphase(const InstDev* insts, int n_inst, bool cplx_, int mode, hipStream_t s);
 hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
 hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int blk, hipStream_t s);
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);

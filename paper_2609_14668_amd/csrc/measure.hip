@@ -8,6 +8,10 @@
 // D = mean a_i b_i; <H_0> = -2 Re Tr(K G); e = <H_0>/N_s + U D
 // (Sec. IV C); S_zz(k) of eq. SpinStrucF from the intra-sublattice
 // correlations of eq. SzSzCrF at k = 0 and k = b1/L; m^2 = S_zz(0)/(2 N_c).
+// The weight det_up det_dn is real and non-negative, since det_dn is the
+// complex conjugate of det_up up to a positive factor (Sec. II B); the phase
+// of det_up itself (tracked per accepted flip, anchored at every
+// recomputation) is recorded with each measurement.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -145,7 +149,7 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
     double v[OBS_COUNT] = {0};
     v[OBS_N] = n; v[OBS_D] = D; v[OBS_EKIN] = ekin; v[OBS_E] = e;
     v[OBS_SZZ_G] = SG; v[OBS_SZZ_DK] = Sdk; v[OBS_M2] = SG / (2.0 * Nc);
-    v[OBS_RM2_NUM] = Sdk; v[OBS_PHASE_RE] = 1.0; v[OBS_PHASE_IM] = 0.0;
+    v[OBS_RM2_NUM] = Sdk; v[OBS_PHASE_RE] = st->ph_re; v[OBS_PHASE_IM] = st->ph_im;
     for (int k = 0; k < OBS_COUNT; ++k) {
       d.obs[k] += v[k];
       d.obs[OBS_COUNT + k] += v[k];

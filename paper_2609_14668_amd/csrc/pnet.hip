@@ -635,6 +635,7 @@ __global__ void __launch_bounds__(LP_THREADS) k_learn_propose(const InstDev* __r
     LearnState* ls = d.learn;
     const double lam = d.lam;
     double R = 1.0;
+    double pre = 1.0, pim = 0.0;   // phase of prod_k r_k
     int valid = 1;
     for (int k = 0; k < m; ++k) ls->S[k] = Ssh[k];
     for (int k = 0; k < m; ++k) {
@@ -645,6 +646,12 @@ __global__ void __launch_bounds__(LP_THREADS) k_learn_propose(const InstDev* __r
       const double ar = absq(r);
       if (!(ar > 0.0) || !(ar < 1e300)) valid = 0;
       R *= exp(2.0 * lam * x) * ar;
+      if (ar > 0.0) {
+        const double sa = sqrt(ar), qr = real_part(r) / sa, qi = imag_part(r) / sa;
+        const double a = pre, b = pim;
+        pre = a * qr - b * qi;
+        pim = a * qi + b * qr;
+      }
       const S cf = valid ? cdiv(dl, r) : ST<S>::zero();
       put_s(ls->c[k], cf);
       S xv[LEARN_MMAX], yv[LEARN_MMAX];
@@ -658,6 +665,8 @@ __global__ void __launch_bounds__(LP_THREADS) k_learn_propose(const InstDev* __r
         for (int b = k + 1; b < m; ++b) Cs[a][b] = Cs[a][b] - xv[a] * yv[b];
     }
     ls->m = m;
+    ls->ph[0] = pre;
+    ls->ph[1] = pim;
     ls->valid = valid && !bad_sh && (R == R) && R < 1e300;
     ls->R = R;
     ls->logq = log_q_of(z, Ssh, m, Nc, zmax, tot);
@@ -710,6 +719,9 @@ __global__ void __launch_bounds__(LP_THREADS) k_learn_decide(const InstDev* __re
       }
       st->m_w = m;
       st->wstart = 0;
+      const double a = st->ph_re, b = st->ph_im;
+      st->ph_re = a * ls->ph[0] - b * ls->ph[1];
+      st->ph_im = a * ls->ph[1] + b * ls->ph[0];
     } else {
       st->m_w = 0;
     }

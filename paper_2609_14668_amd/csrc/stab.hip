@@ -123,6 +123,10 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
     case EO_STACK_STORE: {
       int c = sched_ckpt(st->phase, d.M, d.n_stab);
       if (c < 1 || c > d.n_ckpt - 1) break;
+      if (e0 == 0) {
+        d.stackPh[2 * c] = st->phw_re;
+        d.stackPh[2 * c + 1] = st->phw_im;
+      }
       const S* u = matp<S>(d, MAT_UW);
       const S* t = matp<S>(d, MAT_TW);
       S* su = matp<S>(d, MAT_SU);
@@ -144,6 +148,10 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
         stt[x] = v;
       }
       for (size_t x = e0; x < (size_t)N * (d.n_ckpt + 1); x += stride) d.stackD[x] = 1.0;
+      for (size_t x = e0; x < (size_t)(d.n_ckpt + 1); x += stride) {
+        d.stackPh[2 * x] = 1.0;
+        d.stackPh[2 * x + 1] = 0.0;
+      }
       break;
     }
     case EO_RESET_CHAIN: {
@@ -179,10 +187,7 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
       }
       if (!st->init_mode) {
         for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-        if ((threadIdx.x & 63) == 0) {
-          atomic_max_pos(&st->drift_last, m);
-          atomic_max_pos(&st->drift_max, m);
-        }
+        if ((threadIdx.x & 63) == 0) atomic_max_pos(&st->drift_acc, m);
       }
       break;
     }
@@ -1179,7 +1184,118 @@ __global__ void __launch_bounds__(256) k_trsm_diag(const InstDev* __restrict__ i
     if (r < nr) B[(i0 + r) + (size_t)j * N] = z[r];
 }
 
+// After the drift of a recomputation has been accumulated (EO_DRIFT_REPLACE):
+// drift_last = this recomputation's max |G_wrap - G_scratch|, drift_max the
+// running maximum, NUMERR_DRIFT when it exceeds the instance's tolerance.
+__global__ void k_stab_finish(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  InstState* st = d.st;
+  if (threadIdx.x != 0 || st->idle) return;
+  const double dl = st->drift_acc;
+  st->drift_acc = 0.0;
+  if (st->init_mode) return;
+  st->drift_last = dl;
+  st->drift_max = fmax(st->drift_max, dl);
+  if (!(dl <= d.drift_tol)) atomicOr(&st->numeric_err, NUMERR_DRIFT);
+}
+
+// Phase of a determinant from a Householder QR in MAT_QA / VEC_TAU.  A
+// reflector H = 1 - tau v v^H with tau = (beta - alpha)/beta (beta real) has
+// det H = 1 - tau |v|^2 = -tau / conj(tau) (1 when tau = 0), and
+// det Q = prod_j det H_j.
+//   mode 0 (after the chain step's QR A P = Q R): the working chain's new U is
+//          Q, so phw = phase det Q.
+//   mode 1 (after the QR Y = Q_Y R_Y of the recomputation): with
+//          1 + R L = U_R D_Rb Y D_Lb U_L^dagger (D positive), the phase of
+//          det(1 + B_M .. B_1) = det(1 + R L) (cyclic invariance) is
+//          ph(det U_R) ph(det Q_Y) prod_i ph(R_Y,ii) conj(ph(det U_L)).  It
+//          replaces the tracked phase; the difference is recorded.
+template <typename S>
+__global__ void __launch_bounds__(256) k_detphase(const InstDev* __restrict__ insts, int mode) {
+  const InstDev& d = insts[blockIdx.y];
+  InstState* st = d.st;
+  if (st->idle) return;
+  const int N = d.N;
+  const double* tauv = d.vec[VEC_TAU];
+  const S* A = matp<S>(d, MAT_QA);
+  double pr = 1.0, pi = 0.0;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const double tr = tauv[2 * j], ti = tauv[2 * j + 1];
+    const double t2 = tr * tr + ti * ti;
+    double fr = 1.0, fi = 0.0;
+    if (t2 > 0.0) {   // -tau^2 / |tau|^2
+      fr = -(tr * tr - ti * ti) / t2;
+      fi = -(2.0 * tr * ti) / t2;
+    }
+    if (mode == 1) {
+      const S rjj = A[j + (size_t)j * N];
+      const double ra = sqrt(absq(rjj));
+      if (ra > 0.0) {
+        const double qr = real_part(rjj) / ra, qi = imag_part(rjj) / ra;
+        const double a = fr, b = fi;
+        fr = a * qr - b * qi;
+        fi = a * qi + b * qr;
+      }
+    }
+    const double a = pr, b = pi;
+    pr = a * fr - b * fi;
+    pi = a * fi + b * fr;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double qr = __shfl_xor(pr, off), qi = __shfl_xor(pi, off);
+    const double a = pr, b = pi;
+    pr = a * qr - b * qi;
+    pi = a * qi + b * qr;
+  }
+  __shared__ double part[2][4];
+  if ((threadIdx.x & 63) == 0) { part[0][threadIdx.x >> 6] = pr; part[1][threadIdx.x >> 6] = pi; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  pr = 1.0; pi = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    const double a = pr, b = pi;
+    pr = a * part[0][w] - b * part[1][w];
+    pi = a * part[1][w] + b * part[0][w];
+  }
+  double nrm = sqrt(pr * pr + pi * pi);
+  if (!(nrm > 0.0)) { pr = 1.0; pi = 0.0; nrm = 1.0; }
+  pr /= nrm; pi /= nrm;
+  if (mode == 0) {
+    st->phw_re = pr;
+    st->phw_im = pi;
+    return;
+  }
+  // U_R, U_L: the working chain and the stack slot, by pass (as MAT_RU / MAT_LU)
+  const int up = sched_is_up(st->phase, d.M);
+  const int c = sched_ckpt(st->phase, d.M, d.n_stab);
+  const double wr = st->phw_re, wi = st->phw_im, sr = d.stackPh[2 * c], si = d.stackPh[2 * c + 1];
+  const double rr = up ? wr : sr, ri = up ? wi : si;   // ph det U_R
+  const double lr = up ? sr : wr, li = up ? si : wi;   // ph det U_L
+  double ar = rr * pr - ri * pi, ai = rr * pi + ri * pr;        // ph(U_R) ph(Y)
+  const double br = ar * lr + ai * li, bi = ai * lr - ar * li;  // times conj ph(U_L)
+  nrm = sqrt(br * br + bi * bi);
+  ar = br / nrm;
+  ai = bi / nrm;
+  if (!st->init_mode) {
+    const double dr = st->ph_re - ar, di = st->ph_im - ai;
+    st->ph_drift = fmax(st->ph_drift, sqrt(dr * dr + di * di));
+  }
+  st->ph_re = ar;
+  st->ph_im = ai;
+}
+
 }  // namespace
+
+hipError_t launch_stab_finish(const InstDev* insts, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_stab_finish, dim3(1, n_inst), dim3(64), 0, s, insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_detphase(const InstDev* insts, int n_inst, bool cplx_, int mode, hipStream_t s) {
+  if (cplx_) hipLaunchKernelGGL(k_detphase<cplx>, dim3(1, n_inst), dim3(256), 0, s, insts, mode);
+  else hipLaunchKernelGGL(k_detphase<double>, dim3(1, n_inst), dim3(256), 0, s, insts, mode);
+  return hipGetLastError();
+}
 
 hipError_t launch_elem(const InstDev* insts, int n_inst, int Nmax, bool cplx_, ElemArgs e, hipStream_t s) {
   size_t NN = (size_t)Nmax * Nmax;

@@ -65,7 +65,7 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
   __shared__ S xcol[WMAX], yrow[WMAX];
   __shared__ int xs[WMAX];
   __shared__ int sh_q, sh_mw;
-  __shared__ S sh_c;
+  __shared__ S sh_c, sh_r;
 
   // ---- C = G[w,w] - X[w,:fill0] Y[:fill0,w]
   // every load below reads a clamped address and is masked afterwards, so
@@ -136,7 +136,7 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
         r = ST<S>::one() + dl * (ST<S>::one() - C[q][q]);
         R = e2x * absq(r);
         acc_q = replay ? rbit : usite < R;
-        if (!(R == R) || R == 0.0 || R > 1e300) st->numeric_err = 1;
+        if (!(R == R) || R == 0.0 || R > 1e300) atomicOr(&st->numeric_err, NUMERR_RATIO);
       }
       unsigned long long mask = __ballot(cand && acc_q);
       int qstar = mask ? (__ffsll((long long)mask) - 1) : wn;
@@ -149,6 +149,7 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
             (float)(q == qstar ? 1.0 / (1.0 + R) : (R < 1e300 ? R / (1.0 + R) : 1.0));
       if (q == qstar && cand) {
         sh_c = cdiv(dl, r);
+        sh_r = r;
       }
       if (lane == 0) sh_q = qstar;
     }
@@ -170,6 +171,15 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
       wc[k] = cfac;
       d.acc_site[k] = qs;
       d.acc_gsite[k] = w0 + qs;
+      // det(1 + B..B) of spin up changes by the factor r_up (eq. rRatioLocal)
+      const S rr = sh_r;
+      const double ra = sqrt(absq(rr));
+      if (ra > 0.0) {
+        const double pr = real_part(rr) / ra, pi = imag_part(rr) / ra;
+        const double a = st->ph_re, b = st->ph_im;
+        st->ph_re = a * pr - b * pi;
+        st->ph_im = a * pi + b * pr;
+      }
     }
     __syncthreads();
     // trailing-block rank-1 update C -= x y^T
@@ -410,6 +420,8 @@ __global__ void k_reset_counters(const InstDev* __restrict__ insts, int n) {
   st->series_base = st->sweep;
   st->learn_props = 0;
   st->learn_acc = 0;
+  st->ph_drift = 0.0;
+  st->numeric_err = 0;
 }
 
 }  // namespace

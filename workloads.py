@@ -52,6 +52,11 @@ def plain_L3(seed=1):
     return [desc(3, 3.8, 3.0, k=8, seed=seed)]
 
 
+def plain_L3_chains(n_chains):
+    """n independent chains of the plain L=3 shape, seeds 1..n."""
+    return [desc(3, 3.8, 3.0, k=8, seed=s) for s in range(1, n_chains + 1)]
+
+
 def plain_L12(n_chains=4):
     return [desc(12, 3.7, 12.0, k=32, seed=s) for s in range(1, n_chains + 1)]
 
@@ -79,8 +84,8 @@ def plain_L42(n_chains=1):
 
 # The paper's Table III/IV points used for a physics pin (PBC, HS in the spin
 # channel, beta t = L, dtau = 0.05, symmetric Trotter measurement).
-def table_point(L, U=3.75):
-    return desc(L, U, float(L), dtau=0.05, sym_measure=1)
+def table_point(L, U=3.75, seed=1):
+    return desc(L, U, float(L), dtau=0.05, sym_measure=1, seed=seed)
 
 
 # ---- proposal network inputs (random weights of the layout [tap][out][in]) ----------
