@@ -297,6 +297,21 @@ dqmc_status dqmc_net_workspace_size(int32_t L, int32_t M, int64_t n_samples, int
 dqmc_status dqmc_net_logits(dqmc_handle h, void* dev_ws, size_t bytes, const int8_t* host_fields, int32_t n,
                             int32_t L, int32_t M, float* host_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the logits
+ * of dqmc_net_logits, computed by the same kernels, with the scratch taken
+ * from a static device array of the library (16 MiB on each GPU it runs on,
+ * held until the process ends) instead of a caller workspace.  Needs
+ * 5 n M N + 224 n M N_c bytes (fields, logits, activations; each part
+ * rounded up to 256 bytes; DQMC_EUNSUPPORTED if above 16 MiB: one L = 18,
+ * M = 180 configuration fits, two do not), n <= 64, and the handle's device
+ * to be current
+ * (DQMC_ESTATE otherwise).  Calls no device allocation routine.  Every call
+ * on one GPU shares the array: calls that overlap on one GPU (several
+ * threads or handles) race.  Synchronises the handle's stream. */
+dqmc_status dqmc_net_logits_noalloc(dqmc_handle h, const int8_t* host_fields, int32_t n, int32_t L, int32_t M,
+                                    float* host_out);
+
 /* Loss and gradient (host, DQMC_NET_NPARAM floats) over a batch of n <= 64
  * samples.  window = 0: whole configurations (n x M x N) with targets for
  * every site (n x M x N floats).  window = 1: 7-slice windows (n x 7 x N,

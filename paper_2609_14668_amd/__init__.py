@@ -85,6 +85,7 @@ _SIGS = {
     "dqmc_net_workspace_size": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_size_t)],
     "dqmc_net_logits": [_P, _P, ctypes.c_size_t, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_net_logits_noalloc": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_net_grad": [_P, _P, ctypes.c_size_t, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_int32, _P, _P],
     "dqmc_collect": [_P, ctypes.c_int32],
@@ -358,6 +359,18 @@ class Simulation:
         return out
 
     net_logits = dqmc_net_logits
+
+    def dqmc_net_logits_noalloc(self, fields, L):
+        """As net_logits, with the library's static device scratch (no
+        device allocation in the call)."""
+        x = np.ascontiguousarray(fields, dtype=np.int8)
+        n, M, N = x.shape
+        out = np.empty((n, M, N), dtype=np.float32)
+        self._chk(self.lib.dqmc_net_logits_noalloc(self.h, x.ctypes.data, n, L, M, out.ctypes.data),
+                  "net_logits_noalloc")
+        return out
+
+    net_logits_noalloc = dqmc_net_logits_noalloc
 
     def dqmc_net_grad(self, fields, targets, L, window=False):
         """window=False: configurations (n, M, N) with targets (n, M, N);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -233,6 +234,7 @@ struct dqmc_ctx {
   double wrap_bytes = 0;
   std::vector<int64_t> rank_base;   // flush_rank_sum at timing reset
   int64_t sweeps_done = 0;
+  int device = 0;                   // HIP device the handle was created on
 };
 
 namespace {
@@ -798,6 +800,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     }
   }
   int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) == hipSuccess) h->device = dev;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     h->lds_budget = std::min<size_t>(65536, (size_t)lds);
@@ -1672,3 +1675,80 @@ dqmc_status dqmc_net_train(dqmc_handle h, void* dev_ws, size_t bytes, int32_t st
 }
 
 }  // extern "C"
+
+// ---- Allocation-free network inference --------------------------------------------------
+// dqmc_net_logits_noalloc runs the same kernels as dqmc_net_logits with the
+// forward scratch (fields, activations, logits) in this file-scope device
+// array instead of a caller workspace.  Each GPU holds its own copy, whose
+// address is looked up once per device; every call on a device shares it.
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;   // 16 MiB
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {nullptr};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Forward-only layout of n configurations of size (L, M) in the scratch:
+// the inputs, the logits and the activations of net_pass without a loss.
+bool net_plan_forward(int L, int M, int n, NetPlan& p) {
+  if (L < 2 || L > 45 || M < 1 || n < 1 || n > NET_MAXBATCH) return false;
+  p = NetPlan();
+  p.L = L; p.M = M; p.Nc = L * L; p.N = 2 * p.Nc; p.batch = n; p.n_samples = n;
+  const size_t vox = (size_t)M * p.Nc, B = n;
+  size_t o = 0;
+  p.fields = o; o = al(o + B * M * p.N);
+  p.targets = o; o = al(o + sizeof(float) * B * M * p.N);   // logits out
+  p.a0 = o; o = al(o + 2 * B * vox * 16);
+  p.h1 = o; o = al(o + 2 * B * vox * 32);
+  p.h2 = o; o = al(o + 2 * B * vox * 32);
+  p.z = o; o = al(o + 4 * B * vox * 16);
+  p.total = o;
+  return true;
+}
+
+}  // namespace
+
+extern "C" dqmc_status dqmc_net_logits_noalloc(dqmc_handle h, const int8_t* host_fields, int32_t n, int32_t L,
+                                               int32_t M, float* host_out) {
+  NetPlan p;
+  if (!h || !host_fields || !host_out || !net_plan_forward(L, M, n, p)) return DQMC_EINVAL;
+  if (p.total > NOALLOC_SCRATCH_BYTES)
+    return fail(h, DQMC_EUNSUPPORTED, "net_logits_noalloc: " + std::to_string(p.total) +
+                                          " bytes of scratch needed, the static scratch holds " +
+                                          std::to_string(NOALLOC_SCRATCH_BYTES));
+  int dev = -1;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev != h->device) return fail(h, DQMC_ESTATE, "net_logits_noalloc: current device is not the handle's");
+  void* base = nullptr;
+  HIPCHK(h, scratch_address(dev, &base));
+  hipStream_t s = h->stream;
+  char* ws = (char*)base;
+  dqmc_status st = net_upload(h, p, ws, host_fields, nullptr, s);
+  if (st != DQMC_OK) return st;
+  BatchIdx idx{};
+  idx.n = n;
+  for (int b = 0; b < n; ++b) idx.idx[b] = b;
+  HIPCHK(h, net_pass(h, p, ws, idx, false, false, 0, s));
+  float* out = (float*)(ws + p.targets);
+  HIPCHK(h, launch_net_logits_out((const float*)(ws + p.z), idx, p.N, p.Nc, M, out, s));
+  HIPCHK(h, hipMemcpyAsync(host_out, out, sizeof(float) * (size_t)n * M * p.N, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return DQMC_OK;
+}
