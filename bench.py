@@ -46,8 +46,8 @@ def measured_traffic(workload, k, kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="twist_L18")
     ap.add_argument("--k", type=int, default=None, help="flush rank override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -190,7 +190,35 @@ def tau_int_grouped(series, groups, c=5.0):
     return max(tau, 0.5)
 
 
-def timed_leg(sim, steps, label, learn_m=0, events=True):
+def tau_int_bootstrap(series, groups, n_boot=200, seed=0):
+    """tau_int of the pooled chains and its bootstrap standard error:
+    chains resampled with replacement (within their group), estimator
+    re-evaluated on every resample."""
+    tau = tau_int_grouped(series, groups)
+    if tau is None:
+        return None, None
+    rng = np.random.default_rng(seed)
+    idx_by = {}
+    for i, g in enumerate(groups):
+        idx_by.setdefault(g, []).append(i)
+    taus = []
+    for _ in range(n_boot):
+        pick = []
+        for ids in idx_by.values():
+            pick += list(rng.choice(ids, size=len(ids), replace=True))
+        t = tau_int_grouped([series[i] for i in pick], [groups[i] for i in pick])
+        if t is not None:
+            taus.append(t)
+    return tau, (float(np.std(taus, ddof=1)) if len(taus) > 1 else None)
+
+
+def timed_leg(sim, steps, label, learn_m=0, events=False):
+    """`steps` sweeps timed with the host clock around synchronised calls
+    (events=False: no per-launch events, the handle's instance groups and
+    graphs, as the throughput is measured); events=True instead records the
+    per-kernel-class HIP-event timing (one instance group, eager launches).
+    Effective samples count only the chains of the largest L (the workload's
+    headline size): sum over them of sweeps/s / (2 tau_int[m2])."""
     import torch
     n = sim.n
     sim.reset_obs()
@@ -209,11 +237,16 @@ def timed_leg(sim, steps, label, learn_m=0, events=True):
     d = lambda k: sum(st1[i][k] - st0[i][k] for i in range(n))
     props, acc, sweeps = d("proposals"), d("accepted"), d("sweeps")
     lprops, lacc = d("learn_proposals"), d("learn_accepted")
-    groups = [(x["L"], round(x["theta1"], 9), round(x["theta2"], 9)) for x in sim.descs]
-    tau = tau_int_grouped([sim.series(i)["m2"] for i in range(n)], groups)
+    Lmax = max(x["L"] for x in sim.descs)
+    big = [i for i, x in enumerate(sim.descs) if x["L"] == Lmax]
+    groups = [(sim.descs[i]["L"], round(sim.descs[i]["theta1"], 9), round(sim.descs[i]["theta2"], 9)) for i in big]
+    tau, tau_err = tau_int_bootstrap([sim.series(i)["m2"] for i in big], groups)
+    sweeps_big = sum(st1[i]["sweeps"] - st0[i]["sweeps"] for i in big)
+    ess = (sweeps_big / dt / (2 * tau)) if tau else None
+    ess_err = (ess * tau_err / tau) if (tau and tau_err) else None
     return {"dt": dt, "tim": tim, "props": props, "acc": acc, "sweeps": sweeps, "lprops": lprops, "lacc": lacc,
-            "value": (props + learn_m * lprops) / dt, "tau_m2": tau,
-            "ess_per_s": (sweeps / dt / (2 * tau)) if tau else None,
+            "value": (props + learn_m * lprops) / dt, "tau_m2": tau, "tau_m2_err": tau_err,
+            "ess_per_s": ess, "ess_per_s_err": ess_err, "ess_chains": len(big), "ess_L": Lmax,
             "drift": max(s["drift_max"] for s in st1)}
 
 
@@ -274,7 +307,7 @@ def main():
     sim.collect(0)
     # throughput without per-launch events (both instance groups overlap);
     # then one sweep with live HIP-event timing for the per-kernel rooflines
-    plain = timed_leg(sim, a.steps, "plain", events=False)
+    plain = timed_leg(sim, a.steps, "plain")
     dt = plain["dt"]
     tim = timed_leg(sim, 1, "profiled", events=True)["tim"] if not a.no_timing else plain["tim"]
     line = {
@@ -295,7 +328,10 @@ def main():
                    "dtau": descs[0]["dtau"], "proposal": "plain"},
         "autotune": tuned,
         "ess_per_s": plain["ess_per_s"],
+        "ess_per_s_err": plain["ess_per_s_err"],
+        "ess_over": "%d chains of L=%d" % (plain["ess_chains"], plain["ess_L"]),
         "tau_int_m2_sweeps": plain["tau_m2"],
+        "tau_int_m2_err": plain["tau_m2_err"],
         "acceptance": plain["acc"] / max(plain["props"], 1),
         "drift_max": plain["drift"],
     }
@@ -346,17 +382,21 @@ def main():
             a.train_steps, f, train_s, losses[:20].mean(), losses[-20:].mean()), file=sys.stderr, flush=True)
         sim.set_proposals(a.learn_per_slice, a.learn_m)
         lg = timed_leg(sim, a.steps, "learned", learn_m=a.learn_m)
+        ltim = timed_leg(sim, 1, "learned profiled", learn_m=a.learn_m, events=True)["tim"] \
+            if not a.no_timing else lg["tim"]
         sim.set_proposals(0, 0)
         line["learned"] = {
             "value": lg["value"], "unit": "HS field updates/s (a learned move counts m)",
             "ms_per_step": 1e3 * lg["dt"] / max(a.steps, 1),
-            "ess_per_s": lg["ess_per_s"], "tau_int_m2_sweeps": lg["tau_m2"],
+            "ess_per_s": lg["ess_per_s"], "ess_per_s_err": lg["ess_per_s_err"],
+            "tau_int_m2_sweeps": lg["tau_m2"], "tau_int_m2_err": lg["tau_m2_err"],
             "acceptance_single": lg["acc"] / max(lg["props"], 1),
             "acceptance_learned": lg["lacc"] / max(lg["lprops"], 1),
             "per_slice": a.learn_per_slice, "m": a.learn_m,
             "train": {"steps": a.train_steps, "windows": f, "seconds": train_s,
                       "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
-            "learn_ms": round(lg["tim"]["learn"]["ms"], 1),
+            "time_split_ms": {k: round(ltim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab",
+                                                                    "learn")},
         }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(descs, a.cpu_seconds)
