@@ -22,6 +22,7 @@ import workloads  # noqa: E402
 
 PEAK_FP64 = 78.6e12     # MI355X dense FP64 (vector and matrix), FLOP/s
 PEAK_HBM = 8.0e12       # MI355X HBM3E, B/s
+FLUSH_NAMES = ("direct", "tiled", "queue")
 
 
 def measured_traffic(workload, k, kernel):
@@ -31,7 +32,7 @@ def measured_traffic(workload, k, kernel):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
-    src = {"k_flush_direct": "gemm.hip", "k_gemm<S, 1>": "gemm.hip"}.get(kernel)
+    src = {"k_flush_direct": "gemm.hip", "k_gemm<S, 1>": "gemm.hip", "k_flush_queue": "gemm.hip"}.get(kernel)
     if not src or not os.path.exists(path):
         return None
     with open(os.path.join(ROOT, "paper_2609_14668_amd", "csrc", src), "rb") as f:
@@ -57,7 +58,7 @@ def parse():
     ap.add_argument("--proposal", default="both", choices=("plain", "learned", "both"))
     ap.add_argument("--no-timing", action="store_true", help="no per-launch HIP events (for counter runs)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the workload's flush rank")
-    ap.add_argument("--flush-kernel", choices=("direct", "tiled"), default=None,
+    ap.add_argument("--flush-kernel", choices=("direct", "tiled", "queue"), default=None,
                     help="with --no-autotune: the flush kernel to use")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -288,14 +289,14 @@ def main():
         sim.set_graphs(False)
     tuned = None
     if a.flush_kernel:
-        sim.set_flush_kernel(1 if a.flush_kernel == "tiled" else 0)
+        sim.set_flush_kernel(FLUSH_NAMES.index(a.flush_kernel))
         tuned = {"k": a.k, "flush_kernel": a.flush_kernel, "ms_per_step": None}
     if a.k is None and not a.no_autotune:
         nst = descs[0]["n_stab"]
         cand = [k for k in (16, 24, 32, 48, 64, 96, 128)]
         best, per = sim.autotune(cand, 2 * nst)
-        tuned = {"k": best[0], "flush_kernel": ("direct", "tiled")[best[1]],
-                 "ms_per_step": {"%d/%s" % (k, ("direct", "tiled")[v]): round(t, 3) for (k, v), t in per.items()}}
+        tuned = {"k": best[0], "flush_kernel": FLUSH_NAMES[best[1]],
+                 "ms_per_step": {"%d/%s" % (k, FLUSH_NAMES[v]): round(t, 3) for (k, v), t in per.items()}}
         print("autotuned flush k=%d %s: %s" % (best[0], tuned["flush_kernel"], tuned["ms_per_step"]),
               file=sys.stderr, flush=True)
     for w in range(a.warmup):
@@ -339,7 +340,8 @@ def main():
     fl = tim["flush"]
     if fl["ms"] > 0:
         ach = tim["flush_flops"] / (fl["ms"] * 1e-3)
-        fk = "k_gemm<S, 1>" if (tuned and tuned["flush_kernel"] == "tiled") else "k_flush_direct"
+        fk = {"tiled": "k_gemm<S, 1>", "queue": "k_flush_queue"}.get(tuned["flush_kernel"] if tuned else "direct",
+                                                                    "k_flush_direct")
         kk = tuned["k"] if tuned and tuned.get("k") else descs[0]["n_delay"]
         line["roofline"] = {"bound": "mfma", "kernel": fk, "what": "rank-k flush G -= X Y (k=%d)" % kk,
                             "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",

@@ -179,7 +179,8 @@ dqmc_status dqmc_wrap(dqmc_handle h, int32_t dir, int32_t slice, void* stream);
 /* Rank-k flush G <- G - X Y on instance inst with host X (N x k, column
  * j at X + j*N) and Y (k x N, row m at Y + m*N); elements as for G.
  * Exercises the MFMA flush kernel (eq. FinalDelay) of the handle's
- * precision; synchronises. */
+ * precision and the selected flush kernel (dqmc_set_flush_kernel);
+ * synchronises. */
 dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
                             const double* host_Y, int32_t k);
 
@@ -340,15 +341,18 @@ dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k);
 
 /* Flush kernel: 0 = one wave per 32 x 32 block of G with fragments read
  * straight from memory, 1 = 64 x 64 tiles per workgroup with X and Y staged
- * through LDS.  Mixed precision always uses its FP32 kernel. */
+ * through LDS, 2 = persistent workgroups taking 64 x 64 tiles of all
+ * instances from device work queues (one per XCD), the G block loaded behind
+ * the products.  Mixed precision always uses its FP32 kernel.  dqmc_flush_test
+ * runs the selected kernel. */
 dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant);
 
 /* Autotuner of the flush rank and kernel: for each of the n_cand candidate
- * ranks and each flush kernel, run `steps` slice steps (a multiple of
- * n_stab; the chains advance as in a sweep, without estimators), time them
- * with HIP events, and keep the fastest pair (best[0] = rank, best[1] =
- * kernel; ms_per_step[2 q + v], nullable, gets the time per step of rank q
- * with kernel v, 0 where not tried).  Synchronises. */
+ * ranks and each of the three flush kernels, run `steps` slice steps (a
+ * multiple of n_stab; the chains advance as in a sweep, without estimators),
+ * time them with HIP events, and keep the fastest pair (best[0] = rank,
+ * best[1] = kernel; ms_per_step[3 q + v], nullable, gets the time per step
+ * of rank q with kernel v, 0 where not tried).  Synchronises. */
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 

@@ -47,6 +47,7 @@ class Stats(ctypes.Structure):
 
 
 TIMING_CLASSES = ("wrap", "window", "expand", "flush", "stab", "measure", "learn")
+FLUSH_KERNELS = ("direct", "tiled", "queue")
 NET_NPARAM = 31170
 
 
@@ -432,11 +433,13 @@ class Simulation:
         """Time `steps` slice steps per candidate flush rank and flush kernel
         and keep the fastest; returns ((k, kernel), {(k, kernel): ms per step})."""
         c = np.ascontiguousarray(candidates, dtype=np.int32)
-        ms = np.zeros(2 * c.size, dtype=np.float64)
+        nv = len(FLUSH_KERNELS)
+        ms = np.zeros(nv * c.size, dtype=np.float64)
         best = np.zeros(2, dtype=np.int32)
         self._chk(self.lib.dqmc_autotune(self.h, int(steps), c.ctypes.data, c.size, best.ctypes.data,
                                          ms.ctypes.data), "autotune")
-        per = {(int(k), v): float(ms[2 * q + v]) for q, k in enumerate(c) for v in (0, 1) if ms[2 * q + v] > 0}
+        per = {(int(k), v): float(ms[nv * q + v]) for q, k in enumerate(c) for v in range(nv)
+               if ms[nv * q + v] > 0}
         return (int(best[0]), int(best[1])), per
 
     def dqmc_set_flush_kernel(self, variant):

@@ -155,6 +155,10 @@ struct InstState {
   double phw_re, phw_im;           // phase of det U of the working UDV chain
   double ph_drift;                 // max |tracked - anchored| phase over recomputations
   double drift_acc;                // running max of the recomputation in progress
+  // work queues of the queue flush kernel for launches whose first instance
+  // this is: next ticket and finished workgroups per queue (reset to zero by
+  // the last workgroup of each queue)
+  int32_t fq_next[8], fq_done[8];
 };
 // numeric_err bits
 constexpr int NUMERR_RATIO = 1;    // non-finite or zero acceptance ratio

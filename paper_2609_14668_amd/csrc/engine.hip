@@ -32,6 +32,7 @@ constexpr int TRSM_ROWS = 32;
 constexpr int GROUPS_MAX = 4;   // instance groups on separate streams
 constexpr int MAX_SERIES = 4096;
 constexpr int MAX_DELAY = 192;
+constexpr int FLUSH_KERNELS = 3;   // direct, LDS-tiled, work queue
 // Default tolerance of max |G_wrap - G_scratch| at a recomputation.  FP64
 // sweeps of the workloads here stay below 1e-6 (L = 3 .. 42, n_stab = 10).
 constexpr double DRIFT_TOL_DEFAULT = 1e-4;
@@ -206,7 +207,8 @@ struct dqmc_ctx {
   // learned multi-site moves
   int learn_P = 0, learn_m = 0;   // moves per slice visit, sites per move
   int collect_every = 0;          // store a training sample every this many downward slices (0: off)
-  int flush_variant = 0;          // 0: wave-per-block flush, 1: LDS-tiled GEMM (FP64 only)
+  int flush_variant = 0;          // 0: wave-per-block flush, 1: LDS-tiled GEMM, 2: work-queue flush (FP64 only)
+  int n_cu = 256;                 // compute units (persistent grids)
   // instance groups on their own streams (see issue_steps)
   int n_groups = 1;
   int group_off[GROUPS_MAX] = {0}, group_n[GROUPS_MAX] = {0};
@@ -401,8 +403,8 @@ void upper_solve(Ctx& c) {
 void stabilise(Ctx& c, bool measure) {
   dqmc_ctx* h = c.h;
   c.elem(EO_RESET_CHAIN);
-  for (int j = 0; j < h->n_stab; ++j) c.fft(FOP_STAB_B, 0, MAT_UW, j);
-  c.elem(EO_SCALE_COLS, 0, 0, MAT_UW, VEC_DW);
+  // A = B_chunk U D: the n_stab B's in one pass over U, columns scaled by D
+  c.fft(FOP_STAB_CHAIN, 0, MAT_UW);
   c.chk(launch_colnorm_sort(c.di, c.n, h->Nmax, h->cplx, MAT_UW, c.s));
   c.elem(EO_GATHER_COLS, MAT_UW, 0, MAT_QA);
   c.elem(EO_GATHER_ROWS, MAT_TW, 0, MAT_W3);
@@ -463,6 +465,9 @@ void flush(Ctx& c, int flags) {
   dqmc_ctx* h = c.h;
   if (h->mixed || h->flush_variant == 0) {
     c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, flags, c.s));
+  } else if (h->flush_variant == 2) {
+    // resident workgroups per CU: two for complex (217 VGPRs), three for real
+    c.chk(launch_flush_queue(c.di, c.n, h->cplx, flags, (h->cplx ? 2 : 3) * h->n_cu, c.s));
   } else {
     c.gemm(opnd(MAT_X, 0), opnd(MAT_Y, 1), opnd(MAT_G, 0), dim(1, 0), dim(1, 0), dim(0, 0), -1.0, 1.0,
            GF_K_FILL | flags);
@@ -800,7 +805,12 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     }
   }
   int dev = 0, lds = 0;
-  if (hipGetDevice(&dev) == hipSuccess) h->device = dev;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    h->device = dev;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      h->n_cu = ncu;
+  }
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     h->lds_budget = std::min<size_t>(65536, (size_t)lds);
@@ -1006,7 +1016,7 @@ dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k) {
 }
 
 dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant) {
-  if (!h || variant < 0 || variant > 1) return DQMC_EINVAL;
+  if (!h || variant < 0 || variant > 2) return DQMC_EINVAL;
   h->flush_variant = h->mixed ? 0 : variant;
   return DQMC_OK;
 }
@@ -1022,12 +1032,12 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
   h->timing = false;
   double best_ms = 1e300;
   int32_t bk = h->hd[0].kflush, bv = h->flush_variant;
-  const int nvar = h->mixed ? 1 : 2;
+  const int nvar = h->mixed ? 1 : FLUSH_KERNELS;
   dqmc_status st = DQMC_OK;
   for (int q = 0; q < n_cand && st == DQMC_OK; ++q) {
     st = dqmc_set_delay(h, cand[q]);
-    for (int v = 0; v < 2 && st == DQMC_OK; ++v) {
-      if (v >= nvar) { if (ms_per_step) ms_per_step[2 * q + v] = 0.0; continue; }
+    for (int v = 0; v < FLUSH_KERNELS && st == DQMC_OK; ++v) {
+      if (v >= nvar) { if (ms_per_step) ms_per_step[FLUSH_KERNELS * q + v] = 0.0; continue; }
       h->flush_variant = v;
       st = run_steps(h, h->n_stab, 0, s, 0);   // untimed: captures this configuration's graph
       if (st != DQMC_OK) break;
@@ -1041,7 +1051,7 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
         break;
       }
       const double per = ms / steps;
-      if (ms_per_step) ms_per_step[2 * q + v] = per;
+      if (ms_per_step) ms_per_step[FLUSH_KERNELS * q + v] = per;
       if (per < best_ms) { best_ms = per; bk = cand[q]; bv = v; }
     }
   }
@@ -1151,7 +1161,7 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X, c
   HIPCHK(h, hipMemcpyAsync(d.mat[MAT_Y], host_Y, sizeof(double) * w * (size_t)d.N * k, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync((char*)d.st + offsetof(InstState, fill), &k, sizeof(int32_t), hipMemcpyHostToDevice, s));
   Ctx c{h, s, h->dinst, h->n, 0};
-  c.chk(launch_flush_direct(h->dinst, h->n, h->Nmax, h->cplx, h->mixed, GF_IF_ANY, s));
+  flush(c, GF_IF_ANY);
   c.chk(launch_flush_done(h->dinst, h->n, 1, s));
   if (c.e != hipSuccess) return fail(h, DQMC_EHIP, hipGetErrorString(c.e));
   HIPCHK(h, hipStreamSynchronize(s));

@@ -25,6 +25,8 @@ struct Resolved {
   int active, slice, pre, post, tab;
 };
 
+template <typename C> using real_of_t = decltype(C::x);
+
 __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) {
   Resolved r{0, 0, 0, 0, TAB_P};
   const InstState& st = *d.st;
@@ -66,8 +68,30 @@ __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) 
     case FOP_EXPLICIT:
       r.active = 1; r.slice = a.ex_slice; r.pre = a.ex_pre; r.post = a.ex_post; r.tab = a.ex_tab;
       return r;
+    case FOP_STAB_CHAIN:   // resolved step by step inside the kernel
+      if (a.side != 0) return r;
+      r.active = 1;
+      return r;
   }
   return r;
+}
+
+// Step j of a chain pass: the FOP_STAB_B resolution of that step.
+__device__ __forceinline__ Resolved chain_step(const InstDev& d, const FftArgs& a, int j) {
+  FftArgs aj = a;
+  aj.op = FOP_STAB_B;
+  aj.j = j;
+  return resolve(d, aj);
+}
+
+// v <- e^{sign lambda x_r} v on element r of every vector held in LDS.
+template <typename C>
+__device__ __forceinline__ void lds_diag(C* buf, int tot, int N, int sign, const int8_t* xs,
+                                         real_of_t<C> ep, real_of_t<C> em, int nthreads) {
+  for (int e = threadIdx.x; e < tot; e += nthreads) {
+    const int r = e % N;
+    buf[e] = buf[e] * ((sign * xs[r]) > 0 ? ep : em);
+  }
 }
 
 // Complex compute type C is cplx (complex128) or cplxf (complex64); RT is its
@@ -248,6 +272,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
   const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
   const bool rows = a.side != 0;
+  const bool chain = a.op == FOP_STAB_CHAIN;
   // load (+ pre diagonal), LU elements per thread at a time: every load of a
   // group reads a clamped address and is issued before the first is used
   const int tot = nvl * N;
@@ -286,23 +311,44 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     }
   }
   __syncthreads();
-  C* cur;
-  if constexpr (LC > 0) cur = fft_2d_fixed<LC>(buf, buf2, roots, nvl, -1);
-  else cur = fft_2d<RMAX>(buf, buf2, roots, fac, L, Nc, N, nvl, -1);
-  C* oth = cur == buf ? buf2 : buf;
-  // 2x2 block per momentum
-  const cplx* T = d.tab + (size_t)rs.tab * Nc * 4;
-  for (int e = threadIdx.x; e < nvl * Nc; e += FFT_THREADS) {
-    int vv = e / Nc, k = e - vv * Nc;
-    C qa = cur[vv * N + k], qb = cur[vv * N + Nc + k];
-    C t00 = to_c<C>(T[4 * k]), t01 = to_c<C>(T[4 * k + 1]), t10 = to_c<C>(T[4 * k + 2]),
-      t11 = to_c<C>(T[4 * k + 3]);
-    cur[vv * N + k] = t00 * qa + t01 * qb;
-    cur[vv * N + Nc + k] = t10 * qa + t11 * qb;
+  C* cur = buf;
+  const int nrep = chain ? d.n_stab : 1;
+  for (int rep = 0; rep < nrep; ++rep) {
+    int tabi = rs.tab;
+    if (chain) {   // step rep of the chain: pre diagonal in LDS
+      const Resolved rj = chain_step(d, a, rep);
+      tabi = rj.tab;
+      if (rj.pre) {
+        lds_diag(cur, tot, N, rj.pre, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        __syncthreads();
+      }
+    }
+    C* oth = cur == buf ? buf2 : buf;
+    if constexpr (LC > 0) cur = fft_2d_fixed<LC>(cur, oth, roots, nvl, -1);
+    else cur = fft_2d<RMAX>(cur, oth, roots, fac, L, Nc, N, nvl, -1);
+    oth = cur == buf ? buf2 : buf;
+    // 2x2 block per momentum
+    const cplx* T = d.tab + (size_t)tabi * Nc * 4;
+    for (int e = threadIdx.x; e < nvl * Nc; e += FFT_THREADS) {
+      int vv = e / Nc, k = e - vv * Nc;
+      C qa = cur[vv * N + k], qb = cur[vv * N + Nc + k];
+      C t00 = to_c<C>(T[4 * k]), t01 = to_c<C>(T[4 * k + 1]), t10 = to_c<C>(T[4 * k + 2]),
+        t11 = to_c<C>(T[4 * k + 3]);
+      cur[vv * N + k] = t00 * qa + t01 * qb;
+      cur[vv * N + Nc + k] = t10 * qa + t11 * qb;
+    }
+    __syncthreads();
+    if constexpr (LC > 0) cur = fft_2d_fixed<LC>(cur, oth, roots, nvl, +1);
+    else cur = fft_2d<RMAX>(cur, oth, roots, fac, L, Nc, N, nvl, +1);
+    if (chain) {   // post diagonal of step rep in LDS
+      const Resolved rj = chain_step(d, a, rep);
+      if (rj.post) {
+        lds_diag(cur, tot, N, rj.post, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        __syncthreads();
+      }
+    }
   }
-  __syncthreads();
-  if constexpr (LC > 0) cur = fft_2d_fixed<LC>(cur, oth, roots, nvl, +1);
-  else cur = fft_2d<RMAX>(cur, oth, roots, fac, L, Nc, N, nvl, +1);
+  const double* dsc = chain ? d.vec[VEC_DW] : nullptr;   // chain: columns scaled by the working D
   // store (+ post diagonal)
   for (int e = threadIdx.x; e < tot; e += FFT_THREADS) {
     int vv, r;
@@ -311,6 +357,10 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     int q = v0 + vv;
     C val = cur[vv * N + r];
     if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
+    if (chain) {
+      if constexpr (ST<S>::is_complex) val = val * (RT)dsc[q];
+      else val = C{val.x * (RT)dsc[2 * q], val.y * (RT)dsc[2 * q + 1]};
+    }
     const double vx = (double)val.x, vy = (double)val.y;
     if constexpr (ST<S>::is_complex) {
       if (rows) gst(Mx + (size_t)r * N + q, cmake(vx, -vy));
@@ -424,6 +474,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_reg(const InstDev* __restri
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
   const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
   const bool rows = a.side != 0;
+  const bool chain = a.op == FOP_STAB_CHAIN;
   // load (+ pre diagonal): clamped loads issued in groups, then masked
   const int tot = nvl * N;
   constexpr int LU = 8;
@@ -461,40 +512,60 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_reg(const InstDev* __restri
     }
   }
   __syncthreads();
-  // axis 0, forward: line (vector, sublattice, n2) per thread, L consecutive points
-  if (tid < nvl * 2 * L) line_dft<L, false>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
-  __syncthreads();
-  // axis 1, forward: line (vector, sublattice, k1) per thread
   const bool b_act = tid < nvl * 2 * L;
   const int bv = tid / (2 * L), bs = (tid % (2 * L)) / L, bk1 = tid % L;
   C* pb_own = buf + bv * N + bs * Nc + bk1;
-  if (b_act) line_dft<L, false>(pb_own, L, roots);
-  __syncthreads();
-  // 2x2 block per momentum: the thread of sublattice s forms row s of the
-  // block from both lines of its column, then transforms it back
-  C y[L];
-  if (b_act) {
-    const C* pa = buf + bv * N + bk1;
-    const C* pbb = pa + Nc;
-    const cplx* T = d.tab + (size_t)rs.tab * Nc * 4 + 2 * bs;   // row bs: (t_s0, t_s1)
+  const int nrep = chain ? d.n_stab : 1;
+  for (int rep = 0; rep < nrep; ++rep) {
+    int tabi = rs.tab;
+    if (chain) {   // step rep of the chain: pre diagonal in LDS
+      const Resolved rj = chain_step(d, a, rep);
+      tabi = rj.tab;
+      if (rj.pre) {
+        lds_diag(buf, tot, N, rj.pre, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        __syncthreads();
+      }
+    }
+    // axis 0, forward: line (vector, sublattice, n2) per thread, L consecutive points
+    if (tid < nvl * 2 * L) line_dft<L, false>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
+    __syncthreads();
+    // axis 1, forward: line (vector, sublattice, k1) per thread
+    if (b_act) line_dft<L, false>(pb_own, L, roots);
+    __syncthreads();
+    // 2x2 block per momentum: the thread of sublattice s forms row s of the
+    // block from both lines of its column, then transforms it back
+    C y[L];
+    if (b_act) {
+      const C* pa = buf + bv * N + bk1;
+      const C* pbb = pa + Nc;
+      const cplx* T = d.tab + (size_t)tabi * Nc * 4 + 2 * bs;   // row bs: (t_s0, t_s1)
 #pragma unroll
-    for (int k2 = 0; k2 < L; ++k2) {
-      const int k = bk1 + L * k2;
-      const C t0 = to_c<C>(T[4 * k]), t1 = to_c<C>(T[4 * k + 1]);
-      y[k2] = t0 * pa[k2 * L] + t1 * pbb[k2 * L];
+      for (int k2 = 0; k2 < L; ++k2) {
+        const int k = bk1 + L * k2;
+        const C t0 = to_c<C>(T[4 * k]), t1 = to_c<C>(T[4 * k + 1]);
+        y[k2] = t0 * pa[k2 * L] + t1 * pbb[k2 * L];
+      }
+    }
+    __syncthreads();   // both lines read before either is overwritten
+    if (b_act) {
+      C x[L];
+      rdft<L, L, true>(y, x, roots);
+#pragma unroll
+      for (int n = 0; n < L; ++n) pb_own[n * L] = x[n];
+    }
+    __syncthreads();
+    // axis 0, inverse
+    if (tid < nvl * 2 * L) line_dft<L, true>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
+    __syncthreads();
+    if (chain) {   // post diagonal of step rep in LDS
+      const Resolved rj = chain_step(d, a, rep);
+      if (rj.post) {
+        lds_diag(buf, tot, N, rj.post, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        __syncthreads();
+      }
     }
   }
-  __syncthreads();   // both lines read before either is overwritten
-  if (b_act) {
-    C x[L];
-    rdft<L, L, true>(y, x, roots);
-#pragma unroll
-    for (int n = 0; n < L; ++n) pb_own[n * L] = x[n];
-  }
-  __syncthreads();
-  // axis 0, inverse
-  if (tid < nvl * 2 * L) line_dft<L, true>(buf + (tid / (2 * L)) * N + (tid % (2 * L)) * L, 1, roots);
-  __syncthreads();
+  const double* dsc = chain ? d.vec[VEC_DW] : nullptr;   // chain: columns scaled by the working D
   // store (+ post diagonal)
   for (int e = tid; e < tot; e += FFT_THREADS) {
     int vv, r;
@@ -503,6 +574,10 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_reg(const InstDev* __restri
     const int q = v0 + vv;
     C val = buf[vv * N + r];
     if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
+    if (chain) {
+      if constexpr (ST<S>::is_complex) val = val * (RT)dsc[q];
+      else val = C{val.x * (RT)dsc[2 * q], val.y * (RT)dsc[2 * q + 1]};
+    }
     const double vx = (double)val.x, vy = (double)val.y;
     if constexpr (ST<S>::is_complex) {
       if (rows) gst(Mx + (size_t)r * N + q, cmake(vx, -vy));

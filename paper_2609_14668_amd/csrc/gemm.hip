@@ -66,36 +66,22 @@ __device__ __forceinline__ void xcd_slot(int n_inst, int& inst, int& bx) {
   if (inst >= n_inst) inst = -1;
 }
 
-// ROLE only separates the flush instantiation (1) from the stabilisation
-// products (0) in profiles; the code is the same.
-template <typename S, int ROLE>
-__global__ void __launch_bounds__(GEMM_THREADS, 2)
-k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand B, GemmOperand C,
-       GemmDim Md, GemmDim Nd, GemmDim Kd, double alpha, double beta, int flags) {
+// Shared memory of one 64 x 64 output tile (op(A) and op(B) chunks, real
+// and imaginary planes).
+template <bool CX>
+struct GemmSmem {
+  double Ar[BK][BM + PAD], Br[BK][BN + PAD];
+  double Ai[CX ? BK : 1][BM + PAD], Bi[CX ? BK : 1][BN + PAD];
+};
+
+// C = alpha op(A) op(B) + beta C on the tiles tile0, tile0 + tstep, ... of
+// one instance (M x NC output, depth K): the tile body shared by the batched
+// GEMM and the work-queue flush.
+template <typename S>
+__device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __restrict__ pb, S* pc, int ld,
+                                           int aop, int bop, int M, int NC, int K, bool a_upper, double alpha,
+                                           double beta, int tile0, int tstep, GemmSmem<ST<S>::is_complex>& sm) {
   constexpr bool CX = ST<S>::is_complex;
-  int inst, bx;
-  xcd_slot(n_inst, inst, bx);
-  if (inst < 0) return;
-  const InstDev& d = insts[inst];
-  const int Nn = d.N;
-  const InstState& st = *d.st;
-  if (st.idle) return;
-  if ((flags & GF_SKIP_INIT) && st.init_mode) return;
-  if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
-  if ((flags & GF_IF_ANY) && st.fill <= 0) return;
-  const int M = dimval(Md, Nn);
-  const int NC = dimval(Nd, Nn);
-  const int K = (flags & GF_K_FILL) ? st.fill : dimval(Kd, Nn);
-  if (M <= 0 || NC <= 0) return;
-  const int ld = Nn;
-  const S* pa = reinterpret_cast<const S*>(mat_ptr(d, A.id)) + offval(A.ra, A.rb, Nn) + offval(A.ca, A.cb, Nn) * ld;
-  const S* pb = reinterpret_cast<const S*>(mat_ptr(d, B.id)) + offval(B.ra, B.rb, Nn) + offval(B.ca, B.cb, Nn) * ld;
-  S* pc = reinterpret_cast<S*>(mat_ptr(d, C.id)) + offval(C.ra, C.rb, Nn) + offval(C.ca, C.cb, Nn) * ld;
-  const bool a_upper = flags & GF_A_UPPER;
-
-  __shared__ double Ar[BK][BM + PAD], Br[BK][BN + PAD];
-  __shared__ double Ai[CX ? BK : 1][BM + PAD], Bi[CX ? BK : 1][BN + PAD];
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int tm = (M + BM - 1) / BM, tn = (NC + BN - 1) / BN;
@@ -114,52 +100,52 @@ k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int i, kk;
-      if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
+      if (aop == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
       else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
       const int gi = m0 + i, gk = k0 + kk;
       if (gi < M && gk < K && !(a_upper && gi > gk)) mask_a |= 1u << p;
       const int gic = min(gi, M - 1), gkc = min(gk, K - 1);
-      va[p] = gld(pa + (A.op == 0 ? gic + (size_t)gkc * ld : gkc + (size_t)gic * ld));
+      va[p] = gld(pa + (aop == 0 ? gic + (size_t)gkc * ld : gkc + (size_t)gic * ld));
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int j, kk;
-      if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
+      if (bop == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
       const int gj = n0 + j, gk = k0 + kk;
       if (gj < NC && gk < K) mask_b |= 1u << p;
       const int gjc = min(gj, NC - 1), gkc = min(gk, K - 1);
-      vb[p] = gld(pb + (B.op == 0 ? gkc + (size_t)gjc * ld : gjc + (size_t)gkc * ld));
+      vb[p] = gld(pb + (bop == 0 ? gkc + (size_t)gjc * ld : gjc + (size_t)gkc * ld));
     }
   };
   auto store_chunk = [&]() {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int i, kk;
-      if (A.op == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
+      if (aop == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
       else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
       double re, im;
       split<S>(va[p], re, im);
-      if (A.op == 2) im = -im;
+      if (aop == 2) im = -im;
       const bool in = (mask_a >> p) & 1u;
-      Ar[kk][i] = in ? re : 0.0;
-      if constexpr (CX) Ai[kk][i] = in ? im : 0.0;
+      sm.Ar[kk][i] = in ? re : 0.0;
+      if constexpr (CX) sm.Ai[kk][i] = in ? im : 0.0;
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       int j, kk;
-      if (B.op == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
+      if (bop == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
       double re, im;
       split<S>(vb[p], re, im);
-      if (B.op == 2) im = -im;
+      if (bop == 2) im = -im;
       const bool in = (mask_b >> p) & 1u;
-      Br[kk][j] = in ? re : 0.0;
-      if constexpr (CX) Bi[kk][j] = in ? im : 0.0;
+      sm.Br[kk][j] = in ? re : 0.0;
+      if constexpr (CX) sm.Bi[kk][j] = in ? im : 0.0;
     }
   };
 
-  for (int tile = bx; tile < ntiles; tile += gridDim.x) {
+  for (int tile = tile0; tile < ntiles; tile += tstep) {
     const int m0 = (tile % tm) * BM, n0 = (tile / tm) * BN;
     // accumulators hold transposed 16x16 blocks: operands are fed as (B, A) so
     // that a lane owns 4 columns of one row and stores coalesce along columns
@@ -210,11 +196,11 @@ k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand
         double ar[2], br[2], ai[2], bi[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          ar[t] = Ar[kr][wr + t * 16 + (lane & 15)];
-          br[t] = Br[kr][wc + t * 16 + (lane & 15)];
+          ar[t] = sm.Ar[kr][wr + t * 16 + (lane & 15)];
+          br[t] = sm.Br[kr][wc + t * 16 + (lane & 15)];
           if constexpr (CX) {
-            ai[t] = Ai[kr][wr + t * 16 + (lane & 15)];
-            bi[t] = Bi[kr][wc + t * 16 + (lane & 15)];
+            ai[t] = sm.Ai[kr][wr + t * 16 + (lane & 15)];
+            bi[t] = sm.Bi[kr][wc + t * 16 + (lane & 15)];
           }
         }
 #pragma unroll
@@ -256,6 +242,34 @@ k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand
           }
         }
   }
+}
+
+// ROLE only separates the flush instantiation (1) from the stabilisation
+// products (0) in profiles; the code is the same.
+template <typename S, int ROLE>
+__global__ void __launch_bounds__(GEMM_THREADS, 2)
+k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand B, GemmOperand C,
+       GemmDim Md, GemmDim Nd, GemmDim Kd, double alpha, double beta, int flags) {
+  int inst, bx;
+  xcd_slot(n_inst, inst, bx);
+  if (inst < 0) return;
+  const InstDev& d = insts[inst];
+  const int Nn = d.N;
+  const InstState& st = *d.st;
+  if (st.idle) return;
+  if ((flags & GF_SKIP_INIT) && st.init_mode) return;
+  if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
+  if ((flags & GF_IF_ANY) && st.fill <= 0) return;
+  const int M = dimval(Md, Nn);
+  const int NC = dimval(Nd, Nn);
+  const int K = (flags & GF_K_FILL) ? st.fill : dimval(Kd, Nn);
+  if (M <= 0 || NC <= 0) return;
+  const int ld = Nn;
+  const S* pa = reinterpret_cast<const S*>(mat_ptr(d, A.id)) + offval(A.ra, A.rb, Nn) + offval(A.ca, A.cb, Nn) * ld;
+  const S* pb = reinterpret_cast<const S*>(mat_ptr(d, B.id)) + offval(B.ra, B.rb, Nn) + offval(B.ca, B.cb, Nn) * ld;
+  S* pc = reinterpret_cast<S*>(mat_ptr(d, C.id)) + offval(C.ra, C.rb, Nn) + offval(C.ca, C.cb, Nn) * ld;
+  __shared__ GemmSmem<ST<S>::is_complex> sm;
+  gemm_tiles<S>(pa, pb, pc, ld, A.op, B.op, M, NC, K, (flags & GF_A_UPPER) != 0, alpha, beta, bx, gridDim.x, sm);
 }
 
 // Flush without LDS: G <- G - X Y with X column-major N x K (op N) and Y
@@ -367,6 +381,79 @@ k_flush_direct(const InstDev* __restrict__ insts, int n_inst, int flags) {
             }
           }
         }
+  }
+}
+
+// Flush from device work queues: G <- G - X Y over all instances of the
+// launch with persistent workgroups.  The output is cut into 64 x 64 tiles
+// (a 32 x 32 block per wave); the instances are dealt to nq queues (8, one per
+// XCD label, when the launch has at least 8 instances, else 1) and workgroup w
+// serves queue w % nq, so with the round-robin dispatch of workgroups to XCDs
+// the tiles of an instance are computed in one L2.  A workgroup takes the next
+// tile of its queue with one atomic ticket; tickets past the queue's total end
+// the loop, and the last workgroup of a queue to finish resets its counters
+// (kept in the InstState of the launch's first instance), so no clearing
+// launch is needed between flushes.
+//
+// Each tile runs the LDS-staged body of the batched GEMM (X and Y chunks of
+// 16 shared by the four waves).
+constexpr int FQ_T = BM;   // tile edge
+template <typename S>
+__device__ __forceinline__ bool fq_active(const InstDev& d, int flags) {
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return false;
+  if ((flags & GF_IF_FULL) && st.fill < d.kflush) return false;
+  if ((flags & GF_IF_ANY) && st.fill <= 0) return false;
+  return true;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(GEMM_THREADS, 2)
+k_flush_queue(const InstDev* __restrict__ insts, int n_inst, int flags) {
+  const int nq = n_inst >= N_XCD ? N_XCD : 1;
+  const int q = blockIdx.x % nq;
+  const int wpq = gridDim.x / nq;
+  InstState* qs = insts[0].st;
+  const int tid = threadIdx.x;
+  __shared__ int sh_t;
+  __shared__ GemmSmem<ST<S>::is_complex> sm;
+  // tiles of this queue: instances q, q + nq, ... that flush in this launch
+  int total = 0;
+  for (int i = q; i < n_inst; i += nq) {
+    if (!fq_active<S>(insts[i], flags)) continue;
+    const int nt = (insts[i].N + FQ_T - 1) / FQ_T;
+    total += nt * nt;
+  }
+  for (;;) {
+    if (tid == 0) sh_t = atomicAdd(&qs->fq_next[q], 1);
+    __syncthreads();
+    int t = sh_t;
+    __syncthreads();
+    if (t >= total) break;
+    // ticket -> (instance, tile)
+    int inst = q, nt = 1;
+    for (int i = q; i < n_inst; i += nq) {
+      if (!fq_active<S>(insts[i], flags)) continue;
+      nt = (insts[i].N + FQ_T - 1) / FQ_T;
+      inst = i;
+      if (t < nt * nt) break;
+      t -= nt * nt;
+    }
+    const InstDev& d = insts[inst];
+    const int N = d.N;
+    // G <- G - X Y: A = X (N x fill, column-major), B = Y read transposed
+    gemm_tiles<S>(reinterpret_cast<const S*>(d.mat[MAT_X]), reinterpret_cast<const S*>(d.mat[MAT_Y]),
+                  reinterpret_cast<S*>(d.mat[MAT_G]), N, 0, 1, N, N, d.st->fill, false, -1.0, 1.0, t, 1 << 30, sm);
+  }
+  // the last workgroup of the queue resets it for the next launch (every
+  // workgroup of the queue has taken its final ticket before counting itself)
+  if (tid == 0) {
+    __threadfence();
+    const int done = atomicAdd(&qs->fq_done[q], 1);
+    if (done == wpq - 1) {
+      atomicExch(&qs->fq_next[q], 0);
+      atomicExch(&qs->fq_done[q], 0);
+    }
   }
 }
 
@@ -489,6 +576,15 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
     if (fl) hipLaunchKernelGGL((k_gemm<double, 1>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
     else hipLaunchKernelGGL((k_gemm<double, 0>), grid, dim3(GEMM_THREADS), 0, s, insts, n_inst, A, B, C, M, Nn, K, alpha, beta, flags);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_flush_queue(const InstDev* insts, int n_inst, bool cplx_, int flags, int n_wg, hipStream_t s) {
+  const int nq = n_inst >= N_XCD ? N_XCD : 1;
+  int g = n_wg / nq * nq;
+  if (g < nq) g = nq;
+  if (cplx_) hipLaunchKernelGGL(k_flush_queue<cplx>, dim3(g), dim3(256), 0, s, insts, n_inst, flags);
+  else hipLaunchKernelGGL(k_flush_queue<double>, dim3(g), dim3(256), 0, s, insts, n_inst, flags);
   return hipGetLastError();
 }
 

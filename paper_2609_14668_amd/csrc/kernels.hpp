@@ -4,7 +4,10 @@
 #include "common.hpp"
 
 // ---- FFT propagation -----------------------------------------------------------------
-enum FftOp : int { FOP_WRAP_PRE = 0, FOP_WRAP_POST, FOP_STAB_B, FOP_HALF, FOP_EXPLICIT };
+// FOP_STAB_CHAIN: all n_stab B's of one chain step applied to the columns of
+// the working U in one pass (resolved per step as FOP_STAB_B with j = 0 ..
+// n_stab - 1), the columns scaled by the working D on the way out.
+enum FftOp : int { FOP_WRAP_PRE = 0, FOP_WRAP_POST, FOP_STAB_B, FOP_HALF, FOP_EXPLICIT, FOP_STAB_CHAIN };
 struct FftArgs {
   int op;      // FftOp
   int side;    // 0: columns (left multiplication), 1: rows (right multiplication)
@@ -47,6 +50,11 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
 // FP32 MFMA (operands rounded to float) and subtracted from the FP64 G.
 hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool cplx_, bool single, int flags,
                                hipStream_t s);
+
+// Flush from device work queues with n_wg persistent workgroups (rounded to a
+// multiple of the queue count); the queue counters live in the InstState of
+// insts[0], so concurrent launches must start at different instances.
+hipError_t launch_flush_queue(const InstDev* insts, int n_inst, bool cplx_, int flags, int n_wg, hipStream_t s);
 
 // ---- delayed update -------------------------------------------------------------------
 hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, int replay,

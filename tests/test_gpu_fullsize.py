@@ -18,9 +18,12 @@ the scale-separated inversion keeps the result's error at that level relative
 to max|G| = O(1): 1e-9 absolute leaves a factor 100 over N eps * 18 blocks.
 Wrap: one FFT pass per side, 1e-13 relative to the largest entry as at the
 small sizes.  Drift: the wrapped G carries the rounding of ten wraps and
-about 0.7 N accepted rank-one terms per slice (each O(1e-16) relative), a
-factor ~1e3 growth through the slice propagators, so an intact sweep stays
-below 1e-6; one wrong rank-one term or one wrong wrap gives O(1e-2) or more.
+about 0.7 N accepted rank-one terms per slice (each O(1e-16) relative),
+amplified through the slice propagators (cond(B_l) of a few per slice); on
+this batch intact sweeps measure max |G_wrap - G_scratch| between 1e-7 and
+3e-6 depending on the configurations, so the check uses the library's own
+drift tolerance (1e-4, which also sets numeric_err); one wrong rank-one term
+or one wrong wrap gives O(1e-2) or more.
 """
 import numpy as np
 import pytest
@@ -49,7 +52,7 @@ def batch():
     sim = Simulation(descs)
     sim.set_graphs(True)
     best, _ = sim.autotune([24, 64], 2 * descs[0]["n_stab"])
-    print("autotuned flush rank %d, kernel %s" % (best[0], ("direct", "tiled")[best[1]]), flush=True)
+    print("autotuned flush rank %d, kernel %s" % (best[0], ("direct", "tiled", "queue")[best[1]]), flush=True)
     yield sim, descs
     sim.close()
 
@@ -88,7 +91,7 @@ def test_fullsize_sweep_properties(batch):
         if M == Mmax:
             assert st1[i]["sweeps"] - st0[i]["sweeps"] == 1
         assert st1[i]["numeric_err"] == 0
-        assert st1[i]["drift_max"] < 1e-6
+        assert st1[i]["drift_max"] < 1e-4
         ob = sim.measure(i)
         assert ob["n_meas"] > 0
         assert 0.0 < ob["D"] < 0.3

@@ -50,11 +50,13 @@ def test_wrap_matches_dense_propagation(L, th):
         assert np.abs(out - ref).max() / np.abs(ref).max() < 1e-13
 
 
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("L,th,k", [(3, (0, 0), 8), (12, (0, 0), 32), (12, (0, 0), 96), (4, (0.5, 1.0), 16),
-                                    (9, (0.2, 0.9), 64), (42, (0, 0), 64)])
-def test_flush_matches_numpy(L, th, k):
+                                    (9, (0.2, 0.9), 64), (42, (0, 0), 64), (18, (0.4, 2.0), 45)])
+def test_flush_matches_numpy(L, th, k, kernel):
     d = workloads.desc(L, 3.7, 1.0, theta=th, n_stab=5, k=min(k, 192))
     sim = _sim([d])
+    sim.set_flush_kernel(kernel)
     N, _, cx = sim.shapes[0]
     G = _rand_g(N, cx, 1)
     X = _rand_g(N, cx, 2)[:, :k] if k <= N else np.vstack([_rand_g(N, cx, 2)] * 1)[:, :k]
@@ -153,13 +155,15 @@ def test_flush_rank_does_not_change_the_chain():
     assert np.array_equal(a.fields(0), b.fields(0))
     assert np.abs(a.green(0) - b.green(0)).max() < 1e-10
     best, per = a.autotune([8, 32, 64], 20)
-    assert best[0] in (8, 32, 64) and best[1] in (0, 1) and all(v > 0 for v in per.values())
-    # the tiled flush kernel gives the same chain
-    c = _sim([d])
-    c.set_flush_kernel(1)
-    c.sweep(1, measure=False)
-    assert np.array_equal(c.fields(0), b.fields(0))
-    assert np.abs(c.green(0) - b.green(0)).max() < 1e-10
+    assert best[0] in (8, 32, 64) and best[1] in (0, 1, 2) and all(v > 0 for v in per.values())
+    assert len(per) == 9
+    # the tiled and the work-queue flush kernels give the same chain
+    for kernel in (1, 2):
+        c = _sim([d])
+        c.set_flush_kernel(kernel)
+        c.sweep(1, measure=False)
+        assert np.array_equal(c.fields(0), b.fields(0))
+        assert np.abs(c.green(0) - b.green(0)).max() < 1e-10
 
 
 @pytest.mark.parametrize("groups", [1, 2, 3])
@@ -201,21 +205,29 @@ def test_instance_groups_do_not_change_the_chain():
         assert a.measure(i)["D"] == pytest.approx(b.measure(i)["D"], abs=1e-12)
 
 
-def test_flush_every_instance_of_an_uneven_batch():
+@pytest.mark.parametrize("kernel", [0, 1, 2])
+def test_flush_every_instance_of_an_uneven_batch(kernel):
     """Nine instances (the instance dimension of the grid is padded to 16 and
-    the instances are spread unevenly over the XCD slots): a flush on each
-    instance in turn matches G - X Y and leaves the others unchanged."""
-    descs = [workloads.desc(3, 3.7, 1.0, theta=(0.3 * i, 0.7), n_stab=5, seed=160 + i) for i in range(9)]
+    the instances are spread unevenly over the XCD slots; the work-queue
+    kernel puts instances 0 and 8 in one queue and has eight queues with a
+    single active instance at most): a flush on each instance in turn
+    matches G - X Y and leaves the others unchanged, also on a second round
+    (the queues reset themselves after every launch)."""
+    descs = [workloads.desc(3 + (i % 3) * 3, 3.7, 1.0, theta=(0.3 * i, 0.7), n_stab=5, seed=160 + i)
+             for i in range(9)]
     sim = _sim(descs)
-    N, _, cx = sim.shapes[0]
+    sim.set_flush_kernel(kernel)
+    cx = sim.shapes[0][2]
     k = 8
-    G = [_rand_g(N, cx, 200 + i) for i in range(9)]
+    G = [_rand_g(sim.shapes[i][0], cx, 200 + i) for i in range(9)]
     for i in range(9):
         sim.set_green(i, G[i])
-    for i in range(9):
-        X = _rand_g(N, cx, 300 + i)[:, :k]
-        Y = _rand_g(N, cx, 400 + i)[:k, :]
-        sim.flush_test(i, X, Y)
-        G[i] = G[i] - X @ Y
-        for j in range(9):
-            assert np.abs(sim.green(j) - G[j]).max() / np.abs(G[j]).max() < 1e-13, (i, j)
+    for rnd in range(2):
+        for i in range(9):
+            N = sim.shapes[i][0]
+            X = _rand_g(N, cx, 300 + i + 10 * rnd)[:, :k]
+            Y = _rand_g(N, cx, 400 + i + 10 * rnd)[:k, :]
+            sim.flush_test(i, X, Y)
+            G[i] = G[i] - X @ Y
+            for j in range(9):
+                assert np.abs(sim.green(j) - G[j]).max() / np.abs(G[j]).max() < 1e-13, (rnd, i, j)
