@@ -299,6 +299,14 @@ def main():
                  "ms_per_step": {"%d/%s" % (k, FLUSH_NAMES[v]): round(t, 3) for (k, v), t in per.items()}}
         print("autotuned flush k=%d %s: %s" % (best[0], tuned["flush_kernel"], tuned["ms_per_step"]),
               file=sys.stderr, flush=True)
+    if not a.no_autotune:
+        fchoice, ftimes = sim.autotune_fft(10)
+        tuned = dict(tuned or {})
+        tuned["fft_tiles"] = {"L%d/%s" % (L, ("cols", "rows")[sd]): ("wide", "narrow", "eight")[t]
+                              for (L, sd), t in fchoice.items()}
+        tuned["fft_us"] = {"L%d/%s/%s" % (L, ("cols", "rows")[sd], ("wide", "narrow", "eight")[t]): round(u, 1)
+                           for (L, sd, t), u in ftimes.items() if u > 0}
+        print("autotuned fft tiles %s" % tuned["fft_tiles"], file=sys.stderr, flush=True)
     for w in range(a.warmup):
         if learned and w == a.warmup - 1:
             sim.collect(8)     # training windows from the last warm-up sweep

@@ -356,6 +356,26 @@ dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant);
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 
+/* FFT tiles of the register-line wrap kernel (L <= 24 with a compile-time
+ * plan): vectors (columns, or rows) per workgroup, per L and side (0 columns,
+ * 1 rows): tile 0 = as many as 256 threads cover (2 L threads per vector),
+ * 1 = half as many (half the LDS, more workgroups per CU), 2 = eight (rows of
+ * complex G read as 128-byte segments; the wide tile where eight vectors
+ * would need more than 96 KB of LDS).  Single-precision wraps always use
+ * tile 0.  The tile only changes the grouping of independent vectors, never
+ * the result.  DQMC_EINVAL if no instance of the handle has this L. */
+dqmc_status dqmc_set_fft_tile(dqmc_handle h, int32_t L, int32_t side, int32_t tile);
+/* Distinct lattice sizes with a compile-time FFT plan (n, and Ls[0..n) if
+ * Ls is not null, at most 16), in the order of dqmc_autotune_fft's output. */
+dqmc_status dqmc_fft_plan_count(dqmc_handle h, int32_t* n, int32_t* Ls);
+/* FFT tile autotuner: for every plan L (dqmc_fft_plan_count order q), side
+ * and tile, time `reps` wrap transforms of a scratch matrix of every
+ * instance with HIP events and keep the fastest tile per (L, side).
+ * tiles_out[2 q + side] (nullable) receives the choice, us_out[(2 q + side)
+ * * 3 + tile] (nullable) the microseconds per transform.  The chains are not
+ * advanced.  Synchronises. */
+dqmc_status dqmc_autotune_fft(dqmc_handle h, int32_t reps, int32_t* tiles_out, double* us_out);
+
 /* Instance groups: groups in [1, 4] (default: 3 for 24 or more instances, 2
  * for 8 or more, else 1).  The instances are split into that many contiguous groups of
  * about equal work (fewer if there are fewer instances), group 0 running on

@@ -100,6 +100,9 @@ _SIGS = {
     "dqmc_set_graphs": [_P, ctypes.c_int32],
     "dqmc_autotune": [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P],
     "dqmc_set_flush_kernel": [_P, ctypes.c_int32],
+    "dqmc_set_fft_tile": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "dqmc_fft_plan_count": [_P, ctypes.POINTER(ctypes.c_int32), _P],
+    "dqmc_autotune_fft": [_P, ctypes.c_int32, _P, _P],
     "dqmc_status_string": [ctypes.c_int32],
     "dqmc_last_error": [_P],
 }
@@ -448,6 +451,27 @@ class Simulation:
     set_flush_kernel = dqmc_set_flush_kernel
 
     autotune = dqmc_autotune
+
+    def dqmc_set_fft_tile(self, L, side, tile):
+        self._chk(self.lib.dqmc_set_fft_tile(self.h, int(L), int(side), int(tile)), "set_fft_tile")
+
+    set_fft_tile = dqmc_set_fft_tile
+
+    def dqmc_autotune_fft(self, reps=20):
+        """Pick the register-line FFT tile per (L, side); returns
+        ({(L, side): tile}, {(L, side, tile): microseconds})."""
+        n = ctypes.c_int32(0)
+        Ls = np.zeros(16, dtype=np.int32)
+        self._chk(self.lib.dqmc_fft_plan_count(self.h, ctypes.byref(n), Ls.ctypes.data), "fft_plan_count")
+        tiles = np.zeros(2 * max(n.value, 1), dtype=np.int32)
+        us = np.zeros(6 * max(n.value, 1), dtype=np.float64)
+        self._chk(self.lib.dqmc_autotune_fft(self.h, int(reps), tiles.ctypes.data, us.ctypes.data), "autotune_fft")
+        choice = {(int(Ls[q]), side): int(tiles[2 * q + side]) for q in range(n.value) for side in (0, 1)}
+        times = {(int(Ls[q]), side, t): float(us[(2 * q + side) * 3 + t])
+                 for q in range(n.value) for side in (0, 1) for t in range(3)}
+        return choice, times
+
+    autotune_fft = dqmc_autotune_fft
 
     def dqmc_set_streams(self, groups):
         self._chk(self.lib.dqmc_set_streams(self.h, int(groups)), "set_streams")

@@ -202,6 +202,7 @@ struct dqmc_ctx {
   int rmax = 4;  // largest FFT radix over the instances
   int kcap_max = 0;
   std::vector<int> fixedL;   // distinct L with a compile-time FFT plan
+  std::vector<int> fft_tile; // register-line tile of fixedL[q] for side s at [2 q + s]
   bool any_generic = false;  // some L uses the runtime-plan FFT
   bool mixed = false;        // wraps and flushes in single precision
   // learned multi-site moves
@@ -320,12 +321,12 @@ struct Ctx {
     FftArgs a{op, side, mat, j, 0, 0, 0, 0};
     const bool single = h->mixed && (op == FOP_WRAP_PRE || op == FOP_WRAP_POST);
     chk(launch_fft(di, n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
-                   (int)h->fixedL.size(), h->any_generic, single, s));
+                   (int)h->fixedL.size(), h->any_generic, single, h->fft_tile.data(), s));
   }
   void fft_explicit(int side, int mat, int pre, int tab, int post, int slice) {
     FftArgs a{FOP_EXPLICIT, side, mat, 0, pre, tab, post, slice};
     chk(launch_fft(di, n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
-                   (int)h->fixedL.size(), h->any_generic, h->mixed, s));
+                   (int)h->fixedL.size(), h->any_generic, h->mixed, h->fft_tile.data(), s));
   }
   void gemm(GemmOperand A, GemmOperand B, GemmOperand C, GemmDim M, GemmDim N, GemmDim K,
             double alpha, double beta, int flags = 0) {
@@ -686,6 +687,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
       h->any_generic = true;
     }
   }
+  h->fft_tile.assign(2 * h->fixedL.size(), 0);
   h->ws = (char*)dev_ws;
   h->ws_bytes = bytes;
   h->stream = (hipStream_t)stream;
@@ -940,7 +942,10 @@ static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hip
 // Everything a captured block of n_stab steps depends on besides device
 // memory: the launches of a step are fixed by these.
 static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, int groups) {
-  return {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant, h->kcap_max};
+  std::vector<int> k = {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant,
+                        h->kcap_max};
+  k.insert(k.end(), h->fft_tile.begin(), h->fft_tile.end());
+  return k;
 }
 
 // Sweeps are replayed as HIP graphs of one stabilisation block (n_stab slice
@@ -1062,6 +1067,62 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
   if (st != DQMC_OK) return st;
   if (best) { best[0] = bk; best[1] = bv; }
   return dqmc_set_delay(h, bk);
+}
+
+dqmc_status dqmc_set_fft_tile(dqmc_handle h, int32_t L, int32_t side, int32_t tile) {
+  if (!h || (side != 0 && side != 1) || tile < 0 || tile >= FFT_TILES) return DQMC_EINVAL;
+  for (size_t q = 0; q < h->fixedL.size(); ++q)
+    if (h->fixedL[q] == L) {
+      h->fft_tile[2 * q + side] = L <= 24 ? tile : 0;
+      return DQMC_OK;
+    }
+  return fail(h, DQMC_EINVAL, "no instance of this L uses a register-line FFT plan");
+}
+
+dqmc_status dqmc_autotune_fft(dqmc_handle h, int32_t reps, int32_t* tiles_out, double* us_out) {
+  if (!h || reps < 1) return DQMC_EINVAL;
+  hipStream_t s = h->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  dqmc_status st = DQMC_OK;
+  // each (L, side, tile): reps wrap transforms of the scratch matrix MAT_W1
+  // with the e^{-dtau K} table and a diagonal (the arithmetic of a wrap)
+  for (size_t q = 0; q < h->fixedL.size() && st == DQMC_OK; ++q) {
+    for (int side = 0; side < 2 && st == DQMC_OK; ++side) {
+      double best = 1e300;
+      int bt = 0;
+      for (int t = 0; t < FFT_TILES && st == DQMC_OK; ++t) {
+        h->fft_tile[2 * q + side] = h->fixedL[q] <= 24 ? t : 0;
+        Ctx c{h, s, h->dinst, h->n, 0};
+        c.fft_explicit(side, MAT_W1, 0, TAB_P, side ? -1 : +1, 1);   // untimed first launch
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(h, DQMC_EHIP, "autotune_fft event"); break; }
+        for (int r = 0; r < reps; ++r) c.fft_explicit(side, MAT_W1, 0, TAB_P, side ? -1 : +1, 1);
+        float ms = 0.f;
+        if (c.e != hipSuccess || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = fail(h, DQMC_EHIP, "autotune_fft timing");
+          break;
+        }
+        const double us = 1e3 * ms / reps;
+        if (us_out) us_out[(2 * q + side) * FFT_TILES + t] = us;
+        if (us < best) { best = us; bt = t; }
+      }
+      h->fft_tile[2 * q + side] = h->fixedL[q] <= 24 ? bt : 0;
+      if (tiles_out) tiles_out[2 * q + side] = h->fft_tile[2 * q + side];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+dqmc_status dqmc_fft_plan_count(dqmc_handle h, int32_t* n, int32_t* Ls) {
+  if (!h || !n) return DQMC_EINVAL;
+  *n = (int32_t)h->fixedL.size();
+  if (Ls)
+    for (size_t q = 0; q < h->fixedL.size(); ++q) Ls[q] = h->fixedL[q];
+  return DQMC_OK;
 }
 
 dqmc_status dqmc_sweep(dqmc_handle h, int32_t n_sweeps, int32_t measure, void* stream) {

@@ -453,11 +453,24 @@ __device__ __forceinline__ void line_dft(C* p, int st, const C* roots) {
   for (int n = 0; n < L; ++n) p[n * st] = X[n];
 }
 
-template <typename S, int LC, typename C>
-__global__ void __launch_bounds__(FFT_THREADS) k_fft_reg(const InstDev* __restrict__ insts, FftArgs a) {
+// Tiles of the register-line kernel: NV vectors per workgroup of NT threads.
+//   0 wide:   as many vectors as 256 threads cover (2L threads per vector)
+//   1 narrow: half as many, half the LDS (more workgroups per CU)
+//   2 eight:  8 vectors, so that a row side reads 128-byte segments of
+//             complex G (only where the LDS stays within 96 KB; else wide)
+constexpr int reg_nv(int L, int tile) {
+  const int wide = 256 / (2 * L);
+  if (tile == 1) return (wide + 1) / 2;
+  if (tile == 2 && 8 * 2 * L * L * 16 <= 96 * 1024) return 8;
+  return wide;
+}
+constexpr int reg_nt(int L, int tile) { return (reg_nv(L, tile) * 2 * L + 63) / 64 * 64; }
+
+template <typename S, int LC, typename C, int NV, int NT>
+__global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ insts, FftArgs a) {
   typedef real_of<C> RT;
   constexpr int L = LC, Nc = L * L, N = 2 * Nc;
-  constexpr int NV = FFT_THREADS / (2 * L);   // vectors per workgroup
+  constexpr int FFT_THREADS = NT;
   __shared__ C buf[NV * N];
   __shared__ C roots[L];
   const InstDev& d = insts[blockIdx.y];
@@ -614,16 +627,31 @@ bool fft_has_fixed(int L) {
 }
 
 namespace {
+template <typename S, int LC, typename C, int TILE>
+void launch_reg(const InstDev* insts, int n_inst, const FftArgs& a, hipStream_t s) {
+  constexpr int N = 2 * LC * LC;
+  constexpr int NV = reg_nv(LC, TILE), NT = reg_nt(LC, TILE);
+  constexpr int nvec = ST<S>::is_complex ? N : N / 2;
+  hipLaunchKernelGGL((k_fft_reg<S, LC, C, NV, NT>), dim3((nvec + NV - 1) / NV, n_inst), dim3(NT), 0, s, insts, a);
+}
+
 template <typename S, int LC, typename C>
-void launch_fixed(const InstDev* insts, int n_inst, const FftArgs& a, size_t lds_budget, hipStream_t s) {
+void launch_fixed(const InstDev* insts, int n_inst, const FftArgs& a, size_t lds_budget, int tile, hipStream_t s) {
   constexpr int N = 2 * LC * LC;
   if constexpr (LC <= 24) {
-    // register line transforms: NV vectors per workgroup, LDS sized at compile time
+    // register line transforms, LDS sized at compile time; the single
+    // precision wraps use the wide tile only
     (void)lds_budget;
-    constexpr int NV = FFT_THREADS / (2 * LC);
-    constexpr int nvec = ST<S>::is_complex ? N : N / 2;
-    hipLaunchKernelGGL((k_fft_reg<S, LC, C>), dim3((nvec + NV - 1) / NV, n_inst), dim3(FFT_THREADS), 0, s, insts, a);
+    if constexpr (sizeof(C) == sizeof(cplx)) {
+      if (tile == 1) launch_reg<S, LC, C, 1>(insts, n_inst, a, s);
+      else if (tile == 2) launch_reg<S, LC, C, 2>(insts, n_inst, a, s);
+      else launch_reg<S, LC, C, 0>(insts, n_inst, a, s);
+    } else {
+      (void)tile;
+      launch_reg<S, LC, C, 0>(insts, n_inst, a, s);
+    }
   } else {
+    (void)tile;
     int nv = fft_vectors_per_block(N, lds_budget, sizeof(C));
     int nvec = ST<S>::is_complex ? N : N / 2;
     dim3 grid((nvec + nv - 1) / nv, n_inst);
@@ -648,17 +676,18 @@ void launch_generic(const InstDev* insts, int n_inst, int Nmax, const FftArgs& a
 
 hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, const FftArgs& a,
                       size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, bool single,
-                      hipStream_t s) {
+                      const int* tiles, hipStream_t s) {
   for (int q = 0; q < nL; ++q) {
+    const int tile = tiles ? tiles[2 * q + (a.side != 0)] : 0;
     switch (Ls[q]) {
 #define DQMC_CASE(v)                                                                         \
   case v:                                                                                    \
     if (single) {                                                                            \
-      if (cplx_) launch_fixed<cplx, v, cplxf>(insts, n_inst, a, lds_budget, s);              \
-      else launch_fixed<double, v, cplxf>(insts, n_inst, a, lds_budget, s);                  \
+      if (cplx_) launch_fixed<cplx, v, cplxf>(insts, n_inst, a, lds_budget, tile, s);        \
+      else launch_fixed<double, v, cplxf>(insts, n_inst, a, lds_budget, tile, s);            \
     } else {                                                                                 \
-      if (cplx_) launch_fixed<cplx, v, cplx>(insts, n_inst, a, lds_budget, s);               \
-      else launch_fixed<double, v, cplx>(insts, n_inst, a, lds_budget, s);                   \
+      if (cplx_) launch_fixed<cplx, v, cplx>(insts, n_inst, a, lds_budget, tile, s);         \
+      else launch_fixed<double, v, cplx>(insts, n_inst, a, lds_budget, tile, s);             \
     }                                                                                        \
     break;
       DQMC_FIXED_L(DQMC_CASE)

@@ -19,9 +19,12 @@ int fft_vectors_per_block(int N, size_t lds_budget, size_t elem_bytes);
 // Ls: the distinct L with a compile-time plan among the instances;
 // any_generic: some instance needs the runtime-plan kernel.
 bool fft_has_fixed(int L);
+// tiles (nullable): register-line tile per (L index q, side) at tiles[2 q + side]
+// (0 wide, 1 narrow, 2 eight vectors per workgroup; L <= 24 in FP64)
+constexpr int FFT_TILES = 3;
 hipError_t launch_fft(const InstDev* insts, int n_inst, int Nmax, bool cplx_, const FftArgs& a,
                       size_t lds_budget, int rmax, const int* Ls, int nL, bool any_generic, bool single,
-                      hipStream_t s);
+                      const int* tiles, hipStream_t s);
 
 // ---- batched GEMM on named matrices (FP64 MFMA) --------------------------------------
 // C = alpha * op(A) op(B) + beta * C for every instance.  Row/column offsets

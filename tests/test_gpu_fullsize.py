@@ -2,8 +2,8 @@
 twist grid, four per twist, plus 16 L=12 chains: N = 648 and 288, M = 180 and
 120) in the launch configuration that the benchmark times: the library's
 default instance groups for this batch (three, on three streams),
-stabilisation blocks replayed as HIP graphs, the flush rank and kernel picked
-by the autotuner.
+stabilisation blocks replayed as HIP graphs, the flush rank and kernel and the
+FFT tiles picked by the autotuners.
 
 Sampled outputs are checked against the oracle where it can compute them one
 by one at this size (the scratch G of an L=18 and an L=12 instance from
@@ -52,6 +52,8 @@ def batch():
     sim = Simulation(descs)
     sim.set_graphs(True)
     best, _ = sim.autotune([24, 64], 2 * descs[0]["n_stab"])
+    tiles, _ = sim.autotune_fft(5)
+    print("autotuned fft tiles %s" % tiles, flush=True)
     print("autotuned flush rank %d, kernel %s" % (best[0], ("direct", "tiled", "queue")[best[1]]), flush=True)
     yield sim, descs
     sim.close()

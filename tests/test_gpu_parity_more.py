@@ -258,3 +258,44 @@ def test_network_gradient_over_several_chunks(L, window, M, B):
     for name, _ in pnet.SHAPES:
         rel = np.linalg.norm(gp[name] - rp[name]) / np.linalg.norm(rp[name])
         assert rel < 6e-2, (name, rel)
+
+
+@pytest.mark.parametrize("L", [12, 18])
+def test_every_fft_tile_gives_the_dense_wrap(L):
+    """Each register-line tile (wide, narrow, eight vectors per workgroup)
+    on both sides equals dense propagation; the tile autotuner keeps one of
+    them per (L, side)."""
+    d = workloads.desc(L, 3.7, 1.0, theta=(0.4, 1.9), n_stab=5)
+    sim = _sim([d])
+    m = _model(d)
+    N, M, cx = sim.shapes[0]
+    f = sim.fields(0)
+    rng = np.random.default_rng(L)
+    for tile in (0, 1, 2):
+        for side in (0, 1):
+            sim.set_fft_tile(L, side, tile)
+        for direction, sl in ((0, 2), (1, 4)):
+            G = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+            sim.set_green(0, G)
+            sim.wrap(direction, sl)
+            B, Bi = m.B(0, f[sl - 1]), m.Binv(0, f[sl - 1])
+            ref = B @ G @ Bi if direction == 0 else Bi @ G @ B
+            assert np.abs(sim.green(0) - ref).max() / np.abs(ref).max() < 1e-13, (tile, direction)
+    choice, times = sim.autotune_fft(5)
+    assert set(choice) == {(L, 0), (L, 1)} and all(t in (0, 1, 2) for t in choice.values())
+    assert all(v > 0 for v in times.values())
+
+
+def test_fft_tiles_do_not_change_the_chain():
+    """A sweep with the narrow tile on the columns and eight-vector tiles on
+    the rows reproduces the default tiles' chain (fields exactly, G to FP64
+    rounding)."""
+    d = workloads.desc(12, 3.7, 2.0, theta=(0.4, 1.9), k=32, n_stab=10, seed=77)
+    a, b = _sim([d]), _sim([d])
+    b.set_fft_tile(12, 0, 1)
+    b.set_fft_tile(12, 1, 2)
+    a.sweep(1, measure=True)
+    b.sweep(1, measure=True)
+    assert np.array_equal(a.fields(0), b.fields(0))
+    assert np.abs(a.green(0) - b.green(0)).max() < 1e-12
+    assert abs(a.measure(0)["D"] - b.measure(0)["D"]) < 1e-12
