@@ -273,16 +273,67 @@ class Chain:
 
     def measure(self):
         Gu, Gd = self.measured_greens()
-        return observables(self.m.lat, self.m.K, Gu, Gd, self.m.U)
+        return observables(self.m.lat, self.m.K, Gu, Gd, self.m.U, beta=self.m.beta)
 
 
-def observables(lat, K, Gu, Gd, U):
+def momentum_distribution(lat, Gu, Gd):
+    """Spin-averaged 2 x 2 momentum distribution of eq. nkMatrix on the
+    instance's momentum grid (plain index k = l1 + L l2; with a twist the
+    physical momentum is shifted by the vector potential, eq. kpoints):
+        n_ab(k) = (1/N_c) sum_{r,r'} e^{i k.(r - r')} <c^+_{a r} c_{b r'}>,
+    <c^+_i c_j> = delta_ij - G_ji, i.e. n_ab(k) = delta_ab - [F G_ba F^dagger]_kk / N_c
+    with F the 2-D DFT over the cell grid (numpy fft2 over (n2, n1) on the
+    left, inverse on the right).  Returns an array (N_c, 2, 2), [k, a, b]."""
+    L, Nc = lat.L, lat.Nc
+    out = np.zeros((Nc, 2, 2), dtype=complex)
+    for G in (Gu, Gd):
+        for a in (0, 1):
+            for b in (0, 1):
+                blk = np.asarray(G[b * Nc:(b + 1) * Nc, a * Nc:(a + 1) * Nc], dtype=complex)
+                t = blk.reshape(L, L, L, L)                  # [n2', n1', n2, n1]
+                t = np.fft.fft2(t, axes=(0, 1))              # sum_r' e^{-i k r'}
+                t = np.fft.ifft2(t, axes=(2, 3)) * Nc        # sum_r  e^{+i k r}
+                diag = np.array([t[l2, l1, l2, l1] for l2 in range(L) for l1 in range(L)])
+                out[:, a, b] += (1.0 if a == b else 0.0) - diag / Nc
+    return out / 2.0
+
+
+def nk_bands(nk):
+    """Eigenvalues (n_+, n_-) of each Hermitian 2 x 2 n(k) (n_+ >= n_-): n_+
+    belongs to the lower band eps_{k,-} and n_- to eps_{k,+} (Sec. II C)."""
+    tr = (nk[:, 0, 0] + nk[:, 1, 1]).real
+    df = (nk[:, 0, 0] - nk[:, 1, 1]).real
+    r = np.sqrt(0.25 * df * df + np.abs(nk[:, 0, 1]) ** 2)
+    return 0.5 * tr + r, 0.5 * tr - r
+
+
+def dirac_points(L):
+    """Plain-grid indices (l1, l2) of the two inequivalent Dirac points, where
+    f(k) = 0 (K = (2 b1 + b2)/3 and K' = (b1 + 2 b2)/3); on the grid when
+    L % 3 == 0, else the nearest grid points."""
+    return [(int(round(2 * L / 3)) % L, int(round(L / 3)) % L), (int(round(L / 3)) % L, int(round(2 * L / 3)) % L)]
+
+
+def gab_dirac(lat, nk):
+    """|G_AB(K + dk)| of Sec. IV A: the modulus of the spin-averaged n_AB at
+    K + b1/L, averaged over the two inequivalent Dirac points."""
+    L = lat.L
+    vals = [abs(nk[((l1 + 1) % L) + L * l2, 0, 1]) for (l1, l2) in dirac_points(L)]
+    return float(np.mean(vals))
+
+
+def observables(lat, K, Gu, Gd, U, beta=None):
     """Equal-time estimators for one configuration from G^up, G^dn (Wick).
 
     <n_is> = 1 - G_ii; <c_i^+ c_j> = delta_ij - G_ji;
     <n_is n_js> = (1-G_ii)(1-G_jj) + (delta_ij - G_ji) G_ij (same spin),
     opposite spins factorise.  D (Sec. II C), E = <H_0> + N_s U D (Sec. IV C),
-    C_zz(r) (eq. SzSzCrF), S_zz(k) (eq. SpinStrucF), m^2 and R_m2 (eq. CrfRatio).
+    C_zz(r) (eq. SzSzCrF), S_zz(k) (eq. SpinStrucF), m^2 and R_m2 (eq. CrfRatio),
+    the momentum distribution n(k) (eq. nkMatrix) and, given beta, the
+    charge-compressibility estimator of eq. ChiCharge,
+    chi = (beta/N_s) Re[(sum_i n_i)^2 + sum_s (Tr G^s - Tr G^s G^s)] - beta N_s,
+    whose mean over configurations is (beta/N_s)(<N^2> - <N>^2) at half
+    filling, where the real part of sum_i n_i is N_s in every configuration.
     """
     N, Nc, L = lat.N, lat.Nc, lat.L
     nu = 1.0 - np.diag(Gu)
@@ -307,7 +358,12 @@ def observables(lat, K, Gu, Gd, U):
     ph = np.exp(2j * np.pi * np.arange(L) / L)     # k = b1/L: e^{i k.r} = e^{2 pi i d1/L}
     Szzdk = (Czz * ph[None, :]).sum()
     m2 = SzzG / (2 * Nc)
-    return {
+    extra = {"nk": momentum_distribution(lat, Gu, Gd)}
+    if beta is not None:
+        ntot = np.sum(nu + nd)
+        c1 = ntot * ntot + sum(np.trace(G) - np.trace(G @ G) for G in (Gu, Gd))
+        extra["chi_e"] = float((beta / N) * c1.real - beta * N)
+    return {**extra,
         "n": float(np.mean(nu + nd).real),
         "D": float(D.real),
         "ekin": float(ekin.real),

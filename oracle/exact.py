@@ -73,6 +73,21 @@ def energy_u0(lat, beta):
     return -np.sum(f * np.tanh(beta * f / 2)) / lat.Nc
 
 
+def bands_u0(lat, beta):
+    """Free-fermion band occupations on the instance's grid: the lower band
+    eps_- = -|f| holds n_+ = 1/(1 + e^{-beta |f|}), the upper band n_- =
+    1/(1 + e^{+beta |f|})."""
+    f = np.abs(lat.f_of_k(lat.kpoints()))
+    return 1.0 / (1.0 + np.exp(-beta * f)), 1.0 / (1.0 + np.exp(beta * f))
+
+
+def chi_e_u0(lat, beta):
+    """(beta/N_s)(<N^2> - <N>^2) of free fermions: every single-particle level
+    of either spin contributes its occupation variance n(1 - n)."""
+    npl, nmi = bands_u0(lat, beta)
+    return (beta / lat.N) * 2.0 * np.sum(npl * (1 - npl) + nmi * (1 - nmi))
+
+
 # ---- brute force over HS configurations ---------------------------------------------
 def config_estimators(model, X):
     """Per-configuration weights and Wick estimators for a batch of HS
@@ -117,7 +132,32 @@ def config_estimators(model, X):
         Szzdk += np.einsum("bij,i,j->b", blk, ph.conj(), ph)
     SzzG /= 2 * Nc
     Szzdk /= 2 * Nc
-    return {"W": W, "D": D, "H0": H0, "SzzG": SzzG, "Szzdk": Szzdk, "Gup": Gs[0], "Gdn": Gs[1]}
+    # one-body density matrices rho_ij = <c_i^+ c_j> = delta_ij - G_ji, the
+    # momentum distribution n_ab(k) = (1/N_c) sum_{r,r'} e^{i k (r - r')}
+    # rho_{a r, b r'} (spin average) by explicit Fourier sums with the
+    # unitary U_{k,r} = e^{-i k.r}/L, and the Wick value of N_tot^2 summed
+    # pair by pair
+    Uc = fourier_matrix(model.lat)[:Nc, :Nc]
+    rhos = [np.eye(N)[None] - np.transpose(G, (0, 2, 1)) for G in Gs]
+    nk = np.zeros((B, Nc, 2, 2), dtype=complex)
+    for rho in rhos:
+        for a in (0, 1):
+            for b2 in (0, 1):
+                blk = rho[:, a * Nc:(a + 1) * Nc, b2 * Nc:(b2 + 1) * Nc]
+                m = np.einsum("kr,brs,ks->bk", Uc.conj(), blk, Uc)
+                nk[:, :, a, b2] += 0.5 * m
+    N2 = np.zeros(B, dtype=complex)
+    occ = [np.einsum("bii->bi", rho) for rho in rhos]
+    for s1 in (0, 1):
+        for s2 in (0, 1):
+            if s1 == s2:
+                rho = rhos[s1]
+                N2 += np.einsum("bi,bj->b", occ[s1], occ[s1]) + np.einsum(
+                    "bij,bij->b", rho, np.eye(N)[None] - np.transpose(rho, (0, 2, 1)))
+            else:
+                N2 += occ[s1].sum(axis=1) * occ[s2].sum(axis=1)
+    return {"W": W, "D": D, "H0": H0, "SzzG": SzzG, "Szzdk": Szzdk, "Gup": Gs[0], "Gdn": Gs[1],
+            "nk": nk, "Ntot": sum(o.sum(axis=1) for o in occ), "N2": N2}
 
 
 def brute_force(model, batch=4096):
@@ -127,7 +167,8 @@ def brute_force(model, batch=4096):
     nf = M * N
     if nf > 20:
         raise ValueError("too many fields for brute force")
-    tot = {"Z": 0.0, "D": 0.0, "H0": 0.0, "SzzG": 0.0, "Szzdk": 0.0}
+    tot = {"Z": 0.0, "D": 0.0, "H0": 0.0, "SzzG": 0.0, "Szzdk": 0.0, "N2": 0.0, "Ntot": 0.0}
+    nk_sum = 0.0
     wmin = np.inf
     max_imag = 0.0
     allcfg = np.array(list(itertools.product((1, -1), repeat=nf)), dtype=float)
@@ -138,11 +179,13 @@ def brute_force(model, batch=4096):
         W = W.real
         wmin = min(wmin, float(W.min()))
         tot["Z"] += W.sum()
-        for k in ("D", "H0", "SzzG", "Szzdk"):
+        for k in ("D", "H0", "SzzG", "Szzdk", "N2", "Ntot"):
             tot[k] += (W * c[k]).sum().real
+        nk_sum = nk_sum + np.einsum("b,bkxy->kxy", W, c["nk"])
     Z = tot["Z"]
     return {"Z": Z, "D": tot["D"] / Z, "H0": tot["H0"] / Z, "SzzG": tot["SzzG"] / Z,
-            "Szzdk": tot["Szzdk"] / Z, "wmin": wmin, "w_max_rel_imag": max_imag}
+            "Szzdk": tot["Szzdk"] / Z, "N2": tot["N2"] / Z, "Ntot": tot["Ntot"] / Z, "nk": nk_sum / Z,
+            "wmin": wmin, "w_max_rel_imag": max_imag}
 
 
 # ---- Fock-space exact diagonalisation ------------------------------------------------
@@ -214,9 +257,30 @@ def exact_trotter(model):
             return np.sum(pu * ((O * Dm) @ pd @ Dm.T))
     one = np.ones((dim, dim))
     Z = tr(one)
+    Ntot = ntot[:, None] + ntot[None, :]
+
+    def tr_onebody(Oop, spin):
+        """Tr[O T^M] / Z for a one-body Fock operator O acting on one species."""
+        EO = E @ Oop
+        if M == 1:
+            eo, e = np.diag(EO), np.diag(E)
+            return np.einsum("ab,a,b->", Dm, eo if spin == 0 else e, e if spin == 0 else eo) / Z
+        Po = E * EO.T
+        return np.sum((Po if spin == 0 else P) * (Dm @ (P if spin == 0 else Po) @ Dm.T)) / Z
+
+    # one-body density matrix <c^+_i c_j> of each spin from the Fock operators c^+_i c_j
+    rho = np.zeros((2, N, N), dtype=complex)
+    for i in range(N):
+        for j in range(N):
+            Kij = np.zeros((N, N))
+            Kij[i, j] = 1.0
+            Op = fock_hopping(Kij)
+            for spin in (0, 1):
+                rho[spin, i, j] = tr_onebody(Op, spin)
     return {"Z": Z.real, "D": (tr(Docc) / Z).real,
             "H0": ((tr(one, left_up=True) + tr(one, left_dn=True)) / Z).real,
-            "SzzG": (tr(SG) / Z).real, "Szzdk": (tr(Sdk) / Z).real}
+            "SzzG": (tr(SG) / Z).real, "Szzdk": (tr(Sdk) / Z).real,
+            "N2": (tr(Ntot * Ntot) / Z).real, "Ntot": (tr(Ntot) / Z).real, "rho": rho}
 
 
 def tiny_model(U=3.8, dtau=0.25, M=2, theta1=0.0, theta2=0.0, L=2):

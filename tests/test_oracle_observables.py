@@ -51,7 +51,10 @@ def _violations(obs_fn, tol=1e-12):
             Gu, Gd = ref["Gup"][b], ref["Gdn"][b]
             if not m.complex:
                 Gu, Gd = Gu.real, Gd.real
-            o = obs_fn(m.lat, m.K, Gu, Gd, m.U)
+            o = obs_fn(m.lat, m.K, Gu, Gd, m.U, beta=m.beta)
+            worst = max(worst, float(np.abs(o["nk"] - ref["nk"][b]).max()))
+            chi = (m.beta / m.N) * (ref["N2"][b].real - m.N ** 2)
+            worst = max(worst, abs(o["chi_e"] - chi) / max(1.0, abs(chi)))
             want = {"D": ref["D"][b].real, "ekin": ref["H0"][b].real / m.N,
                     "e": ref["H0"][b].real / m.N + m.U * ref["D"][b].real,
                     "Szz_G": ref["SzzG"][b].real, "Szz_dk": ref["Szzdk"][b].real,
@@ -89,6 +92,31 @@ def _mutant(old, new):
     ("(I - Gu.T) * Gu", "0.0 * Gu"),                                 # exchange term of spin up dropped
     ("Czz /= 2 * Nc", "Czz /= Nc"),                                  # normalisation
     ("-(np.trace(K @ Gu)", "+(np.trace(K @ Gu)"),                    # sign of the hopping energy
+    ("np.trace(G) - np.trace(G @ G)", "np.trace(G)"),                # pair term of chi_e dropped
 ])
 def test_planted_mistakes_fail_the_pin(old, new):
     assert _violations(_mutant(old, new)) > 1e-6
+
+
+def _mutant_nk(old, new):
+    from oracle import dqmc
+    src = textwrap.dedent(inspect.getsource(dqmc.momentum_distribution))
+    assert old in src, old
+    ns = dict(vars(odq))
+    exec(compile(src.replace(old, new), "<planted>", "exec"), ns)
+    planted = ns["momentum_distribution"]
+
+    def obs(lat, K, Gu, Gd, U, beta=None):
+        o = observables(lat, K, Gu, Gd, U, beta=beta)
+        o["nk"] = planted(lat, Gu, Gd)
+        return o
+    return obs
+
+
+@pytest.mark.parametrize("old,new", [
+    ("G[b * Nc:(b + 1) * Nc, a * Nc:(a + 1) * Nc]", "G[a * Nc:(a + 1) * Nc, b * Nc:(b + 1) * Nc]"),  # block G_ab
+    ("t = np.fft.fft2(t, axes=(0, 1))", "t = np.fft.ifft2(t, axes=(0, 1)) * Nc"),  # n(-k) for n(k)
+    ("(1.0 if a == b else 0.0) - diag / Nc", "- diag / Nc"),                       # delta term dropped
+])
+def test_planted_momentum_distribution_mistakes_fail_the_pin(old, new):
+    assert _violations(_mutant_nk(old, new)) > 1e-6

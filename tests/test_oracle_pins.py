@@ -105,6 +105,13 @@ def test_u0_green_energy_double_occupancy(L, beta, th):
     assert abs(o["ekin"] - exact.energy_u0(m.lat, beta)) < 1e-12
     assert abs(o["D"] - 0.25) < 1e-12
     assert abs(o["n"] - 1.0) < 1e-12
+    # momentum distribution (eq. nkMatrix): band occupations are Fermi functions
+    from oracle.dqmc import nk_bands
+    npl, nmi = nk_bands(o["nk"])
+    ref_p, ref_m = exact.bands_u0(m.lat, beta)
+    assert np.abs(npl - ref_p).max() < 1e-12 and np.abs(nmi - ref_m).max() < 1e-12
+    # charge compressibility (eq. ChiCharge): sum of level variances
+    assert abs(o["chi_e"] - exact.chi_e_u0(m.lat, beta)) < 1e-11
 
 
 # ---- brute force over all HS configurations vs Fock-space ED ----------------------------
@@ -114,8 +121,18 @@ def test_bruteforce_equals_exact_diagonalisation(th):
     bf = exact.brute_force(m)
     ed = exact.exact_trotter(m)
     assert bf["wmin"] > 0 and bf["w_max_rel_imag"] < 1e-12
-    for k in ("Z", "D", "H0", "SzzG", "Szzdk"):
+    for k in ("Z", "D", "H0", "SzzG", "Szzdk", "N2", "Ntot"):
         assert abs(bf[k] - ed[k]) <= 1e-12 * max(1.0, abs(ed[k])), k
+    # momentum distribution: Fourier sums of the Fock-space one-body density matrix
+    Nc = m.Nc
+    Uc = exact.fourier_matrix(m.lat)[:Nc, :Nc]
+    nk_ed = np.zeros((Nc, 2, 2), dtype=complex)
+    for spin in (0, 1):
+        for a in (0, 1):
+            for b in (0, 1):
+                blk = ed["rho"][spin][a * Nc:(a + 1) * Nc, b * Nc:(b + 1) * Nc]
+                nk_ed[:, a, b] += 0.5 * np.einsum("kr,rs,ks->k", Uc.conj(), blk, Uc)
+    assert np.abs(bf["nk"] - nk_ed).max() < 1e-12
 
 
 def test_single_slice_exact_diagonalisation():
@@ -262,9 +279,10 @@ def test_markov_chain_reproduces_exact_diagonalisation():
         n0 = len(ch.samples)
         ch.sweep(src)
         per_sweep.append({k: np.mean([s[k] for s in ch.samples[n0:]])
-                          for k in ("D", "ekin", "Szz_G", "Szz_dk")})
+                          for k in ("D", "ekin", "Szz_G", "Szz_dk", "chi_e")})
+    chi_ref = (m.beta / m.N) * (ed["N2"] - ed["Ntot"] ** 2)
     for key, ref in (("D", ed["D"]), ("ekin", ed["H0"] / m.N), ("Szz_G", ed["SzzG"]),
-                     ("Szz_dk", ed["Szzdk"])):
+                     ("Szz_dk", ed["Szzdk"]), ("chi_e", chi_ref)):
         x = np.array([p[key] for p in per_sweep])
         mu, err = stats.mean_err(x)
         assert abs(mu - ref) < 4 * err, (key, mu, ref, err)
