@@ -107,9 +107,18 @@ typedef struct {
  *           The weight det_up det_dn is real and non-negative (det_dn is the
  *           complex conjugate of det_up up to a positive factor, Sec. II B);
  *           the phase of det_up alone is tracked per accepted flip and
- *           re-anchored from the UDV factors at every recomputation. */
+ *           re-anchored from the UDV factors at every recomputation;
+ *   chi_e   charge compressibility of eq. ChiCharge, (beta/N_s)(<N^2> - <N>^2)
+ *           with the equal-time <N^2> from Wick's theorem (<N> = N_s at half
+ *           filling in every configuration);
+ *   GAB_dirac  |G_AB(K + dk)| of Sec. IV A: the modulus of the mean n_AB(k)
+ *           (spin-averaged, eq. nkMatrix) at K + b1/L, averaged over the two
+ *           Dirac points K = (2 b1 + b2)/3 and (b1 + 2 b2)/3 of the
+ *           instance's grid (nearest grid points when L % 3 != 0; the grid
+ *           is shifted by a twist, eq. kpoints); 0 when the momentum
+ *           distribution is not measured (dqmc_set_measure_k). */
 typedef struct {
-  double n, D, ekin, e, Szz_G, Szz_dk, m2, Rm2, phase_cos, phase_sin;
+  double n, D, ekin, e, Szz_G, Szz_dk, m2, Rm2, phase_cos, phase_sin, chi_e, GAB_dirac;
   int64_t n_meas;
 } dqmc_obs;
 
@@ -187,11 +196,29 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
 /* Estimator means of instance inst (see dqmc_obs); synchronises.
  * DQMC_ENUMERIC (out still filled) if the instance hit a numerical error. */
 dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out);
+/* Momentum distribution (eq. nkMatrix) with every measurement: G of each
+ * instance (or its half-step G~) is Fourier transformed on both sides,
+ * Ghat = F G F^dagger (F the unnormalised per-sublattice 2-D DFT of the
+ * wraps), and n_ab(k) = (1/N_c) sum_{r,r'} e^{i k.(r - r')} <c^+_{a r} c_{b r'}>
+ * = delta_ab - Ghat[b k, a k] / N_c (spin up; spin down from the particle-hole
+ * partner) is accumulated as the spin average.  Default on. */
+dqmc_status dqmc_set_measure_k(dqmc_handle h, int32_t on);
+/* Mean momentum distribution of instance inst over the measurements since the
+ * last dqmc_reset_obs, per plain grid index k = l1 + L l2 (momentum
+ * ((l1 + Theta1/2pi) b1 + (l2 + Theta2/2pi) b2)/L).  raw = 1: N_c x 8 doubles,
+ * the complex means of n_AA, n_AB, n_BA, n_BB as (re, im).  raw = 0: N_c x 7
+ * doubles: |f(k)| (the band energies are -+|f|), n_AA, n_BB, Re n_AB, Im n_AB
+ * of the Hermitian part of the mean, and its eigenvalues n_+ >= n_-: n_+
+ * belongs to the band eps_{k,-} = -|f| and n_- to eps_{k,+} (Sec. II C).
+ * DQMC_ESTATE if nothing was measured.  Synchronises. */
+dqmc_status dqmc_get_nk(dqmc_handle h, int32_t inst, int32_t raw, double* host_out);
+
 /* Restart the estimator means and the counters of dqmc_stats (proposals,
  * accepted, flushes, drifts, learned moves) and clear numeric_err. */
 dqmc_status dqmc_reset_obs(dqmc_handle h);
-/* Per-sweep means of the estimators in the order of dqmc_obs (10 doubles per
- * sweep), most recent max_sweeps at most, oldest first; *n_out = sweeps written. */
+/* Per-sweep means of the estimators in the order of dqmc_obs up to chi_e
+ * (11 doubles per sweep), most recent max_sweeps at most, oldest first;
+ * *n_out = sweeps written. */
 dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32_t max_sweeps,
                             int32_t* n_out);
 /* Counters of instance inst; synchronises.  DQMC_ENUMERIC (out still

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libdqmc.so")
 DQMC_OK = 0
 STATUS = {0: "DQMC_OK", -1: "DQMC_EINVAL", -2: "DQMC_ENOMEM", -3: "DQMC_EHIP", -4: "DQMC_ENUMERIC",
           -5: "DQMC_ESTATE", -6: "DQMC_EUNSUPPORTED"}
-OBS_FIELDS = ("n", "D", "ekin", "e", "Szz_G", "Szz_dk", "m2", "Rm2", "phase_cos", "phase_sin")
+OBS_FIELDS = ("n", "D", "ekin", "e", "Szz_G", "Szz_dk", "m2", "Rm2", "phase_cos", "phase_sin", "chi_e", "GAB_dirac")
+SERIES_FIELDS = OBS_FIELDS[:11]
 
 
 class DqmcError(RuntimeError):
@@ -71,6 +72,8 @@ _SIGS = {
     "dqmc_flush_test": [_P, ctypes.c_int32, _P, _P, ctypes.c_int32],
     "dqmc_measure": [_P, ctypes.c_int32, ctypes.POINTER(Obs)],
     "dqmc_reset_obs": [_P],
+    "dqmc_set_measure_k": [_P, ctypes.c_int32],
+    "dqmc_get_nk": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
     "dqmc_set_drift_tol": [_P, ctypes.c_double],
@@ -266,16 +269,36 @@ class Simulation:
 
     measure = dqmc_measure
 
+    def dqmc_set_measure_k(self, on):
+        self._chk(self.lib.dqmc_set_measure_k(self.h, int(bool(on))), "set_measure_k")
+
+    set_measure_k = dqmc_set_measure_k
+
+    def dqmc_get_nk(self, inst=0, raw=False):
+        """raw: complex (N_c, 2, 2) mean n(k); else a dict of the columns
+        eps (|f|), n_AA, n_BB, n_AB (complex), n_plus, n_minus."""
+        Nc = self.shapes[inst][0] // 2
+        out = np.zeros(Nc * (8 if raw else 7), dtype=np.float64)
+        self._chk(self.lib.dqmc_get_nk(self.h, inst, int(bool(raw)), out.ctypes.data), "get_nk")
+        if raw:
+            m = out.reshape(Nc, 2, 2, 2)
+            return m[..., 0] + 1j * m[..., 1]
+        m = out.reshape(Nc, 7)
+        return {"eps": m[:, 0], "n_AA": m[:, 1], "n_BB": m[:, 2], "n_AB": m[:, 3] + 1j * m[:, 4],
+                "n_plus": m[:, 5], "n_minus": m[:, 6]}
+
+    nk = dqmc_get_nk
+
     def dqmc_reset_obs(self):
         self._chk(self.lib.dqmc_reset_obs(self.h), "reset_obs")
 
     reset_obs = dqmc_reset_obs
 
     def dqmc_get_series(self, inst=0, max_sweeps=4096):
-        out = np.zeros((max_sweeps, len(OBS_FIELDS)), dtype=np.float64)
+        out = np.zeros((max_sweeps, len(SERIES_FIELDS)), dtype=np.float64)
         n = ctypes.c_int32()
         self._chk(self.lib.dqmc_get_series(self.h, inst, out.ctypes.data, max_sweeps, ctypes.byref(n)), "series")
-        return {f: out[:n.value, k].copy() for k, f in enumerate(OBS_FIELDS)}
+        return {f: out[:n.value, k].copy() for k, f in enumerate(SERIES_FIELDS)}
 
     series = dqmc_get_series
 

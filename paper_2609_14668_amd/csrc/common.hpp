@@ -182,7 +182,7 @@ struct LearnState {
 // Running sums of equal-time estimators.
 enum ObsId : int {
   OBS_N = 0, OBS_D, OBS_EKIN, OBS_E, OBS_SZZ_G, OBS_SZZ_DK, OBS_M2, OBS_RM2_NUM,
-  OBS_PHASE_RE, OBS_PHASE_IM, OBS_COUNT
+  OBS_PHASE_RE, OBS_PHASE_IM, OBS_CHI, OBS_COUNT
 };
 
 // Rows of N elements in an instance's buffer for the partial products of a
@@ -228,6 +228,7 @@ struct InstDev {
   InstState* st;
   double* obs;              // running sums [OBS_COUNT]
   double* series;           // per-sweep means [max_series x OBS_COUNT]
+  double* nk_sum;           // momentum distribution sums: Nc x 8 (AA, AB, BA, BB as re, im)
   int32_t max_series;
   const uint8_t* replay_bits;  // nullable
   double* replay_ratio;        // nullable

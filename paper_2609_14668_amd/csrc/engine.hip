@@ -56,7 +56,7 @@ bool is_twisted(const dqmc_instance_desc& d) {
 }
 
 struct Offs {
-  size_t st, obs, series, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn, rsplit;
+  size_t st, obs, series, nk, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn, rsplit;
   size_t vec[VEC_COUNT];
   size_t mat[MAT_COUNT];
   size_t stackU, stackT, stackD, stackPh;
@@ -119,6 +119,7 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.st = o; o = al(o + sizeof(InstState));
     f.obs = o; o = al(o + sizeof(double) * (2 * OBS_COUNT + 1));
     f.series = o; o = al(o + sizeof(double) * OBS_COUNT * MAX_SERIES);
+    f.nk = o; o = al(o + sizeof(double) * 8 * Nc);
     f.fields = o; o = al(o + (size_t)M * N);
     f.tab = o; o = al(o + sizeof(cplx) * 16 * Nc);
     f.roots = o; o = al(o + sizeof(cplx) * 64);
@@ -209,6 +210,7 @@ struct dqmc_ctx {
   int learn_P = 0, learn_m = 0;   // moves per slice visit, sites per move
   int collect_every = 0;          // store a training sample every this many downward slices (0: off)
   int flush_variant = 0;          // 0: wave-per-block flush, 1: LDS-tiled GEMM, 2: work-queue flush (FP64 only)
+  bool measure_k = true;          // momentum distribution with every measurement
   int n_cu = 256;                 // compute units (persistent grids)
   // instance groups on their own streams (see issue_steps)
   int n_groups = 1;
@@ -436,13 +438,21 @@ void stabilise(Ctx& c, bool measure) {
     // on G (the half-step launches skip them; MAT_GS holds a copy of G)
     bool sym = false;
     for (int i = c.off; i < c.off + c.n; ++i) sym = sym || h->desc[i].sym_measure;
-    if (sym) {
+    if (sym || h->measure_k) {
       c.elem(EO_COPY, MAT_G, 0, MAT_GS);
-      c.fft(FOP_HALF, 0, MAT_GS);
-      c.fft(FOP_HALF, 1, MAT_GS);
+      if (sym) {
+        c.fft(FOP_HALF, 0, MAT_GS);
+        c.fft(FOP_HALF, 1, MAT_GS);
+      }
       c.chk(launch_measure(c.di, c.n, h->Nmax, h->cplx, MAT_GS, c.s));
     } else {
       c.chk(launch_measure(c.di, c.n, h->Nmax, h->cplx, MAT_G, c.s));
+    }
+    if (h->measure_k) {
+      // momentum distribution: Ghat = F G F^dagger in place, its diagonal blocks
+      c.fft(FOP_FOURIER, 0, MAT_GS);
+      c.fft(FOP_FOURIER, 1, MAT_GS);
+      c.chk(launch_measure_k(c.di, c.n, h->Nmax, h->cplx, MAT_GS, c.s));
     }
   }
 }
@@ -761,6 +771,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.st = (InstState*)(b + f.st);
     dv.obs = (double*)(b + f.obs);
     dv.series = (double*)(b + f.series);
+    dv.nk_sum = (double*)(b + f.nk);
     dv.max_series = MAX_SERIES;
     h->hd.push_back(dv);
 
@@ -797,6 +808,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
         (e = hipMemsetAsync(b + f.st, 0, sizeof(InstState), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.series, 0, sizeof(double) * OBS_COUNT * MAX_SERIES, s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.nk, 0, sizeof(double) * 8 * Nc, s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.targets, 0, sizeof(float) * (size_t)dv.M * dv.N, s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.learn, 0, sizeof(LearnState), s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
@@ -943,7 +955,7 @@ static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hip
 // memory: the launches of a step are fixed by these.
 static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, int groups) {
   std::vector<int> k = {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant,
-                        h->kcap_max};
+                        h->kcap_max, h->measure_k ? 1 : 0};
   k.insert(k.end(), h->fft_tile.begin(), h->fft_tile.end());
   return k;
 }
@@ -1251,6 +1263,23 @@ dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out) {
     out->Rm2 = out->Szz_G != 0.0 ? 1.0 - out->Szz_dk / out->Szz_G : 0.0;
     out->phase_cos = obs[OBS_PHASE_RE] / n;
     out->phase_sin = obs[OBS_PHASE_IM] / n;
+    out->chi_e = obs[OBS_CHI] / n;
+    if (h->measure_k) {
+      // |G_AB(K + dk)|: modulus of the mean spin-averaged n_AB at K + b1/L,
+      // averaged over the two Dirac points K = (2 b1 + b2)/3, (b1 + 2 b2)/3
+      const int L = d.L;
+      const int K1[2][2] = {{(int)std::lround(2.0 * L / 3) % L, (int)std::lround(L / 3.0) % L},
+                            {(int)std::lround(L / 3.0) % L, (int)std::lround(2.0 * L / 3) % L}};
+      double gab = 0;
+      for (int q = 0; q < 2; ++q) {
+        const int k = (K1[q][0] + 1) % L + L * K1[q][1];
+        double ab[2];
+        HIPCHK(h, hipMemcpyAsync(ab, d.nk_sum + 8 * k + 2, sizeof(ab), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        gab += 0.5 * std::hypot(ab[0], ab[1]) / n;
+      }
+      out->GAB_dirac = gab;
+    }
   }
   if (st.numeric_err) return fail(h, DQMC_ENUMERIC, numeric_message(st.numeric_err));
   return DQMC_OK;
@@ -1258,7 +1287,10 @@ dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out) {
 
 dqmc_status dqmc_reset_obs(dqmc_handle h) {
   if (!h) return DQMC_EINVAL;
-  for (auto& d : h->hd) HIPCHK(h, hipMemsetAsync(d.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), h->stream));
+  for (auto& d : h->hd) {
+    HIPCHK(h, hipMemsetAsync(d.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), h->stream));
+    HIPCHK(h, hipMemsetAsync(d.nk_sum, 0, sizeof(double) * 8 * d.Nc, h->stream));
+  }
   Ctx c{h, h->stream, h->dinst, h->n, 0};
   c.chk(launch_reset_counters(h->dinst, h->n, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1282,9 +1314,49 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
     o[0] = row[OBS_N]; o[1] = row[OBS_D]; o[2] = row[OBS_EKIN]; o[3] = row[OBS_E];
     o[4] = row[OBS_SZZ_G]; o[5] = row[OBS_SZZ_DK]; o[6] = row[OBS_M2];
     o[7] = row[OBS_SZZ_G] != 0.0 ? 1.0 - row[OBS_SZZ_DK] / row[OBS_SZZ_G] : 0.0;
-    o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM];
+    o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM]; o[10] = row[OBS_CHI];
   }
   *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_measure_k(dqmc_handle h, int32_t on) {
+  if (!h) return DQMC_EINVAL;
+  h->measure_k = on != 0;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_nk(dqmc_handle h, int32_t inst, int32_t raw, double* host_out) {
+  if (!h || inst < 0 || inst >= h->n || !host_out) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  const int Nc = d.Nc, L = d.L;
+  std::vector<double> sum((size_t)8 * Nc);
+  InstState st;
+  HIPCHK(h, hipMemcpyAsync(sum.data(), d.nk_sum, sizeof(double) * sum.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&st, d.st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (st.n_meas < 1) return fail(h, DQMC_ESTATE, "no measurement taken");
+  const double inv = 1.0 / (double)st.n_meas;
+  const dqmc_instance_desc& x = h->desc[inst];
+  for (int k = 0; k < Nc; ++k) {
+    const double* m = &sum[(size_t)8 * k];
+    if (raw) {
+      for (int c = 0; c < 8; ++c) host_out[(size_t)8 * k + c] = m[c] * inv;
+      continue;
+    }
+    // Hermitian part of the mean, its eigenvalues, and |f| at k + A (eq. kpoints)
+    const double aa = m[0] * inv, bb = m[6] * inv;
+    const double abr = 0.5 * (m[2] + m[4]) * inv, abi = 0.5 * (m[3] - m[5]) * inv;
+    const double r = std::sqrt(0.25 * (aa - bb) * (aa - bb) + abr * abr + abi * abi);
+    const int l1 = k % L, l2 = k / L;
+    const double ka1 = (2.0 * M_PI * l1 + x.theta1) / L, ka2 = (2.0 * M_PI * l2 + x.theta2) / L;
+    const std::complex<double> fk = -x.t * (1.0 + std::polar(1.0, ka1 - ka2) + std::polar(1.0, -ka2));
+    double* o = host_out + (size_t)7 * k;
+    o[0] = std::abs(fk);
+    o[1] = aa; o[2] = bb; o[3] = abr; o[4] = abi;
+    o[5] = 0.5 * (aa + bb) + r;
+    o[6] = 0.5 * (aa + bb) - r;
+  }
   return DQMC_OK;
 }
 

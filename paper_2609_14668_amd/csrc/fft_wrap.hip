@@ -72,6 +72,10 @@ __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) 
       if (a.side != 0) return r;
       r.active = 1;
       return r;
+    case FOP_FOURIER:
+      if (st.init_mode) return r;
+      r.active = 1;
+      return r;
   }
   return r;
 }
@@ -326,6 +330,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     C* oth = cur == buf ? buf2 : buf;
     if constexpr (LC > 0) cur = fft_2d_fixed<LC>(cur, oth, roots, nvl, -1);
     else cur = fft_2d<RMAX>(cur, oth, roots, fac, L, Nc, N, nvl, -1);
+    if (a.op == FOP_FOURIER) break;   // forward transform only
     oth = cur == buf ? buf2 : buf;
     // 2x2 block per momentum
     const cplx* T = d.tab + (size_t)tabi * Nc * 4;
@@ -545,6 +550,7 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
     // axis 1, forward: line (vector, sublattice, k1) per thread
     if (b_act) line_dft<L, false>(pb_own, L, roots);
     __syncthreads();
+    if (a.op == FOP_FOURIER) break;   // forward transform only
     // 2x2 block per momentum: the thread of sublattice s forms row s of the
     // block from both lines of its column, then transforms it back
     C y[L];

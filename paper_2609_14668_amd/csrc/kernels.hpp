@@ -7,7 +7,10 @@
 // FOP_STAB_CHAIN: all n_stab B's of one chain step applied to the columns of
 // the working U in one pass (resolved per step as FOP_STAB_B with j = 0 ..
 // n_stab - 1), the columns scaled by the working D on the way out.
-enum FftOp : int { FOP_WRAP_PRE = 0, FOP_WRAP_POST, FOP_STAB_B, FOP_HALF, FOP_EXPLICIT, FOP_STAB_CHAIN };
+// FOP_FOURIER: only the forward 2-D DFT of each sublattice (columns: M <- F M,
+// rows: M <- M F^dagger), for the momentum-resolved estimators.
+enum FftOp : int { FOP_WRAP_PRE = 0, FOP_WRAP_POST, FOP_STAB_B, FOP_HALF, FOP_EXPLICIT, FOP_STAB_CHAIN,
+                   FOP_FOURIER };
 struct FftArgs {
   int op;      // FftOp
   int side;    // 0: columns (left multiplication), 1: rows (right multiplication)
@@ -113,6 +116,8 @@ hipError_t launch_detphase(const InstDev* insts, int n_inst, bool cplx_, int mod
 hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
 hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int blk, hipStream_t s);
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
+// momentum distribution sums from the forward-transformed G in mat
+hipError_t launch_measure_k(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
 
 // ---- proposal network (BF16 operands, FP32 accumulation) ---------------------------
 // Flat FP32 parameters: W1 [27][32][2], b1 [32], W2 [27][32][32], b2 [32],

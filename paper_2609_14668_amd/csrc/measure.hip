@@ -29,10 +29,12 @@ __device__ __forceinline__ double bsum(double v, double* red) {
 
 // Pair sums over i != j within each sublattice,
 //   pG = sum Re(G_ij G_ji),  pK = sum Re(G_ij G_ji) cos(2 pi (n1_j - n1_i) / L),
-// one workgroup per (sublattice, strip of PB rows i); the strip is walked in
-// PB x PB tiles, G[i, j] and G[j, i] both read down columns (coalesced) into
-// LDS.  The partials go to VEC_NORM (two per strip) and are summed in strip
-// order by k_measure.
+// one workgroup per (sublattice, strip of PB rows i), and over the
+// cross-sublattice pairs (i on A, j on B) pX = sum Re(G_ij G_ji) for the
+// charge compressibility, one workgroup per strip of A rows; each strip is
+// walked in PB x PB tiles, G[i, j] and G[j, i] both read down columns
+// (coalesced) into LDS.  The partials go to VEC_NORM (two per same-sublattice
+// strip, then one per cross strip) and are summed in strip order by k_measure.
 constexpr int PB = 32;
 template <typename S>
 __global__ void __launch_bounds__(MT) k_measure_pairs(const InstDev* __restrict__ insts, int mat) {
@@ -41,8 +43,11 @@ __global__ void __launch_bounds__(MT) k_measure_pairs(const InstDev* __restrict_
   if (st->init_mode || st->idle) return;
   const int N = d.N, Nc = d.Nc, L = d.L;
   const int nb = (Nc + PB - 1) / PB;
-  if ((int)blockIdx.x >= 2 * nb) return;
-  const int sub = blockIdx.x & 1, I0 = (blockIdx.x >> 1) * PB, base = sub * Nc;
+  if ((int)blockIdx.x >= 3 * nb) return;
+  const bool cross = (int)blockIdx.x >= 2 * nb;
+  const int sub = cross ? 0 : (blockIdx.x & 1);
+  const int I0 = (cross ? (int)blockIdx.x - 2 * nb : (int)(blockIdx.x >> 1)) * PB;
+  const int base = sub * Nc, jbase = cross ? Nc : base;
   const S* G = matp<S>(d, mat);
   __shared__ S Aij[PB][PB + 1], Aji[PB][PB + 1];
   __shared__ double cosL[64];
@@ -58,15 +63,15 @@ __global__ void __launch_bounds__(MT) k_measure_pairs(const InstDev* __restrict_
       const int cc = c0 + 8 * u;
       const int i = min(I0 + r, Nc - 1), j = min(J0 + cc, Nc - 1);
       const int jr = min(J0 + r, Nc - 1), ic = min(I0 + cc, Nc - 1);
-      Aij[r][cc] = gld(G + (base + i) + (size_t)(base + j) * N);     // G[I0 + r, J0 + cc]
-      Aji[r][cc] = gld(G + (base + jr) + (size_t)(base + ic) * N);   // G[J0 + r, I0 + cc]
+      Aij[r][cc] = gld(G + (base + i) + (size_t)(jbase + j) * N);     // G[I0 + r, J0 + cc]
+      Aji[r][cc] = gld(G + (jbase + jr) + (size_t)(base + ic) * N);   // G[J0 + r, I0 + cc]
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PB / 8; ++u) {
       const int a = r, b = c0 + 8 * u;
       const int ii = I0 + a, jj = J0 + b;
-      if (ii < Nc && jj < Nc && ii != jj) {
+      if (ii < Nc && jj < Nc && (cross || ii != jj)) {
         const double re = real_part(Aij[a][b] * Aji[b][a]);
         pG += re;
         pK += re * cosL[((jj % L) - (ii % L) + L) % L];
@@ -76,8 +81,12 @@ __global__ void __launch_bounds__(MT) k_measure_pairs(const InstDev* __restrict_
   pG = bsum(pG, red);
   pK = bsum(pK, red);
   if (threadIdx.x == 0) {
-    d.vec[VEC_NORM][2 * blockIdx.x] = pG;
-    d.vec[VEC_NORM][2 * blockIdx.x + 1] = pK;
+    if (cross) {
+      d.vec[VEC_NORM][4 * nb + (blockIdx.x - 2 * nb)] = pG;
+    } else {
+      d.vec[VEC_NORM][2 * blockIdx.x] = pG;
+      d.vec[VEC_NORM][2 * blockIdx.x + 1] = pK;
+    }
   }
 }
 
@@ -92,8 +101,12 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
   const double twopiL = 2.0 * M_PI / L;
   double sn = 0, sD = 0, sdc = 0;
   double zsum[2] = {0, 0}, zc[2] = {0, 0}, zs[2] = {0, 0};
+  double trr = 0, tri = 0, dsq = 0;   // Re, Im Tr G; sum_i Re(G_ii^2)
   for (int i = threadIdx.x; i < N; i += MT) {
     S g = G[i + (size_t)i * N];
+    trr += real_part(g);
+    tri += imag_part(g);
+    dsq += real_part(g * g);
     S a = ST<S>::one() - g;
     S b = conjg(g);
     double ab = real_part(a * b);
@@ -108,12 +121,13 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
     zs[sub] += z * sin(twopiL * n1);
   }
   // pair terms within each sublattice (i != j): partial sums of k_measure_pairs
-  double pG = 0, pK = 0;
-  const int nstrip = 2 * ((Nc + PB - 1) / PB);
+  double pG = 0, pK = 0, pX = 0;
+  const int nbs = (Nc + PB - 1) / PB, nstrip = 2 * nbs;
   for (int x = threadIdx.x; x < nstrip; x += MT) {
     pG += d.vec[VEC_NORM][2 * x];
     pK += d.vec[VEC_NORM][2 * x + 1];
   }
+  for (int x = threadIdx.x; x < nbs; x += MT) pX += d.vec[VEC_NORM][4 * nbs + x];
   // Tr(K G): K[A(r), B(r+delta)] = -t e^{+i Phi_delta}, Gauge-I phases
   const double ph[3] = {0.0, (d.theta1 - d.theta2) / L, -d.theta2 / L};
   const int dn1[3] = {0, 1, 0}, dn2[3] = {0, -1, -1};
@@ -138,7 +152,11 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
   double s0 = bsum(zs[0], red), s1 = bsum(zs[1], red);
   pG = bsum(pG, red);
   pK = bsum(pK, red);
+  pX = bsum(pX, red);
   tk = bsum(tk, red);
+  trr = bsum(trr, red);
+  tri = bsum(tri, red);
+  dsq = bsum(dsq, red);
   if (threadIdx.x == 0) {
     double n = sn / N;
     double D = sD / N;
@@ -150,6 +168,12 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
     v[OBS_N] = n; v[OBS_D] = D; v[OBS_EKIN] = ekin; v[OBS_E] = e;
     v[OBS_SZZ_G] = SG; v[OBS_SZZ_DK] = Sdk; v[OBS_M2] = SG / (2.0 * Nc);
     v[OBS_RM2_NUM] = Sdk; v[OBS_PHASE_RE] = st->ph_re; v[OBS_PHASE_IM] = st->ph_im;
+    // charge compressibility (eq. ChiCharge): (beta/N)(Re[(sum_i n_i)^2 +
+    // sum_s (Tr G^s - Tr G^s G^s)] - N^2) with sum_i n_i = N - 2 i Im Tr G and
+    // the spin-down traces the conjugates of the spin-up ones
+    const double retr2 = dsq + pG + 2.0 * pX;   // Re Tr(G G) over all pairs
+    const double beta = d.M * d.dtau;
+    v[OBS_CHI] = (beta / N) * (-4.0 * tri * tri + 2.0 * (trr - retr2));
     for (int k = 0; k < OBS_COUNT; ++k) {
       d.obs[k] += v[k];
       d.obs[OBS_COUNT + k] += v[k];
@@ -159,11 +183,46 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
   }
 }
 
+// Momentum distribution (eq. nkMatrix) from Ghat = F G F^dagger (the forward
+// 2-D DFT of both sides, in mat): spin up n_ab(k) = delta_ab - Ghat[b k, a k] / Nc,
+// spin down (G_dn = P (1 - G_up^dagger) P) n_ab(k) = s_a s_b conj(Ghat[a k, b k]) / Nc,
+// s_A = 1, s_B = -1; the spin average is added to the instance's sums.
+template <typename S>
+__global__ void __launch_bounds__(MT) k_measure_k(const InstDev* __restrict__ insts, int mat) {
+  const InstDev& d = insts[blockIdx.y];
+  const InstState* st = d.st;
+  if (st->init_mode || st->idle) return;
+  const int N = d.N, Nc = d.Nc;
+  const int k = blockIdx.x * MT + threadIdx.x;
+  if (k >= Nc) return;
+  const S* G = matp<S>(d, mat);
+  const double inv = 1.0 / Nc;
+  double* o = d.nk_sum + (size_t)8 * k;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const S gba = G[(b * Nc + k) + (size_t)(a * Nc + k) * N];   // Ghat[b k, a k]
+      const S gab = G[(a * Nc + k) + (size_t)(b * Nc + k) * N];   // Ghat[a k, b k]
+      const double sab = (a == b) ? 1.0 : -1.0;
+      const double up_re = (a == b ? 1.0 : 0.0) - real_part(gba) * inv, up_im = -imag_part(gba) * inv;
+      const double dn_re = sab * real_part(gab) * inv, dn_im = -sab * imag_part(gab) * inv;
+      o[4 * a + 2 * b] += 0.5 * (up_re + dn_re);
+      o[4 * a + 2 * b + 1] += 0.5 * (up_im + dn_im);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_measure_k(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s) {
+  const int ncm = Nmax / 2;
+  dim3 grid((ncm + MT - 1) / MT, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_measure_k<cplx>, grid, dim3(MT), 0, s, insts, mat);
+  else hipLaunchKernelGGL(k_measure_k<double>, grid, dim3(MT), 0, s, insts, mat);
+  return hipGetLastError();
+}
 
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s) {
   const int ncm = Nmax / 2;
-  dim3 grid(2 * ((ncm + PB - 1) / PB), n_inst);
+  dim3 grid(3 * ((ncm + PB - 1) / PB), n_inst);
   if (cplx_) hipLaunchKernelGGL(k_measure_pairs<cplx>, grid, dim3(MT), 0, s, insts, mat);
   else hipLaunchKernelGGL(k_measure_pairs<double>, grid, dim3(MT), 0, s, insts, mat);
   if (cplx_) hipLaunchKernelGGL(k_measure<cplx>, dim3(1, n_inst), dim3(MT), 0, s, insts, mat);

@@ -119,7 +119,7 @@ def test_replay_measurements_match_oracle():
     o = sim.measure(0)
     assert o["n_meas"] == len(ch.samples)
     for key, okey in (("D", "D"), ("ekin", "ekin"), ("e", "e"), ("Szz_G", "Szz_G"), ("Szz_dk", "Szz_dk"),
-                      ("m2", "m2"), ("n", "n")):
+                      ("m2", "m2"), ("n", "n"), ("chi_e", "chi_e")):
         ref = np.mean([s[okey] for s in ch.samples])
         assert abs(o[key] - ref) < 1e-10, key
 

@@ -21,7 +21,7 @@ from oracle.dqmc import BitSource, Chain, Model, PhiloxSource
 
 pytestmark = pytest.mark.gpu
 
-EST_KEYS = ("n", "D", "ekin", "e", "Szz_G", "Szz_dk", "m2")
+EST_KEYS = ("n", "D", "ekin", "e", "Szz_G", "Szz_dk", "m2", "chi_e")
 
 
 def _sim(descs):
@@ -37,13 +37,25 @@ def _model(d):
                  n_stab=d["n_stab"])
 
 
-def _check_estimators(o, samples, tol=1e-10):
+def _check_estimators(o, samples, tol=1e-10, sim=None, inst=0, lat=None):
     assert o["n_meas"] == len(samples)
     for key in EST_KEYS:
         ref = np.mean([s[key] for s in samples])
         assert abs(o[key] - ref) < tol, (key, o[key], ref)
     rm2 = 1.0 - np.mean([s["Szz_dk"] for s in samples]) / np.mean([s["Szz_G"] for s in samples])
     assert abs(o["Rm2"] - rm2) < tol
+    if sim is not None:
+        # momentum distribution (eq. nkMatrix): mean of the spin-averaged 2 x 2 n(k)
+        from oracle.dqmc import gab_dirac, nk_bands
+        nk_ref = np.mean([s["nk"] for s in samples], axis=0)
+        nk = sim.nk(inst, raw=True)
+        assert np.abs(nk - nk_ref).max() < tol
+        assert abs(o["GAB_dirac"] - gab_dirac(lat, nk_ref)) < tol
+        herm = 0.5 * (nk_ref + np.conj(np.transpose(nk_ref, (0, 2, 1))))
+        npl, nmi = nk_bands(herm)
+        d = sim.nk(inst)
+        assert np.abs(d["n_plus"] - npl).max() < tol and np.abs(d["n_minus"] - nmi).max() < tol
+        assert np.abs(d["eps"] - np.abs(lat.f_of_k(lat.kpoints()))).max() < 1e-12
 
 
 def _det_phase(model, fields):
@@ -71,7 +83,7 @@ def test_replay_twisted_estimators_match_oracle(sym):
         ch.sweep(src, measure=True)
     assert np.array_equal(sim.fields(0), ch.fields)
     assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
-    _check_estimators(sim.measure(0), ch.samples)
+    _check_estimators(sim.measure(0), ch.samples, sim=sim, inst=0, lat=m.lat)
 
 
 def test_instances_choose_their_own_measurement():
@@ -91,7 +103,7 @@ def test_instances_choose_their_own_measurement():
         ch = Chain(_model(descs[i]), fs[i], sym_measure=bool(i))
         ch.sweep(BitSource(bits[i]), measure=True)
         assert np.abs(sim.green(i) - ch.G[0]).max() < 1e-10
-        _check_estimators(sim.measure(i), ch.samples)
+        _check_estimators(sim.measure(i), ch.samples, sim=sim, inst=i, lat=ch.m.lat)
 
 
 def test_uneven_batch_replay_matches_oracle():
@@ -137,7 +149,7 @@ def test_uneven_batch_replay_matches_oracle():
         assert np.abs(ratios[i, :nr] - np.array(ch.ratios)).max() / np.abs(ch.ratios).max() < 1e-10
         st = sim.stats(i)
         assert st["accepted"] == ch.accepted and st["proposals"] == ch.proposals
-        _check_estimators(sim.measure(i), ch.samples)
+        _check_estimators(sim.measure(i), ch.samples, sim=sim, inst=i, lat=m.lat)
 
 
 def test_replay_twisted_L18_matches_oracle():
