@@ -71,9 +71,12 @@ typedef enum {
  * FFT in complex64 and the flushes form X Y with FP32 matrix cores (operands
  * rounded to float, FP32 accumulation); G stays stored in FP64, and the
  * acceptance ratios, the delayed-vector builder, the QR stabilisation and the
- * estimators stay FP64.  The accumulated single-precision error is reported
- * as the drift max |G_wrap - G_scratch| at each recomputation (dqmc_stats). */
-typedef enum { DQMC_FP64 = 0, DQMC_MIXED = 1 } dqmc_precision;
+ * estimators stay FP64.  DQMC_MIXED_FLUSH: only the flushes in FP32;
+ * DQMC_MIXED_WRAP: only the wraps in complex64.  The accumulated
+ * single-precision error is reported as the drift max |G_wrap - G_scratch|
+ * at each recomputation (dqmc_stats) and checked against the drift
+ * tolerance (dqmc_set_drift_tol). */
+typedef enum { DQMC_FP64 = 0, DQMC_MIXED = 1, DQMC_MIXED_FLUSH = 2, DQMC_MIXED_WRAP = 3 } dqmc_precision;
 
 /* One Markov chain.  All instances of a handle share n_stab, and every
  * beta/dtau must be a multiple of n_stab.  L in [2, 45] with prime factors in

@@ -94,7 +94,7 @@ dqmc_status validate(const dqmc_instance_desc* d, int n, std::string& err) {
     if (x.n_stab < 1 || ((int)std::lround(M)) % x.n_stab != 0) { err = "n_stab must divide beta/dtau"; return DQMC_EINVAL; }
     if (x.n_stab != d[0].n_stab) { err = "all instances must share n_stab"; return DQMC_EINVAL; }
     if (x.n_delay < 1 || x.n_delay > MAX_DELAY) { err = "n_delay must be in [1, 192]"; return DQMC_EINVAL; }
-    if (x.precision != DQMC_FP64 && x.precision != DQMC_MIXED) { err = "unknown precision"; return DQMC_EINVAL; }
+    if (x.precision < DQMC_FP64 || x.precision > DQMC_MIXED_WRAP) { err = "unknown precision"; return DQMC_EINVAL; }
     if (x.precision != d[0].precision) { err = "all instances must share the precision"; return DQMC_EINVAL; }
   }
   return DQMC_OK;
@@ -205,7 +205,9 @@ struct dqmc_ctx {
   std::vector<int> fixedL;   // distinct L with a compile-time FFT plan
   std::vector<int> fft_tile; // register-line tile of fixedL[q] for side s at [2 q + s]
   bool any_generic = false;  // some L uses the runtime-plan FFT
-  bool mixed = false;        // wraps and flushes in single precision
+  bool mixed = false;        // some step in single precision
+  bool single_wrap = false;  // wraps run the FFT in complex64
+  bool single_flush = false; // flushes form X Y with FP32 matrix cores
   // learned multi-site moves
   int learn_P = 0, learn_m = 0;   // moves per slice visit, sites per move
   int collect_every = 0;          // store a training sample every this many downward slices (0: off)
@@ -321,14 +323,14 @@ struct Ctx {
   // stabilisation and the measurement's half step stay in FP64.
   void fft(int op, int side, int mat, int j = 0) {
     FftArgs a{op, side, mat, j, 0, 0, 0, 0};
-    const bool single = h->mixed && (op == FOP_WRAP_PRE || op == FOP_WRAP_POST);
+    const bool single = h->single_wrap && (op == FOP_WRAP_PRE || op == FOP_WRAP_POST);
     chk(launch_fft(di, n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
                    (int)h->fixedL.size(), h->any_generic, single, h->fft_tile.data(), s));
   }
   void fft_explicit(int side, int mat, int pre, int tab, int post, int slice) {
     FftArgs a{FOP_EXPLICIT, side, mat, 0, pre, tab, post, slice};
     chk(launch_fft(di, n, h->Nmax, h->cplx, a, h->lds_budget, h->rmax, h->fixedL.data(),
-                   (int)h->fixedL.size(), h->any_generic, h->mixed, h->fft_tile.data(), s));
+                   (int)h->fixedL.size(), h->any_generic, h->single_wrap, h->fft_tile.data(), s));
   }
   void gemm(GemmOperand A, GemmOperand B, GemmOperand C, GemmDim M, GemmDim N, GemmDim K,
             double alpha, double beta, int flags = 0) {
@@ -474,8 +476,8 @@ double wrap_pass_bytes(dqmc_ctx* h, int64_t s, bool up) {
 // kernel or the LDS-tiled GEMM (chosen by the autotuner).
 void flush(Ctx& c, int flags) {
   dqmc_ctx* h = c.h;
-  if (h->mixed || h->flush_variant == 0) {
-    c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->mixed, flags, c.s));
+  if (h->single_flush || h->flush_variant == 0) {
+    c.chk(launch_flush_direct(c.di, c.n, h->Nmax, h->cplx, h->single_flush, flags, c.s));
   } else if (h->flush_variant == 2) {
     // resident workgroups per CU: two for complex (217 VGPRs), three for real
     c.chk(launch_flush_queue(c.di, c.n, h->cplx, flags, (h->cplx ? 2 : 3) * h->n_cu, c.s));
@@ -683,7 +685,9 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
   h->Nmax = p.Nmax;
   h->Mmax = p.Mmax;
   h->n_stab = p.n_stab;
-  h->mixed = d[0].precision == DQMC_MIXED;
+  h->mixed = d[0].precision != DQMC_FP64;
+  h->single_wrap = d[0].precision == DQMC_MIXED || d[0].precision == DQMC_MIXED_WRAP;
+  h->single_flush = d[0].precision == DQMC_MIXED || d[0].precision == DQMC_MIXED_FLUSH;
   h->desc.assign(d, d + n);
   h->plan = p;
   for (int i = 0; i < n; ++i) {
@@ -740,7 +744,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.is_complex = p.cplx;
     dv.sym_measure = x.sym_measure;
     dv.fft_fixed = fft_has_fixed(x.L) ? 1 : 0;
-    dv.mixed = x.precision == DQMC_MIXED ? 1 : 0;
+    dv.mixed = x.precision != DQMC_FP64 ? 1 : 0;
     dv.lam = std::acosh(std::exp(x.dtau * x.U / 2.0));
     dv.U = x.U; dv.dtau = x.dtau; dv.t = x.t;
     dv.theta1 = x.theta1; dv.theta2 = x.theta2;
@@ -1034,7 +1038,7 @@ dqmc_status dqmc_set_delay(dqmc_handle h, int32_t k) {
 
 dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant) {
   if (!h || variant < 0 || variant > 2) return DQMC_EINVAL;
-  h->flush_variant = h->mixed ? 0 : variant;
+  h->flush_variant = h->single_flush ? 0 : variant;
   return DQMC_OK;
 }
 
@@ -1049,7 +1053,7 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
   h->timing = false;
   double best_ms = 1e300;
   int32_t bk = h->hd[0].kflush, bv = h->flush_variant;
-  const int nvar = h->mixed ? 1 : FLUSH_KERNELS;
+  const int nvar = h->single_flush ? 1 : FLUSH_KERNELS;
   dqmc_status st = DQMC_OK;
   for (int q = 0; q < n_cand && st == DQMC_OK; ++q) {
     st = dqmc_set_delay(h, cand[q]);

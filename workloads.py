@@ -74,8 +74,8 @@ def twist_L18(chains_per_twist=4, n_grid=4, n_small=16, k=None):
     return out
 
 
-def mixed_L30(precision=1):
-    return [desc(30, 3.73, 30.0, theta=(0.3 * math.pi, 0.7 * math.pi), k=64, precision=precision)]
+def mixed_L30(precision=1, n_stab=10):
+    return [desc(30, 3.73, 30.0, theta=(0.3 * math.pi, 0.7 * math.pi), k=64, precision=precision, n_stab=n_stab)]
 
 
 def plain_L42(n_chains=1):
