@@ -62,6 +62,8 @@ def parse():
                     help="with --no-autotune: the flush kernel to use")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--y-solver", choices=("lu", "qr"), default="lu",
+                    help="how the recomputations apply Y^-1 (pivoted LU or Householder QR)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every step eagerly (counter collection does not follow graph launches)")
     ap.add_argument("--groups", type=int, choices=(1, 2, 3, 4), default=None,
@@ -287,6 +289,7 @@ def main():
         sim.set_streams(a.groups)
     if a.no_graphs:
         sim.set_graphs(False)
+    sim.set_y_solver(1 if a.y_solver == "lu" else 0)
     tuned = None
     if a.flush_kernel:
         sim.set_flush_kernel(FLUSH_NAMES.index(a.flush_kernel))
@@ -334,7 +337,7 @@ def main():
                   else ("c128" if sim.shapes[0][2] else "f64")),
         "data": "synthetic",
         "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
-                   "dtau": descs[0]["dtau"], "proposal": "plain"},
+                   "dtau": descs[0]["dtau"], "proposal": "plain", "y_solver": a.y_solver},
         "autotune": tuned,
         "ess_per_s": plain["ess_per_s"],
         "ess_per_s_err": plain["ess_per_s_err"],

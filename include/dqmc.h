@@ -199,6 +199,14 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
 /* Estimator means of instance inst (see dqmc_obs); synchronises.
  * DQMC_ENUMERIC (out still filled) if the instance hit a numerical error. */
 dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out);
+/* How a recomputation applies Y^{-1} in G = U_L D_Lb^{-1} Y^{-1} D_Rb^{-1}
+ * U_R^H (eq. GrFMat with the split of D into its large and small parts,
+ * Sec. II B): lu = 1 (default) factors Y by LU with partial pivoting, whose
+ * trailing updates are MFMA GEMMs; lu = 0 by a second Householder QR.  Both
+ * give G to rounding (Y is well conditioned after the split); the phase of
+ * det Y comes from the pivots and diag U, or from the reflectors and diag R.
+ * DQMC_EINVAL for other values. */
+dqmc_status dqmc_set_y_solver(dqmc_handle h, int32_t lu);
 /* Momentum distribution (eq. nkMatrix) with every measurement: G of each
  * instance (or its half-step G~) is Fourier transformed on both sides,
  * Ghat = F G F^dagger (F the unnormalised per-sublattice 2-D DFT of the

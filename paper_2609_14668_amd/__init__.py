@@ -73,6 +73,7 @@ _SIGS = {
     "dqmc_measure": [_P, ctypes.c_int32, ctypes.POINTER(Obs)],
     "dqmc_reset_obs": [_P],
     "dqmc_set_measure_k": [_P, ctypes.c_int32],
+    "dqmc_set_y_solver": [_P, ctypes.c_int32],
     "dqmc_get_nk": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
@@ -268,6 +269,12 @@ class Simulation:
         return d
 
     measure = dqmc_measure
+
+    def dqmc_set_y_solver(self, lu):
+        """1: Y^{-1} by pivoted LU (default); 0: by Householder QR."""
+        self._chk(self.lib.dqmc_set_y_solver(self.h, int(lu)), "set_y_solver")
+
+    set_y_solver = dqmc_set_y_solver
 
     def dqmc_set_measure_k(self, on):
         self._chk(self.lib.dqmc_set_measure_k(self.h, int(bool(on))), "set_measure_k")

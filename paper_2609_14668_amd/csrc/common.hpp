@@ -215,7 +215,8 @@ struct InstDev {
   const cplx* tab;          // 4 tables x Nc x (2x2): exp(-dtau h)/Nc, exp(+dtau h)/Nc, half steps
   const cplx* roots;        // L-th roots of unity exp(-2 pi i m / L)
   const int32_t* factors;   // radix list of L (terminated by 0)
-  int32_t* perm;            // column permutation of the current QR
+  int32_t* perm;            // 2N: column permutation of the current QR, or the LU's
+                            // interchanges; then the LU's composed row order of Y
   int32_t* acc_site;        // accepted sites: position in the window (or in S)
   int32_t* acc_gsite;       // accepted sites: site index
   float* targets;           // M x N single-flip acceptance after each decision (downward pass)

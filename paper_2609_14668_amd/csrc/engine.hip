@@ -124,7 +124,7 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.tab = o; o = al(o + sizeof(cplx) * 16 * Nc);
     f.roots = o; o = al(o + sizeof(cplx) * 64);
     f.factors = o; o = al(o + sizeof(int32_t) * 16);
-    f.perm = o; o = al(o + sizeof(int32_t) * N);
+    f.perm = o; o = al(o + sizeof(int32_t) * 2 * N);
     f.acc = o; o = al(o + sizeof(int32_t) * WINDOW);
     f.gsite = o; o = al(o + sizeof(int32_t) * WINDOW);
     f.wcoef = o; o = al(o + ss * (WINDOW + 2 * WINDOW * WINDOW));
@@ -213,6 +213,7 @@ struct dqmc_ctx {
   int collect_every = 0;          // store a training sample every this many downward slices (0: off)
   int flush_variant = 0;          // 0: wave-per-block flush, 1: LDS-tiled GEMM, 2: work-queue flush (FP64 only)
   bool measure_k = true;          // momentum distribution with every measurement
+  bool y_lu = true;               // Y^{-1} by pivoted LU (false: by Householder QR)
   int n_cu = 256;                 // compute units (persistent grids)
   // instance groups on their own streams (see issue_steps)
   int n_groups = 1;
@@ -403,6 +404,48 @@ void upper_solve(Ctx& c) {
   upper_solve_blocks(c, 0, nblk);
 }
 
+// MAT_QA <- its LU factors with partial pivoting, P Y = L U (L unit lower,
+// U upper, in place), recursively over column halves: factor the left half,
+// A12 <- L11^{-1} A12, A22 <- A22 - A21 A12 (one MFMA GEMM whose depth is
+// the left half's width), factor the right half.  The leaves are 16-column
+// register panels; their row interchanges go to every other column at once,
+// and the composed row permutation of Y collects in perm[N ..] (set to the
+// identity by EO_BUILD_Y).  Column offsets count from 0 for every instance,
+// so instances of a batch with smaller N drop out of the later launches.
+void lower_solve(Ctx& c, int r0, int r1, int col0, int col1, int target);
+
+void lu_factor(Ctx& c, int c0, int c1) {
+  const int w = c1 - c0;
+  if (w <= LU_NB) {
+    c.chk(launch_lu_panel(c.di, c.n, c.h->Nmax, c.h->cplx, c0, w, c.s));
+    c.chk(launch_lu_swap(c.di, c.n, c.h->Nmax, c.h->cplx, c0, w, c.s));
+    return;
+  }
+  const int mid = c0 + ((w / 2 + LU_NB - 1) / LU_NB) * LU_NB;
+  lu_factor(c, c0, mid);
+  lower_solve(c, c0, mid, mid, c1, MAT_QA);
+  // A22 -= A21 A12: rows [mid, N), columns [mid, min(c1, N)), depth mid - c0
+  c.gemm(opnd(MAT_QA, 0, 0, mid, 0, c0), opnd(MAT_QA, 0, 0, c0, 0, mid), opnd(MAT_QA, 0, 0, mid, 0, mid),
+         dim(1, -mid), dim(1, -mid, c1 - mid), dim(0, mid - c0), -1.0, 1.0);
+  lu_factor(c, mid, c1);
+}
+
+// target[r0:r1, col0:col1] <- L^{-1} target[r0:r1, col0:col1] with L the unit
+// lower triangle of MAT_QA's rows and columns [r0, r1): 32-row diagonal
+// blocks, halves joined by one GEMM (rows and columns clipped at each
+// instance's N).
+void lower_solve(Ctx& c, int r0, int r1, int col0, int col1, int target) {
+  if (r1 - r0 <= TL_NB) {
+    c.chk(launch_trsm_lower(c.di, c.n, c.h->cplx, r0, r1 - r0, col0, col1, target, c.s));
+    return;
+  }
+  const int rm = r0 + ((r1 - r0) / 2 + TL_NB - 1) / TL_NB * TL_NB;
+  lower_solve(c, r0, rm, col0, col1, target);
+  c.gemm(opnd(MAT_QA, 0, 0, rm, 0, r0), opnd(target, 0, 0, r0, 0, col0), opnd(target, 0, 0, rm, 0, col0),
+         dim(1, -rm, r1 - rm), dim(1, -col0, col1 - col0), dim(0, rm - r0), -1.0, 1.0);
+  lower_solve(c, rm, r1, col0, col1, target);
+}
+
 // One checkpoint: advance the working UDV chain by n_stab slices, recompute
 // G against the stack partner, record the drift, replace G, store the chain.
 void stabilise(Ctx& c, bool measure) {
@@ -425,10 +468,18 @@ void stabilise(Ctx& c, bool measure) {
   c.gemm(opnd(MAT_RU, 2), opnd(MAT_LU, 0), opnd(MAT_W1, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
   c.gemm(opnd(MAT_RT, 0), opnd(MAT_LT, 2), opnd(MAT_W2, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
   c.elem(EO_BUILD_Y, MAT_W1, MAT_W2, MAT_QA);
-  c.elem(EO_BUILD_RHS, 0, 0, MAT_W3);
-  qr_factor(c);
-  c.chk(launch_detphase(c.di, c.n, h->cplx, 1, c.s));
-  apply_qh(c, MAT_W3);
+  if (h->y_lu) {
+    // Y^{-1} RHS = U^{-1} L^{-1} (P RHS), the RHS built with P's row order
+    lu_factor(c, 0, h->Nmax);
+    c.chk(launch_detphase(c.di, c.n, h->cplx, 2, c.s));
+    c.elem(EO_BUILD_RHS, 0, 0, MAT_W3, 1);
+    lower_solve(c, 0, h->Nmax, 0, h->Nmax, MAT_W3);
+  } else {
+    c.elem(EO_BUILD_RHS, 0, 0, MAT_W3);
+    qr_factor(c);
+    c.chk(launch_detphase(c.di, c.n, h->cplx, 1, c.s));
+    apply_qh(c, MAT_W3);
+  }
   upper_solve(c);
   c.elem(EO_SCALE_ROWS_DLB, 0, 0, MAT_W3);
   c.gemm(opnd(MAT_LU, 0), opnd(MAT_W3, 0), opnd(MAT_GS, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
@@ -959,7 +1010,7 @@ static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hip
 // memory: the launches of a step are fixed by these.
 static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, int groups) {
   std::vector<int> k = {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant,
-                        h->kcap_max, h->measure_k ? 1 : 0};
+                        h->kcap_max, h->measure_k ? 1 : 0, h->y_lu ? 1 : 0};
   k.insert(k.end(), h->fft_tile.begin(), h->fft_tile.end());
   return k;
 }
@@ -1321,6 +1372,12 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
     o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM]; o[10] = row[OBS_CHI];
   }
   *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_y_solver(dqmc_handle h, int32_t lu) {
+  if (!h || (lu != 0 && lu != 1)) return DQMC_EINVAL;
+  h->y_lu = lu != 0;
   return DQMC_OK;
 }
 

@@ -86,7 +86,7 @@ enum ElemOp : int {
   EO_GATHER_COLS,     // mat c[:, j] = mat a[:, perm[j]]
   EO_GATHER_ROWS,     // mat c[i, :] = mat a[perm[i], :]
   EO_BUILD_Y,         // c = D_Rb^-1 a D_Lb^-1 + D_Rs b D_Ls  (a = U_R^H U_L, b = T_R T_L^H)
-  EO_BUILD_RHS,       // c = D_Rb^-1 U_R^H
+  EO_BUILD_RHS,       // c = D_Rb^-1 U_R^H (v = 1: rows in the LU's row order)
   EO_SCALE_ROWS_DLB,  // c[i, :] /= max(D_L[i], 1)
   EO_STACK_STORE,     // stack slot <- working chain (interior checkpoints only)
   EO_STACK_IDENTITY,  // every stack slot <- identity chain
@@ -113,6 +113,15 @@ hipError_t launch_apply_refl(const InstDev* insts, int n_inst, int Nmax, bool cp
 hipError_t launch_stab_finish(const InstDev* insts, int n_inst, hipStream_t s);
 // phase of det U of the chain step (mode 0) / anchored phase of det(1 + B..B) (mode 1)
 hipError_t launch_detphase(const InstDev* insts, int n_inst, bool cplx_, int mode, hipStream_t s);
+// LU with partial pivoting of MAT_QA: leaf panel of columns [c0, c0 + nbw)
+// (nbw <= 16, pivots to perm), its interchanges on the rest of MAT_QA and on
+// MAT_W3, and the unit lower-triangular block solve (nb <= 32 rows from r0)
+// on columns [col0, col1) of a target with L from MAT_QA.
+constexpr int LU_NB = 16, TL_NB = 32;
+hipError_t launch_lu_panel(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int c0, int nbw, hipStream_t s);
+hipError_t launch_lu_swap(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int c0, int nbw, hipStream_t s);
+hipError_t launch_trsm_lower(const InstDev* insts, int n_inst, bool cplx_, int r0, int nb, int col0, int col1,
+                             int target, hipStream_t s);
 hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
 hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int blk, hipStream_t s);
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);

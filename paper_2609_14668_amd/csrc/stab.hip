@@ -102,6 +102,7 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
       S* c = matp<S>(d, e.c);
       const double* dr = vec_ptr(d, VEC_RD);
       const double* dl = vec_ptr(d, VEC_LD);
+      for (size_t x = e0; x < (size_t)N; x += stride) d.perm[N + x] = (int)x;   // row order of the LU
       for (size_t x = e0; x < NN; x += stride) {
         size_t i = x % N, j = x / N;
         double rb = fmax(dr[i], 1.0), rs = fmin(dr[i], 1.0);
@@ -110,12 +111,14 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
       }
       break;
     }
-    case EO_BUILD_RHS: {
+    case EO_BUILD_RHS: {   // v = 1: rows in the LU's order, row i from row perm[N + i]
       const S* u = matp<S>(d, MAT_RU);
       S* c = matp<S>(d, e.c);
       const double* dr = vec_ptr(d, VEC_RD);
+      const int* rp = d.perm + N;
       for (size_t x = e0; x < NN; x += stride) {
         size_t i = x % N, j = x / N;
+        if (e.v) i = (size_t)rp[i];
         c[x] = conjg(u[j + i * N]) * (1.0 / fmax(dr[i], 1.0));
       }
       break;
@@ -1184,6 +1187,233 @@ __global__ void __launch_bounds__(256) k_trsm_diag(const InstDev* __restrict__ i
     if (r < nr) B[(i0 + r) + (size_t)j * N] = z[r];
 }
 
+// ---- LU with partial pivoting of Y (MAT_QA), for G = ... Y^{-1} ... ----------------------
+template <typename S, int PT>
+struct LuShared {
+  double redv[PT / 64];
+  int redi[PT / 64];
+  S prow[NBR], orow[NBR];
+};
+
+// Column C of the leaf panel (compile-time, so the register array is indexed
+// with constants): the pivot (largest |a|^2 on or below the diagonal row
+// r = c0 + C, ties to the smaller row) by a block-wide arg-max, the swap of
+// rows r and p through LDS, the multipliers and the update of the later
+// panel columns.  Two barriers per column.
+template <typename S, int RPT, int PT, int C>
+struct LuColumn {
+  static __device__ __forceinline__ void run(S (&a)[RPT][NBR], LuShared<S, PT>& sh, int* piv, int c0, int N,
+                                             int nbe) {
+    if constexpr (C < NBR) {
+      if (C < nbe) {
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int r = c0 + C;
+        double best = -1.0;
+        int bi = N;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int i = c0 + tid + PT * q;
+          const double v = absq(a[q][C]);
+          if (i >= r && i < N && v > best) { best = v; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) { sh.redv[wave] = best; sh.redi[wave] = bi; }
+        __syncthreads();
+        best = sh.redv[0];
+        bi = sh.redi[0];
+#pragma unroll
+        for (int w = 1; w < PT / 64; ++w)
+          if (sh.redv[w] > best || (sh.redv[w] == best && sh.redi[w] < bi)) { best = sh.redv[w]; bi = sh.redi[w]; }
+        const int p = bi < N ? bi : r;
+        // row r sits in thread C (q = 0); row p in thread (p - c0) % PT
+        const int ow_p = (p - c0) % PT, q_p = (p - c0) / PT;
+        // (selects rather than branches on q: merged branches would index the
+        // register array with a variable and demote it to scratch memory)
+        if (tid == ow_p) {
+          S sel[NBR];
+#pragma unroll
+          for (int cc = 0; cc < NBR; ++cc) sel[cc] = a[0][cc];
+#pragma unroll
+          for (int q = 1; q < RPT; ++q)
+#pragma unroll
+            for (int cc = 0; cc < NBR; ++cc) sel[cc] = psel(q == q_p, a[q][cc], sel[cc]);
+#pragma unroll
+          for (int cc = 0; cc < NBR; ++cc) sh.prow[cc] = sel[cc];
+        }
+        if (tid == C) {
+#pragma unroll
+          for (int cc = 0; cc < NBR; ++cc) sh.orow[cc] = a[0][cc];
+          piv[r] = p;
+        }
+        __syncthreads();
+        if (tid == C) {
+#pragma unroll
+          for (int cc = 0; cc < NBR; ++cc) a[0][cc] = sh.prow[cc];
+        }
+        if (tid == ow_p && p != r) {
+#pragma unroll
+          for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int cc = 0; cc < NBR; ++cc) a[q][cc] = psel(q == q_p, sh.orow[cc], a[q][cc]);
+        }
+        const S inv = cdiv(ST<S>::one(), sh.prow[C]);
+        S pr[NBR];
+#pragma unroll
+        for (int cc = C + 1; cc < NBR; ++cc) pr[cc] = sh.prow[cc];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int i = c0 + tid + PT * q;
+          if (i > r && i < N) {
+            const S l = a[q][C] * inv;
+            a[q][C] = l;
+#pragma unroll
+            for (int cc = C + 1; cc < NBR; ++cc) a[q][cc] = a[q][cc] - l * pr[cc];
+          }
+        }
+      }
+      LuColumn<S, RPT, PT, C + 1>::run(a, sh, piv, c0, N, nbe);
+    }
+  }
+};
+
+// Leaf panel of the recursive LU: columns [c0, c0 + nbw) (nbw <= 16), rows
+// [c0, N) held in registers (thread t owns rows c0 + t + PT q).  The
+// interchanges go to perm[c0 ..] (row r swapped with perm[r]); applying them
+// to the other columns is k_lu_swap's job.
+template <typename S, int RPT, int PT>
+__global__ void __launch_bounds__(PT) k_lu_panel(const InstDev* __restrict__ insts, int c0, int nbw) {
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  if (c0 >= N) return;
+  const int nbe = min(nbw, N - c0);
+  S* A = matp<S>(d, MAT_QA);
+  const int tid = threadIdx.x;
+  __shared__ LuShared<S, PT> sh;
+  S a[RPT][NBR];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = c0 + tid + PT * q;
+#pragma unroll
+    for (int c = 0; c < NBR; ++c) a[q][c] = gld(A + min(i, N - 1) + (size_t)(c0 + min(c, nbe - 1)) * N);
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = c0 + tid + PT * q;
+#pragma unroll
+    for (int c = 0; c < NBR; ++c) a[q][c] = psel(i < N && c < nbe, a[q][c], ST<S>::zero());
+  }
+  LuColumn<S, RPT, PT, 0>::run(a, sh, d.perm, c0, N, nbe);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = c0 + tid + PT * q;
+    if (i < N) {
+#pragma unroll
+      for (int c = 0; c < NBR; ++c)
+        if (c < nbe) A[i + (size_t)(c0 + c) * N] = a[q][c];
+    }
+  }
+}
+
+// The interchanges of the leaf panel [c0, c0 + nbw), in order, on every
+// column of MAT_QA outside the panel.  Every wave first composes them into
+// one map of at most 2 nbw rows (lane e holds row pos_e, whose new content
+// is the old row src_e): the panel rows start in lanes 0 .. nbe - 1, a pivot
+// row outside the panel takes the next free lane.  Each half-wave then moves
+// the rows of one column: a coalesced gather of the sources, then the stores.
+template <typename S>
+__global__ void __launch_bounds__(256) k_lu_swap(const InstDev* __restrict__ insts, int c0, int nbw) {
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  if (c0 >= N) return;
+  const int nbe = min(nbw, N - c0);
+  const int lane = threadIdx.x & 63, e = lane & 31;
+  const int* piv = d.perm;
+  int pos = e < nbe ? c0 + e : -1;
+  int src = pos;
+  int cnt = nbe;
+  for (int c = 0; c < nbe; ++c) {
+    const int b = piv[c0 + c];
+    if (b == c0 + c) continue;
+    unsigned long long m = __ballot(pos == b) & 0xffffffffull;
+    int lb;
+    if (m == 0) {
+      lb = cnt++;
+      if (e == lb) { pos = b; src = b; }
+    } else {
+      lb = __ffsll(m) - 1;
+    }
+    const int sa = __shfl(src, c), sb = __shfl(src, lb);
+    if (e == c) src = sb;
+    if (e == lb) src = sa;
+  }
+  const bool mv = e < cnt && src != pos;
+  if (!__any(mv)) return;
+  S* A = matp<S>(d, MAT_QA);
+  const int half = lane >> 5;
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  if (blockIdx.x == 0 && threadIdx.x < 32 && mv) {   // the composed row order of Y
+    int* rp = d.perm + N;
+    const int v = rp[src];
+    rp[pos] = v;
+  }
+  // columns handled by this block: [j0, j0 + 64)
+  const int j0 = blockIdx.x * 64;
+  for (int jj = 2 * wave + half; jj < 64; jj += 2 * nwave) {
+    const int j = j0 + jj;
+    if (j >= N || (j >= c0 && j < c0 + nbe)) continue;
+    S* col = A + (size_t)j * N;
+    S v = ST<S>::zero();
+    if (mv) v = col[src];
+    if (mv) col[pos] = v;
+  }
+}
+
+// Unit lower-triangular solve on rows [r0, r0 + nb) (nb <= 32) of columns
+// [col0, col1) of a target, L from the strict lower part of MAT_QA: one thread
+// per column, the L block in LDS.
+static_assert(TL_NB == 32, "k_trsm_lower holds 32 rows");
+constexpr int TL_ROWS = TL_NB;
+template <typename S>
+__global__ void __launch_bounds__(256) k_trsm_lower(const InstDev* __restrict__ insts, int r0, int nb, int col0,
+                                                    int col1, int target) {
+  const InstDev& d = insts[blockIdx.y];
+  if (d.st->idle) return;
+  const int N = d.N;
+  if (r0 >= N) return;
+  const int nr = min(nb, N - r0);
+  const S* Lm = matp<S>(d, MAT_QA);
+  S* B = matp<S>(d, target);
+  __shared__ S Lb[TL_ROWS][TL_ROWS + 1];
+  for (int x = threadIdx.x; x < nr * nr; x += blockDim.x) {
+    const int r = x % nr, c = x / nr;
+    Lb[r][c] = Lm[(r0 + r) + (size_t)(r0 + c) * N];
+  }
+  __syncthreads();
+  const int j = col0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= min(col1, N)) return;
+  S z[TL_ROWS];
+#pragma unroll
+  for (int r = 0; r < TL_ROWS; ++r) z[r] = r < nr ? B[(r0 + r) + (size_t)j * N] : ST<S>::zero();
+#pragma unroll
+  for (int r = 1; r < TL_ROWS; ++r) {
+    if (r < nr) {
+      S s2 = z[r];
+#pragma unroll
+      for (int c = 0; c < r; ++c) s2 = s2 - Lb[r][c] * z[c];
+      z[r] = s2;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < TL_ROWS; ++r)
+    if (r < nr) B[(r0 + r) + (size_t)j * N] = z[r];
+}
+
 // After the drift of a recomputation has been accumulated (EO_DRIFT_REPLACE):
 // drift_last = this recomputation's max |G_wrap - G_scratch|, drift_max the
 // running maximum, NUMERR_DRIFT when it exceeds the instance's tolerance.
@@ -1205,6 +1435,8 @@ __global__ void k_stab_finish(const InstDev* __restrict__ insts) {
 // det Q = prod_j det H_j.
 //   mode 0 (after the chain step's QR A P = Q R): the working chain's new U is
 //          Q, so phw = phase det Q.
+//   mode 2 (after the LU P Y = L U of the recomputation): as mode 1 with
+//          ph(det Y) = (-1)^(number of interchanges) prod_i ph(U_ii).
 //   mode 1 (after the QR Y = Q_Y R_Y of the recomputation): with
 //          1 + R L = U_R D_Rb Y D_Lb U_L^dagger (D positive), the phase of
 //          det(1 + B_M .. B_1) = det(1 + R L) (cyclic invariance) is
@@ -1220,14 +1452,18 @@ __global__ void __launch_bounds__(256) k_detphase(const InstDev* __restrict__ in
   const S* A = matp<S>(d, MAT_QA);
   double pr = 1.0, pi = 0.0;
   for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    const double tr = tauv[2 * j], ti = tauv[2 * j + 1];
-    const double t2 = tr * tr + ti * ti;
     double fr = 1.0, fi = 0.0;
-    if (t2 > 0.0) {   // -tau^2 / |tau|^2
-      fr = -(tr * tr - ti * ti) / t2;
-      fi = -(2.0 * tr * ti) / t2;
+    if (mode == 2) {
+      if (d.perm[j] != j) fr = -1.0;
+    } else {
+      const double tr = tauv[2 * j], ti = tauv[2 * j + 1];
+      const double t2 = tr * tr + ti * ti;
+      if (t2 > 0.0) {   // -tau^2 / |tau|^2
+        fr = -(tr * tr - ti * ti) / t2;
+        fi = -(2.0 * tr * ti) / t2;
+      }
     }
-    if (mode == 1) {
+    if (mode >= 1) {
       const S rjj = A[j + (size_t)j * N];
       const double ra = sqrt(absq(rjj));
       if (ra > 0.0) {
@@ -1285,6 +1521,47 @@ __global__ void __launch_bounds__(256) k_detphase(const InstDev* __restrict__ in
 }
 
 }  // namespace
+
+hipError_t launch_lu_panel(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int c0, int nbw, hipStream_t s) {
+#define DQMC_LUP(R, T)                                                                                          \
+  if (cplx_) hipLaunchKernelGGL((k_lu_panel<cplx, R, T>), dim3(1, n_inst), dim3(T), 0, s, insts, c0, nbw);      \
+  else hipLaunchKernelGGL((k_lu_panel<double, R, T>), dim3(1, n_inst), dim3(T), 0, s, insts, c0, nbw);
+  const int rows = Nmax - c0;
+  if (rows <= 0) return hipSuccess;
+  if (rows <= 1024) {
+    const int rpt = (rows + 255) / 256;
+    if (rpt <= 1) { DQMC_LUP(1, 256) }
+    else if (rpt <= 2) { DQMC_LUP(2, 256) }
+    else if (rpt <= 3) { DQMC_LUP(3, 256) }
+    else { DQMC_LUP(4, 256) }
+  } else if (rows <= 2048) {
+    if (rows <= 1536) { DQMC_LUP(3, 512) }
+    else { DQMC_LUP(4, 512) }
+  } else if (rows <= 4096) {
+    if (rows <= 3072) { DQMC_LUP(3, 1024) }
+    else { DQMC_LUP(4, 1024) }
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef DQMC_LUP
+  return hipGetLastError();
+}
+
+hipError_t launch_lu_swap(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int c0, int nbw, hipStream_t s) {
+  dim3 grid((Nmax + 63) / 64, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_lu_swap<cplx>, grid, dim3(256), 0, s, insts, c0, nbw);
+  else hipLaunchKernelGGL(k_lu_swap<double>, grid, dim3(256), 0, s, insts, c0, nbw);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_lower(const InstDev* insts, int n_inst, bool cplx_, int r0, int nb, int col0, int col1,
+                             int target, hipStream_t s) {
+  if (nb > TL_ROWS || col1 <= col0) return col1 <= col0 ? hipSuccess : hipErrorInvalidValue;
+  dim3 grid((col1 - col0 + 255) / 256, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_trsm_lower<cplx>, grid, dim3(256), 0, s, insts, r0, nb, col0, col1, target);
+  else hipLaunchKernelGGL(k_trsm_lower<double>, grid, dim3(256), 0, s, insts, r0, nb, col0, col1, target);
+  return hipGetLastError();
+}
 
 hipError_t launch_stab_finish(const InstDev* insts, int n_inst, hipStream_t s) {
   hipLaunchKernelGGL(k_stab_finish, dim3(1, n_inst), dim3(64), 0, s, insts);

@@ -82,9 +82,10 @@ def test_initial_green_matches_oracle(L, th, beta):
     assert np.abs(sim.green(0, spin=1) - refd).max() < 1e-10
 
 
-def _replay_case(d, seed, p=0.4, sweeps=1, measure=False):
+def _replay_case(d, seed, p=0.4, sweeps=1, measure=False, y_solver=1):
     import torch
     sim = _sim([d])
+    sim.set_y_solver(y_solver)
     m = _model(d)
     N, M, cx = sim.shapes[0]
     f0 = workloads.random_fields(seed, M, N)
@@ -100,10 +101,13 @@ def _replay_case(d, seed, p=0.4, sweeps=1, measure=False):
     return sim, ch, ratios.cpu().numpy().ravel()
 
 
+@pytest.mark.parametrize("y_solver", [1, 0])
 @pytest.mark.parametrize("L,th,beta,k", [(3, (0, 0), 3.0, 8), (4, (0.7, 2.2), 2.0, 16), (6, (0, 0), 2.0, 24)])
-def test_replay_sweep_matches_oracle(L, th, beta, k):
+def test_replay_sweep_matches_oracle(L, th, beta, k, y_solver):
+    """Both ways of applying Y^{-1} in the recomputations (pivoted LU, the
+    default, and Householder QR) reproduce the oracle's chain."""
     d = workloads.desc(L, 3.8, beta, theta=th, k=k, n_stab=10)
-    sim, ch, ratios = _replay_case(d, 11)
+    sim, ch, ratios = _replay_case(d, 11, y_solver=y_solver)
     assert np.array_equal(sim.fields(0), ch.fields)
     assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
     assert np.abs(sim.green(0, spin=1) - ch.G[1]).max() < 1e-10
