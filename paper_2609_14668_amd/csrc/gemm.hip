@@ -16,6 +16,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
+constexpr int GEMM_KB = 16;   // chunk depth of the batched GEMM
 constexpr int GEMM_THREADS = 256;
 
 __host__ __device__ __forceinline__ int dimval(GemmDim g, int n) {
@@ -68,21 +69,25 @@ __device__ __forceinline__ void xcd_slot(int n_inst, int& inst, int& bx) {
 
 // Shared memory of one 64 x 64 output tile (op(A) and op(B) chunks, real
 // and imaginary planes).
-template <bool CX>
+template <bool CX, int KB = BK>
 struct GemmSmem {
-  double Ar[BK][BM + PAD], Br[BK][BN + PAD];
-  double Ai[CX ? BK : 1][BM + PAD], Bi[CX ? BK : 1][BN + PAD];
+  double Ar[KB][BM + PAD], Br[KB][BN + PAD];
+  double Ai[CX ? KB : 1][BM + PAD], Bi[CX ? KB : 1][BN + PAD];
 };
 
 // C = alpha op(A) op(B) + beta C on the tiles tile0, tile0 + tstep, ... of
 // one instance (M x NC output, depth K): the tile body shared by the batched
 // GEMM and the work-queue flush.
-template <typename S>
+template <typename S, int KB = BK>
 __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __restrict__ pb, S* pc, int ld,
                                            int aop, int bop, int M, int NC, int K, bool a_upper, double alpha,
-                                           double beta, int tile0, int tstep, GemmSmem<ST<S>::is_complex>& sm) {
+                                           double beta, int tile0, int tstep, GemmSmem<ST<S>::is_complex, KB>& sm) {
+  static_assert(KB == 16 || KB == 32, "chunk depth");
+  constexpr int P = KB / 4;          // staged values of op(A) and of op(B) per thread
+  constexpr int KROW = 256 / KB;     // rows (columns) per pass of a k-contiguous load
   constexpr bool CX = ST<S>::is_complex;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in a scalar register
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int tm = (M + BM - 1) / BM, tn = (NC + BN - 1) / BN;
   const int ntiles = tm * tn;
@@ -92,25 +97,25 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
   // in-range mask; masking and conjugation happen in store_chunk, so the
   // loads of the next chunk stay in flight while the current one is
   // multiplied (no branch, no select right behind the loads).
-  S va[4], vb[4];
+  S va[P], vb[P];
   unsigned mask_a = 0, mask_b = 0;
   auto load_chunk = [&](int m0, int n0, int k0) {
     mask_a = 0;
     mask_b = 0;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < P; ++p) {
       int i, kk;
       if (aop == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
-      else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
+      else { kk = tid % KB; i = tid / KB + KROW * p; }
       const int gi = m0 + i, gk = k0 + kk;
       if (gi < M && gk < K && !(a_upper && gi > gk)) mask_a |= 1u << p;
       const int gic = min(gi, M - 1), gkc = min(gk, K - 1);
       va[p] = gld(pa + (aop == 0 ? gic + (size_t)gkc * ld : gkc + (size_t)gic * ld));
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < P; ++p) {
       int j, kk;
-      if (bop == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
+      if (bop == 0) { kk = tid % KB; j = tid / KB + KROW * p; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
       const int gj = n0 + j, gk = k0 + kk;
       if (gj < NC && gk < K) mask_b |= 1u << p;
@@ -120,10 +125,10 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < P; ++p) {
       int i, kk;
       if (aop == 0) { i = tid & 63; kk = (tid >> 6) + 4 * p; }
-      else { kk = tid & 15; i = (tid >> 4) + 16 * p; }
+      else { kk = tid % KB; i = tid / KB + KROW * p; }
       double re, im;
       split<S>(va[p], re, im);
       if (aop == 2) im = -im;
@@ -132,9 +137,9 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
       if constexpr (CX) sm.Ai[kk][i] = in ? im : 0.0;
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < P; ++p) {
       int j, kk;
-      if (bop == 0) { kk = tid & 15; j = (tid >> 4) + 16 * p; }
+      if (bop == 0) { kk = tid % KB; j = tid / KB + KROW * p; }
       else { j = tid & 63; kk = (tid >> 6) + 4 * p; }
       double re, im;
       split<S>(vb[p], re, im);
@@ -182,37 +187,48 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
             if constexpr (CX) acc_p[ti][tj][r] = in ? cscale * (re + im) : 0.0;
           }
     }
-    // upper-triangular op(A): chunks with k < m0 contribute nothing
-    const int kbeg = a_upper ? (m0 / BK) * BK : 0;
-    if (kbeg < K) load_chunk(m0, n0, kbeg);
-    for (int k0 = kbeg; k0 < K; k0 += BK) {
-      store_chunk();
-      __syncthreads();
-      if (k0 + BK < K) load_chunk(m0, n0, k0 + BK);
-      const int ksn = min(BK, K - k0 + 3) / 4;
-#pragma unroll 1
-      for (int ks = 0; ks < ksn; ++ks) {
-        const int kr = ks * 4 + (lane >> 4);
-        double ar[2], br[2], ai[2], bi[2];
+    // 16 x 16 blocks wholly outside the output are not multiplied (edge tiles
+    // of sizes that are not multiples of 64 leave up to 3/4 of a tile empty)
+    const bool vi0 = m0 + wr < M, vi1 = m0 + wr + 16 < M;
+    const bool vj0 = n0 + wc < NC, vj1 = n0 + wc + 16 < NC;
+    auto kstep = [&](int kr) {
+      double ar[2], br[2], ai[2], bi[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          ar[t] = sm.Ar[kr][wr + t * 16 + (lane & 15)];
-          br[t] = sm.Br[kr][wc + t * 16 + (lane & 15)];
-          if constexpr (CX) {
-            ai[t] = sm.Ai[kr][wr + t * 16 + (lane & 15)];
-            bi[t] = sm.Bi[kr][wc + t * 16 + (lane & 15)];
-          }
+      for (int t = 0; t < 2; ++t) {
+        ar[t] = sm.Ar[kr][wr + t * 16 + (lane & 15)];
+        br[t] = sm.Br[kr][wc + t * 16 + (lane & 15)];
+        if constexpr (CX) {
+          ai[t] = sm.Ai[kr][wr + t * 16 + (lane & 15)];
+          bi[t] = sm.Bi[kr][wc + t * 16 + (lane & 15)];
         }
+      }
 #pragma unroll
-        for (int ti = 0; ti < 2; ++ti)
+      for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < 2; ++tj) {
+        for (int tj = 0; tj < 2; ++tj) {
+          if ((ti ? vi1 : vi0) && (tj ? vj1 : vj0)) {
             acc_r[ti][tj] = mfma(br[tj], ar[ti], acc_r[ti][tj]);
             if constexpr (CX) {
               acc_i[ti][tj] = mfma(bi[tj], ai[ti], acc_i[ti][tj]);
               acc_p[ti][tj] = mfma(br[tj] + bi[tj], ar[ti] + ai[ti], acc_p[ti][tj]);
             }
           }
+        }
+    };
+    // upper-triangular op(A): chunks with k < m0 contribute nothing
+    const int kbeg = a_upper ? (m0 / KB) * KB : 0;
+    if (kbeg < K) load_chunk(m0, n0, kbeg);
+    for (int k0 = kbeg; k0 < K; k0 += KB) {
+      store_chunk();
+      __syncthreads();
+      if (k0 + KB < K) load_chunk(m0, n0, k0 + KB);
+      if (k0 + KB <= K) {   // full chunk: unrolled
+#pragma unroll
+        for (int ks = 0; ks < KB / 4; ++ks) kstep(ks * 4 + (lane >> 4));
+      } else {
+        const int ksn = (K - k0 + 3) / 4;
+#pragma unroll 1
+        for (int ks = 0; ks < ksn; ++ks) kstep(ks * 4 + (lane >> 4));
       }
       __syncthreads();
     }
@@ -268,8 +284,9 @@ k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand
   const S* pa = reinterpret_cast<const S*>(mat_ptr(d, A.id)) + offval(A.ra, A.rb, Nn) + offval(A.ca, A.cb, Nn) * ld;
   const S* pb = reinterpret_cast<const S*>(mat_ptr(d, B.id)) + offval(B.ra, B.rb, Nn) + offval(B.ca, B.cb, Nn) * ld;
   S* pc = reinterpret_cast<S*>(mat_ptr(d, C.id)) + offval(C.ra, C.rb, Nn) + offval(C.ca, C.cb, Nn) * ld;
-  __shared__ GemmSmem<ST<S>::is_complex> sm;
-  gemm_tiles<S>(pa, pb, pc, ld, A.op, B.op, M, NC, K, (flags & GF_A_UPPER) != 0, alpha, beta, bx, gridDim.x, sm);
+  __shared__ GemmSmem<ST<S>::is_complex, GEMM_KB> sm;
+  gemm_tiles<S, GEMM_KB>(pa, pb, pc, ld, A.op, B.op, M, NC, K, (flags & GF_A_UPPER) != 0, alpha, beta, bx,
+                         gridDim.x, sm);
 }
 
 // Flush without LDS: G <- G - X Y with X column-major N x K (op N) and Y
