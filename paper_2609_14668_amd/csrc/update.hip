@@ -29,6 +29,10 @@ namespace {
 constexpr int WMAX = 64;
 constexpr int WIN_THREADS = 256;
 
+// Lane src's value of a real or complex scalar.
+__device__ __forceinline__ double shfl_s(double v, int src) { return __shfl(v, src); }
+__device__ __forceinline__ cplx shfl_s(cplx v, int src) { return cmake(__shfl(v.x, src), __shfl(v.y, src)); }
+
 // window coefficient layout (in units of S): [0, WMAX) c_k; then xw[k][a]; then yw[k][b]
 constexpr int WC_X = WMAX;
 constexpr int WC_Y = WMAX + WMAX * WMAX;
@@ -65,7 +69,6 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
   __shared__ S xcol[WMAX], yrow[WMAX];
   __shared__ int xs[WMAX];
   __shared__ int sh_q, sh_mw;
-  __shared__ S sh_c, sh_r;
 
   // ---- C = G[w,w] - X[w,:fill0] Y[:fill0,w]
   // every load below reads a clamped address and is masked afterwards, so
@@ -123,11 +126,17 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
     if (replay) rbit = d.replay_bits[rpos + lane] != 0;
     else usite = site_uniform(d.seed, (uint64_t)st->sweep, pass, l, w0 + lane);
   }
-  int p = 0;
+  // The phase of det_up is carried in registers of thread 0 for the window.
+  double ph_re = 0.0, ph_im = 0.0;
+  if (tid == 0) { ph_re = st->ph_re; ph_im = st->ph_im; }
+  int p = 0, k = 0;
   while (true) {
+    // wave 0: ratios of the undecided sites, the first accepted one, and the
+    // window parts of its x_k (column qs of C times c_k) and y_k (minus row
+    // qs), zero on the sites up to qs
     if (wave == 0) {
-      int q = lane;
-      bool cand = q < wn && q >= p;
+      const int q = lane;
+      const bool cand = q < wn && q >= p;
       bool acc_q = false;
       double R = 0.0;
       S r = ST<S>::one(), dl = ST<S>::zero();
@@ -138,60 +147,60 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
         acc_q = replay ? rbit : usite < R;
         if (!(R == R) || R == 0.0 || R > 1e300) atomicOr(&st->numeric_err, NUMERR_RATIO);
       }
-      unsigned long long mask = __ballot(cand && acc_q);
-      int qstar = mask ? (__ffsll((long long)mask) - 1) : wn;
-      if (cand && q <= qstar && d.replay_ratio) d.replay_ratio[rpos + q] = R;
+      const unsigned long long mask = __ballot(cand && acc_q);
+      const int qs = mask ? (__ffsll((long long)mask) - 1) : wn;
+      if (cand && q <= qs && d.replay_ratio) d.replay_ratio[rpos + q] = R;
       // training target of the proposal network: Barker acceptance Rt/(1+Rt)
       // of flipping the site again right after this decision (downward
       // pass), Rt = 1/R after an accepted flip and R after a rejected one
-      if (cand && q <= qstar && pass == 1 && d.targets)
+      if (cand && q <= qs && pass == 1 && d.targets)
         d.targets[(size_t)(l - 1) * N + w0 + q] =
-            (float)(q == qstar ? 1.0 / (1.0 + R) : (R < 1e300 ? R / (1.0 + R) : 1.0));
-      if (q == qstar && cand) {
-        sh_c = cdiv(dl, r);
-        sh_r = r;
+            (float)(q == qs ? 1.0 / (1.0 + R) : (R < 1e300 ? R / (1.0 + R) : 1.0));
+      if (lane == 0) sh_q = qs;
+      if (qs < wn) {
+        const S cfac = shfl_s(cdiv(dl, r), qs);
+        const S rr = shfl_s(r, qs);
+        const bool tail = q > qs && q < wn;
+        const S xv = tail ? C[q][qs] * cfac : ST<S>::zero();
+        const S yv = tail ? -C[qs][q] : ST<S>::zero();
+        xcol[q] = xv;
+        yrow[q] = yv;
+        wc[WC_X + k * WMAX + q] = xv;
+        wc[WC_Y + k * WMAX + q] = yv;
+        if (lane == 0) {
+          wc[k] = cfac;
+          d.acc_site[k] = qs;
+          d.acc_gsite[k] = w0 + qs;
+          // det(1 + B..B) of spin up changes by the factor r_up (eq. rRatioLocal)
+          const double ra = sqrt(absq(rr));
+          if (ra > 0.0) {
+            const double pr = real_part(rr) / ra, pi = imag_part(rr) / ra;
+            const double a = ph_re, b = ph_im;
+            ph_re = a * pr - b * pi;
+            ph_im = a * pi + b * pr;
+          }
+        }
+        if (q == qs) xs[qs] = -xs[qs];
       }
-      if (lane == 0) sh_q = qstar;
     }
     __syncthreads();
     const int qs = sh_q;
     if (qs >= wn) break;
-    const int k = sh_mw;
-    const S cfac = sh_c;
-    if (tid < WMAX) {
-      int a = tid;
-      S xv = (a > qs && a < wn) ? C[a][qs] * cfac : ST<S>::zero();
-      S yv = (a > qs && a < wn) ? -C[qs][a] : ST<S>::zero();
-      xcol[a] = xv;
-      yrow[a] = yv;
-      wc[WC_X + k * WMAX + a] = xv;
-      wc[WC_Y + k * WMAX + a] = yv;
-    }
-    if (tid == 0) {
-      wc[k] = cfac;
-      d.acc_site[k] = qs;
-      d.acc_gsite[k] = w0 + qs;
-      // det(1 + B..B) of spin up changes by the factor r_up (eq. rRatioLocal)
-      const S rr = sh_r;
-      const double ra = sqrt(absq(rr));
-      if (ra > 0.0) {
-        const double pr = real_part(rr) / ra, pi = imag_part(rr) / ra;
-        const double a = st->ph_re, b = st->ph_im;
-        st->ph_re = a * pr - b * pi;
-        st->ph_im = a * pi + b * pr;
+    // trailing-block rank-1 update C -= x y^T: lane b of every wave takes
+    // column b (a row of C is contiguous in LDS), the waves split the rows
+    {
+      const int b = qs + 1 + lane;
+      if (b < wn) {
+        const S yb = yrow[b];
+        for (int a = qs + 1 + wave; a < wn; a += WIN_THREADS / 64) C[a][b] = C[a][b] - xcol[a] * yb;
       }
     }
-    __syncthreads();
-    // trailing-block rank-1 update C -= x y^T
-    const int span = wn - qs - 1;
-    for (int e = tid; e < span * span; e += WIN_THREADS) {
-      int a = qs + 1 + e % span, b = qs + 1 + e / span;
-      C[a][b] = C[a][b] - xcol[a] * yrow[b];
-    }
-    if (tid == 0) { xs[qs] = -xs[qs]; sh_mw = k + 1; }
+    ++k;
     p = qs + 1;
     __syncthreads();
   }
+  if (tid == 0) { st->ph_re = ph_re; st->ph_im = ph_im; sh_mw = k; }
+  __syncthreads();
   // write back flipped fields and counters
   const int mw = sh_mw;
   if (tid < wn) d.fields[(size_t)(l - 1) * N + w0 + tid] = (int8_t)xs[tid];
