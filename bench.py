@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--groups", type=int, choices=(1, 2, 3, 4), default=None,
                     help="instance groups on separate streams (1: every launch covers all instances; "
                          "default: the library's choice for the batch size)")
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="sweeps of the plain leg (default --steps); lets a long learned leg run on its own")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -319,7 +321,10 @@ def main():
     sim.collect(0)
     # throughput without per-launch events (both instance groups overlap);
     # then one sweep with live HIP-event timing for the per-kernel rooflines
-    plain = timed_leg(sim, a.steps, "plain")
+    plain_steps = a.steps if a.plain_steps is None else a.plain_steps
+    plain = timed_leg(sim, plain_steps, "plain")
+    # per-sweep series of the timed leg (the profiled sweep below resets them)
+    main_series = [sim.series(i) for i in range(n)]
     dt = plain["dt"]
     tim = timed_leg(sim, 1, "profiled", events=True)["tim"] if not a.no_timing else plain["tim"]
     line = {
@@ -327,9 +332,9 @@ def main():
         "value": plain["value"],
         "unit": "HS field updates/s",
         "n_gpus": 1,
-        "steps": a.steps,
+        "steps": plain_steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * dt / max(a.steps, 1),
+        "ms_per_step": 1e3 * dt / max(plain_steps, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -382,8 +387,7 @@ def main():
         line["roofline"]["frac"] = line["roofline"]["achieved"] / 157.3
     if descs[0]["precision"] == 1:
         if not a.no_fp64_twin:
-            ser = [sim.series(i) for i in range(n)]
-            line["fp64_twin"] = fp64_twin(descs, a.warmup, a.steps, ser)
+            line["fp64_twin"] = fp64_twin(descs, a.warmup, plain_steps, main_series)
     if learned:
         f, cap = sim.sample_count()
         sim.net_init(1)
