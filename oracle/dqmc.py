@@ -1,19 +1,26 @@
-"""Plain dense FP64 DQMC for the honeycomb Hubbard model (HS in the spin-s^z
-channel), written from the paper's formalism.  Test infrastructure only.
+"""Plain dense FP64 DQMC for the honeycomb Hubbard model, HS in the spin-s^z
+channel or in the charge channel, written from the paper's formalism.  Test
+infrastructure only.
 
 What is computed, and where it is defined:
-  * lambda = arccosh(exp(dtau U / 2))                       (eq. coupling)
-  * B^sigma_l = exp(s_sigma lambda diag(x_l)) exp(-dtau K), s_up = +1,
-    s_dn = -1                                        (eqs. BIOpSz, ConfgWeight)
+  * spin channel (HS-s^z, eq. SzHS): lambda = gamma_s = arccosh(exp(dtau U/2))
+    (eq. coupling), B^sigma_l = exp(s_sigma lambda diag(x_l)) exp(-dtau K),
+    s_up = +1, s_dn = -1, p(x_l) = 2^{-N_s}      (eqs. BIOpSz, ConfgWeight)
+  * charge channel (HS-n, eq. DensityHS): gamma_c = i alpha with
+    alpha = arccos(exp(-dtau U/2)) (eq. coupling), the same
+    B_l = exp(i alpha diag(x_l)) exp(-dtau K) for both spins (eq. BIOpnT),
+    p(x_l) = (exp(dtau U N_s/2) / 2^{N_s}) exp(-i alpha sum_i x_{l,i})
   * G^sigma(l) = (1 + B_l..B_1 B_M..B_{l+1})^{-1}                (eq. GrFMat)
     recomputed with a UDV chain over chunks of n_stab slices using pivoted
     Householder QR (the periodic QR stabilisation of Sec. II B), with the
     usual split of D into factors >= 1 and <= 1 before the inversion.
   * wraps G -> B_l G B_l^{-1} (upward) and G -> B_l^{-1} G B_l (downward),
     with dense exp(-+dtau K) from an eigendecomposition of K   (Sec. III A)
-  * single-site Metropolis: Delta^sigma = exp(-2 s_sigma lambda x) - 1,
-    r_sigma = 1 + Delta^sigma (1 - G^sigma_ii), accept if u < r_up r_dn
-    (P(X) is uniform for this channel)        (eqs. DetailBalance, rRatioLocal)
+  * single-site Metropolis: Delta^sigma = v_sigma(-x)/v_sigma(x) - 1 with
+    v_sigma the diagonal of exp(H_I^sigma), r_sigma = 1 + Delta^sigma
+    (1 - G^sigma_ii), accept if u < R = [p(x')/p(x)] r_up r_dn, the prior
+    ratio being 1 (spin) or exp(2 i alpha x) (charge; R is real and positive
+    up to rounding)                            (eqs. DetailBalance, rRatioLocal)
   * Sherman-Morrison G' = G - x y^T with x = G[:, i] Delta / r and
     y^T = (1 - G)[i, :]                                    (eq. GupdateLocal)
   * both spins are propagated independently: no particle-hole shortcut.
@@ -40,6 +47,14 @@ def hs_lambda(U, dtau):
     return float(np.arccosh(np.exp(dtau * U / 2.0)))
 
 
+def hs_alpha(U, dtau):
+    """alpha = arccos(exp(-dtau U / 2)), gamma_c = i alpha   (eq. coupling)."""
+    return float(np.arccos(np.exp(-dtau * U / 2.0)))
+
+
+CHANNELS = ("spin", "charge")
+
+
 def hermitian_expm(K, c):
     """exp(c K) for Hermitian K via its eigendecomposition."""
     w, V = np.linalg.eigh(K)
@@ -50,7 +65,7 @@ class Model:
     """Dense single-particle matrices of one (L, U, beta, dtau, twist) point."""
 
     def __init__(self, L, U, beta, dtau, t=1.0, theta1=0.0, theta2=0.0,
-                 n_stab=10, gauge="I"):
+                 n_stab=10, gauge="I", channel="spin"):
         M = beta / dtau
         if abs(M - round(M)) > 1e-9:
             raise ValueError("beta/dtau must be an integer")
@@ -59,9 +74,13 @@ class Model:
         self.U, self.beta, self.dtau = float(U), float(beta), float(dtau)
         self.M = int(round(M))
         self.n_stab = int(n_stab)
+        if channel not in CHANNELS:
+            raise ValueError("channel must be 'spin' or 'charge'")
+        self.channel = channel
         self.lam = hs_lambda(U, dtau)
+        self.alpha = hs_alpha(U, dtau)
         self.K = self.lat.hopping_matrix(gauge)
-        self.complex = np.iscomplexobj(self.K)
+        self.complex = np.iscomplexobj(self.K) or channel == "charge"
         dt = complex if self.complex else float
         self.Ep = hermitian_expm(self.K, -self.dtau).astype(dt)       # exp(-dtau K)
         self.Em = hermitian_expm(self.K, +self.dtau).astype(dt)       # exp(+dtau K)
@@ -71,9 +90,28 @@ class Model:
 
     # ---- propagators ----------------------------------------------------------
     def vdiag(self, spin, x):
-        """Diagonal of exp(H_I^sigma(x)) = exp(s_sigma lambda x)."""
+        """Diagonal of exp(H_I^sigma(x)): exp(s_sigma lambda x) (spin channel)
+        or exp(i alpha x) for both spins (charge channel)."""
+        x = np.asarray(x, dtype=float)
+        if self.channel == "charge":
+            return np.exp(1j * self.alpha * x)
         s = 1.0 if spin == 0 else -1.0
-        return np.exp(s * self.lam * np.asarray(x, dtype=float))
+        return np.exp(s * self.lam * x)
+
+    def prior_ratio(self, x):
+        """p(x')/p(x) of flipping one field x -> -x: 1 (spin channel) or
+        exp(-gamma_c (x' - x)) = exp(2 i alpha x) (charge channel)."""
+        if self.channel == "charge":
+            return np.exp(2j * self.alpha * float(x))
+        return 1.0
+
+    def log_prior(self, fields):
+        """log P(X) of a whole configuration (eqs. BIOpSz, BIOpnT)."""
+        X = np.asarray(fields, dtype=float)
+        nf = X.size
+        if self.channel == "charge":
+            return nf * (self.dtau * self.U / 2.0 - np.log(2.0)) - 1j * self.alpha * X.sum()
+        return -nf * np.log(2.0)
 
     def B(self, spin, x):
         return self.vdiag(spin, x)[:, None] * self.Ep
@@ -215,15 +253,22 @@ class Chain:
             v = self.m.vdiag(s, x)
             self.G[s] = self.m.Em @ ((self.G[s] / v[:, None]) * v[None, :]) @ self.m.Ep
 
+    def site_ratio(self, l, i):
+        """Metropolis ratio of flipping x_{l,i} on the current G (eqs.
+        DetailBalance, DRatio, rRatioLocal): (R, Delta^sigma, r_sigma)."""
+        x = float(self.fields[l - 1, i])
+        dl = tuple(complex(self.m.vdiag(s, -x) / self.m.vdiag(s, x)) - 1.0 for s in (0, 1))
+        if not self.m.complex:
+            dl = tuple(d.real for d in dl)
+        r = [1.0 + dl[s] * (1.0 - self.G[s][i, i]) for s in (0, 1)]
+        R = (self.m.prior_ratio(x) * r[0] * r[1]).real
+        return R, dl, r
+
     def update_slice(self, l, pas, decide):
         """Sequential single-site Metropolis on slice l (eqs. rRatioLocal, GupdateLocal)."""
-        lam = self.m.lam
         N = self.m.N
         for i in range(N):
-            x = float(self.fields[l - 1, i])
-            dl = (np.exp(-2 * lam * x) - 1.0, np.exp(2 * lam * x) - 1.0)
-            r = [1.0 + dl[s] * (1.0 - self.G[s][i, i]) for s in (0, 1)]
-            R = (r[0] * r[1]).real
+            R, dl, r = self.site_ratio(l, i)
             self.ratios.append(R)
             self.proposals += 1
             acc = decide(self.sweep_index, pas, l, i, R)

@@ -5,9 +5,12 @@
   eq. h0kMat at the shifted grid of eq. kpoints and the Fourier matrix
   U_{k,r} = exp(-i k.r)/L of eq. NewBlMat; energy per site
   e = -(1/N_c) sum_k |f(k)| tanh(beta |f(k)| / 2); D = 1/4.
-* Brute force: Z = sum_X W(X), W = 2^{-N M} det(1 + B^up_M..B^up_1)
-  det(1 + B^dn_M..B^dn_1) over every HS configuration (eq. ConfgWeight), with
-  estimators taken on G(l = M).
+* Brute force: Z = sum_X W(X), W = P(X) det(1 + B^up_M..B^up_1)
+  det(1 + B^dn_M..B^dn_1) over every HS configuration (eq. ConfgWeight), in
+  either HS channel (P(X) = 2^{-N M} for HS-s^z; for HS-n the prefactor and
+  the phase exp(-gamma_c sum x) of eq. BIOpnT), with estimators taken on
+  G(l = M).  Both channels represent the same Trotterised partition function,
+  so both must reproduce the exact diagonalisation below.
 * Exact diagonalisation of the Trotterised partition function
   Tr[(exp(-dtau H_U) exp(-dtau H_0))^M] in the 4^N-dimensional Fock space
   for M in {1, 2}, H_U = U sum_i (n_up n_dn - (n_up + n_dn)/2)
@@ -107,15 +110,14 @@ def config_estimators(model, X):
     B = len(X)
     dets, Gs = [], []
     for spin in (0, 1):
-        sgn = 1.0 if spin == 0 else -1.0
         P = np.broadcast_to(np.eye(N, dtype=complex), (B, N, N)).copy()
         for l in range(M):
-            v = np.exp(sgn * model.lam * X[:, l, :])
+            v = model.vdiag(spin, X[:, l, :])
             P = v[:, :, None] * (model.Ep[None] @ P)
         A = np.eye(N)[None] + P
         dets.append(np.linalg.det(A))
         Gs.append(np.linalg.inv(A))
-    W = dets[0] * dets[1] * 2.0 ** (-M * N)
+    W = dets[0] * dets[1] * np.exp(np.array([model.log_prior(x) for x in X]))
     nu = 1 - np.einsum("bii->bi", Gs[0])
     nd = 1 - np.einsum("bii->bi", Gs[1])
     D = np.mean(nu * nd, axis=1)
@@ -283,5 +285,5 @@ def exact_trotter(model):
             "N2": (tr(Ntot * Ntot) / Z).real, "Ntot": (tr(Ntot) / Z).real, "rho": rho}
 
 
-def tiny_model(U=3.8, dtau=0.25, M=2, theta1=0.0, theta2=0.0, L=2):
-    return Model(L, U, M * dtau, dtau, theta1=theta1, theta2=theta2, n_stab=max(1, M))
+def tiny_model(U=3.8, dtau=0.25, M=2, theta1=0.0, theta2=0.0, L=2, channel="spin"):
+    return Model(L, U, M * dtau, dtau, theta1=theta1, theta2=theta2, n_stab=max(1, M), channel=channel)

@@ -28,24 +28,27 @@ from oracle import exact
 from oracle.dqmc import Model, g_down_from_up, observables
 
 
-def _cases():
+def _cases(channel="spin"):
     out = []
     for L, M, th, n_cfg, seed in ((2, 2, (0.0, 0.0), 96, 1), (2, 2, (0.7, 1.9), 96, 2),
                                   (3, 2, (0.0, 0.0), 24, 3), (3, 2, (1.1, 0.4), 24, 4),
                                   (4, 2, (0.3 * np.pi, 0.7 * np.pi), 8, 5)):
-        m = Model(L, 3.8, M * 0.25, 0.25, theta1=th[0], theta2=th[1], n_stab=M)
+        m = Model(L, 3.8, M * 0.25, 0.25, theta1=th[0], theta2=th[1], n_stab=M, channel=channel)
         X = np.random.default_rng(seed).choice([-1.0, 1.0], size=(n_cfg, M, m.N))
         out.append((m, X))
     return out
 
 
 CASES = _cases()
+CHARGE_CASES = _cases("charge")
 
 
-def _violations(obs_fn, tol=1e-12):
-    """Largest deviation of obs_fn from the per-configuration reference."""
+def _violations(obs_fn, tol=1e-12, cases=None):
+    """Largest deviation of obs_fn from the per-configuration reference.  In
+    the charge channel the per-configuration estimators are complex (only
+    their averages are real): observables() returns their real parts."""
     worst = 0.0
-    for m, X in CASES:
+    for m, X in (CASES if cases is None else cases):
         ref = exact.config_estimators(m, X)
         for b in range(len(X)):
             Gu, Gd = ref["Gup"][b], ref["Gdn"][b]
@@ -59,7 +62,7 @@ def _violations(obs_fn, tol=1e-12):
                     "e": ref["H0"][b].real / m.N + m.U * ref["D"][b].real,
                     "Szz_G": ref["SzzG"][b].real, "Szz_dk": ref["Szzdk"][b].real,
                     "m2": ref["SzzG"][b].real / (2 * m.Nc),
-                    "Rm2": 1.0 - ref["Szzdk"][b].real / ref["SzzG"][b].real}
+                    "Rm2": (1.0 - ref["Szzdk"][b] / ref["SzzG"][b]).real}
             for k, v in want.items():
                 worst = max(worst, abs(o[k] - v) / max(1.0, abs(v)))
     return worst
@@ -76,6 +79,14 @@ def test_reference_is_real_and_uses_both_spins_consistently():
 
 def test_observables_match_per_configuration_reference():
     assert _violations(observables) < 1e-12
+
+
+def test_observables_match_per_configuration_reference_charge_channel():
+    # HS-n: G_dn = G_up for every configuration (same B for both spins)
+    for m, X in CHARGE_CASES:
+        ref = exact.config_estimators(m, X[:4])
+        assert np.abs(ref["Gdn"] - ref["Gup"]).max() == 0.0
+    assert _violations(observables, cases=CHARGE_CASES) < 1e-12
 
 
 def _mutant(old, new):

@@ -115,9 +115,15 @@ def test_u0_green_energy_double_occupancy(L, beta, th):
 
 
 # ---- brute force over all HS configurations vs Fock-space ED ----------------------------
+@pytest.mark.parametrize("channel", ["spin", "charge"])
 @pytest.mark.parametrize("th", [(0.0, 0.0), (0.7, 1.9)])
-def test_bruteforce_equals_exact_diagonalisation(th):
-    m = exact.tiny_model(U=3.8, dtau=0.25, M=2, theta1=th[0], theta2=th[1])
+def test_bruteforce_equals_exact_diagonalisation(th, channel):
+    """Both HS channels (eqs. SzHS and DensityHS) decouple the same
+    Trotterised interaction, so the sum of either channel's weights over
+    every configuration reproduces the Fock-space trace, and every weight is
+    real and positive (for HS-n by the partial particle-hole symmetry of
+    Sec. II B, with the phase of P(X) included)."""
+    m = exact.tiny_model(U=3.8, dtau=0.25, M=2, theta1=th[0], theta2=th[1], channel=channel)
     bf = exact.brute_force(m)
     ed = exact.exact_trotter(m)
     assert bf["wmin"] > 0 and bf["w_max_rel_imag"] < 1e-12
@@ -133,6 +139,23 @@ def test_bruteforce_equals_exact_diagonalisation(th):
                 blk = ed["rho"][spin][a * Nc:(a + 1) * Nc, b * Nc:(b + 1) * Nc]
                 nk_ed[:, a, b] += 0.5 * np.einsum("kr,rs,ks->k", Uc.conj(), blk, Uc)
     assert np.abs(bf["nk"] - nk_ed).max() < 1e-12
+
+
+@pytest.mark.parametrize("th", [(0.0, 0.0), (0.7, 1.9)])
+def test_charge_channel_configurations_are_particle_hole_symmetric(th):
+    """HS-n couples both spins identically (G_dn = G_up in the original
+    basis), and at half filling every configuration has Re G_ii = 1/2 and a
+    real positive weight P(X) det^2; a planted sign error in the prior phase
+    breaks the positivity."""
+    m = exact.tiny_model(U=3.8, dtau=0.25, M=2, theta1=th[0], theta2=th[1], channel="charge")
+    X = np.random.default_rng(5).choice([-1, 1], size=(64, m.M, m.N))
+    c = exact.config_estimators(m, X)
+    assert np.abs(c["Gup"] - c["Gdn"]).max() == 0.0
+    assert np.abs(np.einsum("bii->bi", c["Gup"]).real - 0.5).max() < 1e-13
+    assert np.max(np.abs(c["W"].imag) / np.abs(c["W"])) < 1e-12 and c["W"].real.min() > 0
+    # planted mistake: the prior phase with the wrong sign
+    bad = c["W"] * np.exp(2j * m.alpha * X.reshape(len(X), -1).sum(axis=1))
+    assert np.max(np.abs(bad.imag) / np.abs(bad)) > 1e-3
 
 
 def test_single_slice_exact_diagonalisation():
@@ -183,6 +206,39 @@ def test_ratio_and_update_against_determinants(th):
                     assert np.abs(Gs - ch.G[s]).max() < 1e-10
             del ch_ratio_index
     assert w0 > 0
+
+
+@pytest.mark.parametrize("th", [(0.0, 0.0), (1.3, 0.2)])
+def test_charge_ratio_and_update_against_determinants(th):
+    """HS-n chain: every ratio R = exp(2 i alpha x) r_up r_dn equals the
+    brute-force weight ratio P(X') det'^2 / P(X) det^2, and the
+    Sherman-Morrison G equals the direct recomputation after each flip."""
+    m = Model(2, 3.8, 1.0, 0.25, theta1=th[0], theta2=th[1], n_stab=2, channel="charge")
+    rng = np.random.default_rng(9)
+    ch = Chain(m, rng.choice([-1, 1], size=(m.M, m.N)).astype(np.int8))
+
+    def weight(f):
+        return np.exp(m.log_prior(f)) * np.prod(m.weight_dets(f))
+
+    src = BitSource(np.tile([1, 0], m.M * m.N))
+    for l in range(1, m.M + 1):
+        ch.wrap_up(l)
+        for i in range(m.N):
+            trial = ch.fields.copy()
+            trial[l - 1, i] = -trial[l - 1, i]
+            ratio = weight(trial) / weight(ch.fields)
+            R, dl, r = ch.site_ratio(l, i)
+            assert abs(ratio.imag) < 1e-10 * abs(ratio) and abs(R - ratio.real) < 1e-10 * max(1.0, abs(R))
+            if src(0, 0, l, i, R):
+                for s in (0, 1):
+                    G = ch.G[s]
+                    xv = G[:, i] * (dl[s] / r[s])
+                    yv = -G[i, :].copy()
+                    yv[i] += 1
+                    ch.G[s] = G - np.outer(xv, yv)
+                ch.fields[l - 1, i] *= -1
+                for s in (0, 1):
+                    assert np.abs(m.green_direct(ch.fields, l, s) - ch.G[s]).max() < 1e-10
 
 
 def test_weight_ratio_factorises_through_spin_up_only():
@@ -265,8 +321,9 @@ def test_replay_all_reject_keeps_fields_and_all_accept_flips_all():
 
 
 @pytest.mark.slow
-def test_markov_chain_reproduces_exact_diagonalisation():
-    m = exact.tiny_model(U=3.8, dtau=0.25, M=2)
+@pytest.mark.parametrize("channel", ["spin", "charge"])
+def test_markov_chain_reproduces_exact_diagonalisation(channel):
+    m = exact.tiny_model(U=3.8, dtau=0.25, M=2, channel=channel)
     ed = exact.exact_trotter(m)
     rng = np.random.default_rng(17)
     ch = Chain(m, rng.choice([-1, 1], size=(m.M, m.N)))
