@@ -4,7 +4,8 @@
  * Finite-temperature determinant QMC for the half-filled honeycomb Hubbard
  * model, H = -t sum_<ij>s (c^+_is c_js + h.c.) + U sum_i (n_iu n_id - (n_iu + n_id)/2)
  * (Sec. II A, eq. HubbModel), with the Hubbard-Stratonovich transformation in
- * the spin-s^z channel, cosh(lambda) = exp(dtau U / 2) (eqs. SzHS, coupling).
+ * the spin-s^z channel, cosh(lambda) = exp(dtau U / 2) (eqs. SzHS, coupling),
+ * or per instance in the charge channel (eq. DensityHS; dqmc_channel).
  * One call of dqmc_sweep runs the paper's Monte Carlo sweep (Sec. III): an
  * upward pass l = 1..M (wrap G, then update slice l) and a downward pass
  * l = M..1 (update slice l, then wrap), with
@@ -78,6 +79,17 @@ typedef enum {
  * tolerance (dqmc_set_drift_tol). */
 typedef enum { DQMC_FP64 = 0, DQMC_MIXED = 1, DQMC_MIXED_FLUSH = 2, DQMC_MIXED_WRAP = 3 } dqmc_precision;
 
+/* Hubbard-Stratonovich channel of an instance (Sec. II B).  DQMC_HS_SPIN
+ * (eq. SzHS): B^sigma = exp(+-lambda diag(x)) exp(-dtau K), lambda =
+ * arccosh(exp(dtau U/2)), uniform P(X); real arithmetic without a twist.
+ * DQMC_HS_CHARGE (eq. DensityHS, eq. BIOpnT): B = exp(i alpha diag(x))
+ * exp(-dtau K) for both spins, alpha = arccos(exp(-dtau U/2)) (gamma_c =
+ * i alpha, eq. coupling), P(X) carrying exp(-gamma_c sum x); the flip ratio
+ * is R = exp(2 i alpha x) r_up^2, real and positive by the partial
+ * particle-hole symmetry, and G_dn = G_up.  The charge channel always runs
+ * in complex arithmetic; learned proposals support the spin channel only. */
+typedef enum { DQMC_HS_SPIN = 0, DQMC_HS_CHARGE = 1 } dqmc_channel;
+
 /* One Markov chain.  All instances of a handle share n_stab, and every
  * beta/dtau must be a multiple of n_stab.  L in [2, 45] with prime factors in
  * {2, 3, 5, 7, 11, 13}. */
@@ -92,6 +104,7 @@ typedef struct {
   int32_t precision;    /* dqmc_precision, the same for all instances of a handle */
   int32_t sym_measure;  /* 1: estimators on exp(-dtau K/2) G exp(+dtau K/2) */
   uint64_t seed;        /* Philox key */
+  int32_t channel;      /* dqmc_channel: Hubbard-Stratonovich channel */
 } dqmc_instance_desc;
 
 /* Equal-time estimators (Sec. II C, Sec. IV C), means over all measurements
@@ -176,7 +189,8 @@ dqmc_status dqmc_replay(dqmc_handle h, const uint8_t* dev_bits, int64_t bits_per
  * G_ij = <c_i c_j^dagger> = (1 + B_l..B_1 B_M..B_{l+1})^{-1} at the current
  * slice l of the instance's sweep (l = 0 between sweeps), spin 0 (up) or 1
  * (down: P (1 - G_up^dagger) P with P = diag(+1 on A, -1 on B), the
- * particle-hole partner of Sec. II B in the original basis).  host_out:
+ * particle-hole partner of Sec. II B in the original basis; G_up itself in the
+ * charge channel).  host_out:
  * N x N row-major, real doubles or interleaved (re, im) for twisted
  * handles; caller-allocated.  Synchronises the handle's stream. */
 dqmc_status dqmc_get_green(dqmc_handle h, int32_t inst, int32_t spin, double* host_out);

@@ -32,7 +32,7 @@ class InstanceDesc(ctypes.Structure):
                 ("theta1", ctypes.c_double), ("theta2", ctypes.c_double),
                 ("n_delay", ctypes.c_int32), ("n_stab", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("sym_measure", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("channel", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -134,7 +134,7 @@ def _descs(descs):
     arr = (InstanceDesc * len(descs))()
     for i, d in enumerate(descs):
         for k, _ in InstanceDesc._fields_:
-            setattr(arr[i], k, d[k])
+            setattr(arr[i], k, d.get(k, 0) if k == "channel" else d[k])
     return arr
 
 

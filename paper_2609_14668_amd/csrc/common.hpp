@@ -199,7 +199,8 @@ struct InstDev {
   int32_t sym_measure;
   int32_t fft_fixed;        // 1: a compile-time FFT plan exists for L
   int32_t mixed;            // 1: wraps and flushes in single precision
-  double lam;               // HS coupling lambda
+  double lam;               // HS coupling: lambda (spin channel) or alpha (charge channel)
+  int channel;              // 0: HS-s^z, 1: HS-n
   double drift_tol;         // recomputation drift above this sets NUMERR_DRIFT
   double U, dtau, t;
   double theta1, theta2;

@@ -96,13 +96,14 @@ dqmc_status validate(const dqmc_instance_desc* d, int n, std::string& err) {
     if (x.n_delay < 1 || x.n_delay > MAX_DELAY) { err = "n_delay must be in [1, 192]"; return DQMC_EINVAL; }
     if (x.precision < DQMC_FP64 || x.precision > DQMC_MIXED_WRAP) { err = "unknown precision"; return DQMC_EINVAL; }
     if (x.precision != d[0].precision) { err = "all instances must share the precision"; return DQMC_EINVAL; }
+    if (x.channel != DQMC_HS_SPIN && x.channel != DQMC_HS_CHARGE) { err = "unknown HS channel"; return DQMC_EINVAL; }
   }
   return DQMC_OK;
 }
 
 Plan make_plan(const dqmc_instance_desc* d, int n) {
   Plan p;
-  for (int i = 0; i < n; ++i) p.cplx = p.cplx || is_twisted(d[i]);
+  for (int i = 0; i < n; ++i) p.cplx = p.cplx || is_twisted(d[i]) || d[i].channel == DQMC_HS_CHARGE;
   const size_t ss = p.cplx ? 16 : 8;
   size_t o = 0;
   p.insts_off = o;
@@ -796,7 +797,9 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.sym_measure = x.sym_measure;
     dv.fft_fixed = fft_has_fixed(x.L) ? 1 : 0;
     dv.mixed = x.precision != DQMC_FP64 ? 1 : 0;
-    dv.lam = std::acosh(std::exp(x.dtau * x.U / 2.0));
+    dv.channel = x.channel;
+    dv.lam = x.channel == DQMC_HS_CHARGE ? std::acos(std::exp(-x.dtau * x.U / 2.0))
+                                         : std::acosh(std::exp(x.dtau * x.U / 2.0));
     dv.U = x.U; dv.dtau = x.dtau; dv.t = x.t;
     dv.theta1 = x.theta1; dv.theta2 = x.theta2;
     dv.seed = x.seed;
@@ -1235,7 +1238,7 @@ dqmc_status dqmc_get_green(dqmc_handle h, int32_t inst, int32_t spin, double* ho
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) {
-      if (spin == 0) {
+      if (spin == 0 || d.channel == DQMC_HS_CHARGE) {   // charge channel: G_dn = G_up
         for (int c = 0; c < w; ++c) host_out[((size_t)i * N + j) * w + c] = g[((size_t)j * N + i) * w + c];
       } else {
         // P (1 - G^dagger) P: element (i, j) = s_i s_j (delta_ij - conj(G_ji))
@@ -1489,8 +1492,11 @@ dqmc_status dqmc_set_drift_tol(dqmc_handle h, double tol) {
 dqmc_status dqmc_set_proposals(dqmc_handle h, int32_t per_slice, int32_t m) {
   if (!h || per_slice < 0 || per_slice > 8) return DQMC_EINVAL;
   if (per_slice > 0 && (m < 1 || m > LEARN_MMAX)) return DQMC_EINVAL;
-  for (auto& d : h->hd)
+  for (auto& d : h->hd) {
     if (per_slice > 0 && m >= d.N) return fail(h, DQMC_EINVAL, "m must be smaller than the number of sites");
+    if (per_slice > 0 && d.channel == DQMC_HS_CHARGE)
+      return fail(h, DQMC_EUNSUPPORTED, "learned proposals support the spin channel only");
+  }
   h->learn_P = per_slice;
   h->learn_m = per_slice > 0 ? m : 0;
   return DQMC_OK;

@@ -23,12 +23,13 @@ constexpr int FFT_THREADS = 256;
 
 struct Resolved {
   int active, slice, pre, post, tab;
+  int cj;   // 1: the HS diagonal enters conjugated (B^dagger of the downward chain)
 };
 
 template <typename C> using real_of_t = decltype(C::x);
 
 __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) {
-  Resolved r{0, 0, 0, 0, TAB_P};
+  Resolved r{0, 0, 0, 0, TAB_P, 0};
   const InstState& st = *d.st;
   if (st.idle) return r;
   int M = d.M;
@@ -54,9 +55,10 @@ __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) 
       if (up) {  // R_c = B_{c ns} .. B_{(c-1) ns + 1} R_{c-1}: lowest slice first
         r.slice = (c - 1) * d.n_stab + 1 + a.j;
         r.pre = 0; r.tab = TAB_P; r.post = +1;
-      } else {   // L_c^dag = B^dag_{c ns+1} .. B^dag_{(c+1) ns} L_{c+1}^dag: highest first
+      } else {   // L_c^dag = B^dag_{c ns+1} .. B^dag_{(c+1) ns} L_{c+1}^dag: highest first,
+                 // B^dag = E+ conj(e^{V}) (E+ is Hermitian)
         r.slice = c * d.n_stab + d.n_stab - a.j;
-        r.pre = +1; r.tab = TAB_P; r.post = 0;
+        r.pre = +1; r.tab = TAB_P; r.post = 0; r.cj = 1;
       }
       return r;
     }
@@ -88,15 +90,6 @@ __device__ __forceinline__ Resolved chain_step(const InstDev& d, const FftArgs& 
   return resolve(d, aj);
 }
 
-// v <- e^{sign lambda x_r} v on element r of every vector held in LDS.
-template <typename C>
-__device__ __forceinline__ void lds_diag(C* buf, int tot, int N, int sign, const int8_t* xs,
-                                         real_of_t<C> ep, real_of_t<C> em, int nthreads) {
-  for (int e = threadIdx.x; e < tot; e += nthreads) {
-    const int r = e % N;
-    buf[e] = buf[e] * ((sign * xs[r]) > 0 ? ep : em);
-  }
-}
 
 // Complex compute type C is cplx (complex128) or cplxf (complex64); RT is its
 // real type.  Tables and roots are held in double and rounded once on load.
@@ -105,6 +98,47 @@ template <typename C> __device__ __forceinline__ C mkc(double a, double b) {
   return C{(real_of<C>)a, (real_of<C>)b};
 }
 template <typename C> __device__ __forceinline__ C to_c(cplx a) { return mkc<C>(a.x, a.y); }
+
+// The factors of the HS diagonal exp(H_I(x)) as multipliers in the
+// transform's domain: e^{+-lambda} for the spin channel, e^{+-i alpha} for
+// the charge channel (eqs. BIOpSz, BIOpnT).  Real G (two real vectors packed
+// per complex transform) only occurs in the spin channel and keeps real
+// factors; the row side of complex G is transformed conjugated, so a complex
+// factor is applied conjugated there.
+// mul(v, plus, cj): v e^{+-H_I} (conjugated when cj, for B^dagger).
+template <typename C, bool CX>
+struct HsDiag {
+  real_of_t<C> p, m;
+  __device__ HsDiag(const InstDev& d, bool) : p((real_of_t<C>)exp(d.lam)), m((real_of_t<C>)exp(-d.lam)) {}
+  __device__ C mul(C v, bool plus, int = 0) const { return v * (plus ? p : m); }
+};
+template <typename C>
+struct HsDiag<C, true> {
+  C p, m;
+  bool charge;
+  __device__ HsDiag(const InstDev& d, bool rows) : charge(d.channel != 0) {
+    if (charge) {
+      const double c = cos(d.lam), s = rows ? -sin(d.lam) : sin(d.lam);
+      p = mkc<C>(c, s);
+      m = mkc<C>(c, -s);
+    } else {
+      p = mkc<C>(exp(d.lam), 0.0);
+      m = mkc<C>(exp(-d.lam), 0.0);
+    }
+  }
+  // conj(e^{+i alpha}) = e^{-i alpha}; the spin factors are real
+  __device__ C mul(C v, bool plus, int cj = 0) const { return v * ((plus != (charge && cj)) ? p : m); }
+};
+
+// v <- e^{sign H_I(x_r)} v on element r of every vector held in LDS.
+template <typename C, typename HD>
+__device__ __forceinline__ void lds_diag(C* buf, int tot, int N, int sign, int cj, const int8_t* xs,
+                                         const HD& hd, int nthreads) {
+  for (int e = threadIdx.x; e < tot; e += nthreads) {
+    const int r = e % N;
+    buf[e] = hd.mul(buf[e], (sign * xs[r]) > 0, cj);
+  }
+}
 
 template <typename C>
 __device__ __forceinline__ C root_pow(const C* roots, int L, int m, int sign) {
@@ -274,8 +308,8 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
   if (threadIdx.x < 16) fac[threadIdx.x] = d.factors[threadIdx.x];
   S* Mx = matp<S>(d, a.mat);
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
-  const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
   const bool rows = a.side != 0;
+  const HsDiag<C, ST<S>::is_complex> hd(d, rows);
   const bool chain = a.op == FOP_STAB_CHAIN;
   // load (+ pre diagonal), LU elements per thread at a time: every load of a
   // group reads a clamped address and is issued before the first is used
@@ -309,7 +343,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
         C val;
         if constexpr (ST<S>::is_complex) val = mkc<C>(raw[u][0].x, rows ? -raw[u][0].y : raw[u][0].y);
         else val = mkc<C>(raw[u][0], raw[u][1]);
-        if (rs.pre) val = val * ((rs.pre * xr[u]) > 0 ? ep : em);
+        if (rs.pre) val = hd.mul(val, (rs.pre * xr[u]) > 0, rs.cj);
         buf[vv * N + r] = val;
       }
     }
@@ -323,7 +357,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
       const Resolved rj = chain_step(d, a, rep);
       tabi = rj.tab;
       if (rj.pre) {
-        lds_diag(cur, tot, N, rj.pre, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        lds_diag(cur, tot, N, rj.pre, rj.cj, d.fields + (size_t)(rj.slice - 1) * N, hd, FFT_THREADS);
         __syncthreads();
       }
     }
@@ -348,7 +382,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     if (chain) {   // post diagonal of step rep in LDS
       const Resolved rj = chain_step(d, a, rep);
       if (rj.post) {
-        lds_diag(cur, tot, N, rj.post, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        lds_diag(cur, tot, N, rj.post, rj.cj, d.fields + (size_t)(rj.slice - 1) * N, hd, FFT_THREADS);
         __syncthreads();
       }
     }
@@ -361,7 +395,7 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
     else { vv = e % nvl; r = e / nvl; }
     int q = v0 + vv;
     C val = cur[vv * N + r];
-    if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
+    if (rs.post) val = hd.mul(val, (rs.post * xs[r]) > 0, rs.cj);
     if (chain) {
       if constexpr (ST<S>::is_complex) val = val * (RT)dsc[q];
       else val = C{val.x * (RT)dsc[2 * q], val.y * (RT)dsc[2 * q + 1]};
@@ -490,8 +524,8 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
   if (tid < L) roots[tid] = to_c<C>(d.roots[tid]);
   S* Mx = matp<S>(d, a.mat);
   const int8_t* xs = rs.slice > 0 ? d.fields + (size_t)(rs.slice - 1) * N : nullptr;
-  const RT ep = (RT)exp(d.lam), em = (RT)exp(-d.lam);
   const bool rows = a.side != 0;
+  const HsDiag<C, ST<S>::is_complex> hd(d, rows);
   const bool chain = a.op == FOP_STAB_CHAIN;
   // load (+ pre diagonal): clamped loads issued in groups, then masked
   const int tot = nvl * N;
@@ -524,7 +558,7 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
         C val;
         if constexpr (ST<S>::is_complex) val = mkc<C>(raw[u][0].x, rows ? -raw[u][0].y : raw[u][0].y);
         else val = mkc<C>(raw[u][0], raw[u][1]);
-        if (rs.pre) val = val * ((rs.pre * xr[u]) > 0 ? ep : em);
+        if (rs.pre) val = hd.mul(val, (rs.pre * xr[u]) > 0, rs.cj);
         buf[vv * N + r] = val;
       }
     }
@@ -540,7 +574,7 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
       const Resolved rj = chain_step(d, a, rep);
       tabi = rj.tab;
       if (rj.pre) {
-        lds_diag(buf, tot, N, rj.pre, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        lds_diag(buf, tot, N, rj.pre, rj.cj, d.fields + (size_t)(rj.slice - 1) * N, hd, FFT_THREADS);
         __syncthreads();
       }
     }
@@ -579,7 +613,7 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
     if (chain) {   // post diagonal of step rep in LDS
       const Resolved rj = chain_step(d, a, rep);
       if (rj.post) {
-        lds_diag(buf, tot, N, rj.post, d.fields + (size_t)(rj.slice - 1) * N, ep, em, FFT_THREADS);
+        lds_diag(buf, tot, N, rj.post, rj.cj, d.fields + (size_t)(rj.slice - 1) * N, hd, FFT_THREADS);
         __syncthreads();
       }
     }
@@ -592,7 +626,7 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
     else { vv = e % nvl; r = e / nvl; }
     const int q = v0 + vv;
     C val = buf[vv * N + r];
-    if (rs.post) val = val * ((rs.post * xs[r]) > 0 ? ep : em);
+    if (rs.post) val = hd.mul(val, (rs.post * xs[r]) > 0, rs.cj);
     if (chain) {
       if constexpr (ST<S>::is_complex) val = val * (RT)dsc[q];
       else val = C{val.x * (RT)dsc[2 * q], val.y * (RT)dsc[2 * q + 1]};

@@ -1,16 +1,20 @@
 // Equal-time estimators from the spin-up Green's function alone (Sec. II B-C).
 //
-// The spin-down partner follows from the particle-hole relation in the
-// original basis, G_dn = P (1 - G_up^dagger) P with P = +1 on A and -1 on B,
-// so <n_dn,i> = conj(G_ii) and for i != j
+// In the spin channel the spin-down partner follows from the particle-hole
+// relation in the original basis, G_dn = P (1 - G_up^dagger) P with P = +1 on
+// A and -1 on B, so <n_dn,i> = b_i = conj(G_ii); in the charge channel both
+// spins see the same B's, G_dn = G_up and b_i = 1 - G_ii.  For i != j
 //   4 <s_i s_j> = (a_i - b_i)(a_j - b_j) - 2 Re(G_ij G_ji),
-//   a_i = 1 - G_ii, b_i = conj(G_ii);  4 <s_i^2> = a_i + b_i - 2 a_i b_i.
+//   a_i = 1 - G_ii;  4 <s_i^2> = a_i + b_i - 2 a_i b_i
+// (real parts: the charge channel's per-configuration estimators are complex
+// and only their averages are real).
 // D = mean a_i b_i; <H_0> = -2 Re Tr(K G); e = <H_0>/N_s + U D
 // (Sec. IV C); S_zz(k) of eq. SpinStrucF from the intra-sublattice
 // correlations of eq. SzSzCrF at k = 0 and k = b1/L; m^2 = S_zz(0)/(2 N_c).
-// The weight det_up det_dn is real and non-negative, since det_dn is the
-// complex conjugate of det_up up to a positive factor (Sec. II B); the phase
-// of det_up itself (tracked per accepted flip, anchored at every
+// The weight is real and non-negative (spin channel: det_dn is the complex
+// conjugate of det_up up to a positive factor; charge channel: P(X) det_up^2
+// with the phase of P(X), by the partial particle-hole symmetry of Sec. II B);
+// the phase of det_up itself (tracked per accepted flip, anchored at every
 // recomputation) is recorded with each measurement.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -97,6 +101,7 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
   if (st->init_mode || st->idle) return;
   const int N = d.N, Nc = d.Nc, L = d.L;
   const S* G = matp<S>(d, mat);
+  const bool charge = d.channel != 0;   // G_dn = G_up (else the particle-hole partner)
   __shared__ double red[4];
   const double twopiL = 2.0 * M_PI / L;
   double sn = 0, sD = 0, sdc = 0;
@@ -107,10 +112,10 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
     trr += real_part(g);
     tri += imag_part(g);
     dsq += real_part(g * g);
-    S a = ST<S>::one() - g;
-    S b = conjg(g);
+    S a = ST<S>::one() - g;                       // <n_up,i>
+    S b = charge ? ST<S>::one() - g : conjg(g);   // <n_dn,i>
     double ab = real_part(a * b);
-    double z = 1.0 - 2.0 * real_part(g);
+    double z = real_part(a - b);
     sn += real_part(a + b);
     sD += ab;
     sdc += real_part(a + b) - 2.0 * ab - z * z;
@@ -186,7 +191,8 @@ __global__ void __launch_bounds__(MT) k_measure(const InstDev* __restrict__ inst
 // Momentum distribution (eq. nkMatrix) from Ghat = F G F^dagger (the forward
 // 2-D DFT of both sides, in mat): spin up n_ab(k) = delta_ab - Ghat[b k, a k] / Nc,
 // spin down (G_dn = P (1 - G_up^dagger) P) n_ab(k) = s_a s_b conj(Ghat[a k, b k]) / Nc,
-// s_A = 1, s_B = -1; the spin average is added to the instance's sums.
+// s_A = 1, s_B = -1 (charge channel: equal to spin up); the spin average is
+// added to the instance's sums.
 template <typename S>
 __global__ void __launch_bounds__(MT) k_measure_k(const InstDev* __restrict__ insts, int mat) {
   const InstDev& d = insts[blockIdx.y];
@@ -204,7 +210,8 @@ __global__ void __launch_bounds__(MT) k_measure_k(const InstDev* __restrict__ in
       const S gab = G[(a * Nc + k) + (size_t)(b * Nc + k) * N];   // Ghat[a k, b k]
       const double sab = (a == b) ? 1.0 : -1.0;
       const double up_re = (a == b ? 1.0 : 0.0) - real_part(gba) * inv, up_im = -imag_part(gba) * inv;
-      const double dn_re = sab * real_part(gab) * inv, dn_im = -sab * imag_part(gab) * inv;
+      double dn_re = sab * real_part(gab) * inv, dn_im = -sab * imag_part(gab) * inv;
+      if (d.channel) { dn_re = up_re; dn_im = up_im; }   // charge channel: G_dn = G_up
       o[4 * a + 2 * b] += 0.5 * (up_re + dn_re);
       o[4 * a + 2 * b + 1] += 0.5 * (up_im + dn_im);
     }

@@ -116,13 +116,28 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
   const int64_t rpos = st->replay_pos;
   // per-site constants of the scan, fixed for the whole window (a site's
   // field only changes when it is accepted, which ends its candidacy):
-  // Delta, e^{2 lambda x}, and the uniform u (or the replayed decision)
-  double dlt = 0.0, e2x = 1.0, usite = 0.0;
+  // Delta, the prior factor of the ratio, and the uniform u (or the replayed
+  // decision).  Spin channel: Delta = e^{-2 lambda x} - 1, R = e^{2 lambda x}
+  // |r_up|^2; charge channel: Delta = e^{-2 i alpha x} - 1, R = e^{2 i alpha x}
+  // r_up^2 (r_dn = r_up, prior ratio e^{2 i alpha x}), real up to rounding.
+  const bool charge = d.channel != 0;
+  S dls = ST<S>::zero(), pri = ST<S>::one();
+  double usite = 0.0;
   bool rbit = false;
   if (wave == 0 && lane < wn) {
     const double x = (double)xs[lane];
-    dlt = exp(-2.0 * lam * x) - 1.0;
-    e2x = exp(2.0 * lam * x);
+    if constexpr (ST<S>::is_complex) {
+      if (charge) {
+        dls = cmake(cos(2.0 * lam * x) - 1.0, -sin(2.0 * lam * x));
+        pri = cmake(cos(2.0 * lam * x), sin(2.0 * lam * x));
+      } else {
+        dls = ST<S>::from_re(exp(-2.0 * lam * x) - 1.0);
+        pri = ST<S>::from_re(exp(2.0 * lam * x));
+      }
+    } else {
+      dls = exp(-2.0 * lam * x) - 1.0;
+      pri = exp(2.0 * lam * x);
+    }
     if (replay) rbit = d.replay_bits[rpos + lane] != 0;
     else usite = site_uniform(d.seed, (uint64_t)st->sweep, pass, l, w0 + lane);
   }
@@ -141,9 +156,9 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
       double R = 0.0;
       S r = ST<S>::one(), dl = ST<S>::zero();
       if (cand) {
-        dl = ST<S>::from_re(dlt);
+        dl = dls;
         r = ST<S>::one() + dl * (ST<S>::one() - C[q][q]);
-        R = e2x * absq(r);
+        R = charge ? real_part(pri * r * r) : real_part(pri) * absq(r);
         acc_q = replay ? rbit : usite < R;
         if (!(R == R) || R == 0.0 || R > 1e300) atomicOr(&st->numeric_err, NUMERR_RATIO);
       }

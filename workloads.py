@@ -38,14 +38,14 @@ def twist_grid(n=4):
 
 
 def desc(L, U, beta, dtau=0.1, theta=(0.0, 0.0), k=None, n_stab=10, seed=1,
-         precision=0, sym_measure=0, t=1.0):
+         precision=0, sym_measure=0, t=1.0, channel=0):
     N = 2 * L * L
     if k is None:
         k = max(8, int(round(math.sqrt(N))))
     return {"L": L, "t": t, "U": U, "beta": beta, "dtau": dtau,
             "theta1": float(theta[0]), "theta2": float(theta[1]),
             "n_delay": int(k), "n_stab": int(n_stab), "precision": int(precision),
-            "sym_measure": int(sym_measure), "seed": int(seed)}
+            "sym_measure": int(sym_measure), "seed": int(seed), "channel": int(channel)}
 
 
 def plain_L3(seed=1):
