@@ -62,6 +62,8 @@ def parse():
                     help="with --no-autotune: the flush kernel to use")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--channel", choices=("spin", "charge"), default="spin",
+                    help="Hubbard-Stratonovich channel of every instance (eq. SzHS or eq. DensityHS)")
     ap.add_argument("--y-solver", choices=("lu", "qr"), default="lu",
                     help="how the recomputations apply Y^-1 (pivoted LU or Householder QR)")
     ap.add_argument("--no-graphs", action="store_true",
@@ -280,13 +282,15 @@ def main():
     import torch
     from paper_2609_14668_amd import Simulation
     descs = make_descs(a.workload, a.k)
+    if a.channel == "charge":
+        descs = [dict(d, channel=1) for d in descs]
     sim = Simulation(descs)
     n = len(descs)
     Nmax = max(s[0] for s in sim.shapes)
     Mmax = max(s[1] for s in sim.shapes)
     print("workload %s: %d instances, Nmax %d, Mmax %d, complex %s" % (a.workload, n, Nmax, Mmax,
                                                                       sim.shapes[0][2]), file=sys.stderr, flush=True)
-    learned = a.proposal in ("learned", "both")
+    learned = a.proposal in ("learned", "both") and a.channel == "spin"   # learned moves: spin channel only
     if a.groups:
         sim.set_streams(a.groups)
     if a.no_graphs:
@@ -342,7 +346,8 @@ def main():
                   else ("c128" if sim.shapes[0][2] else "f64")),
         "data": "synthetic",
         "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
-                   "dtau": descs[0]["dtau"], "proposal": "plain", "y_solver": a.y_solver},
+                   "dtau": descs[0]["dtau"], "proposal": "plain", "y_solver": a.y_solver,
+                   "hs_channel": a.channel},
         "autotune": tuned,
         "ess_per_s": plain["ess_per_s"],
         "ess_per_s_err": plain["ess_per_s_err"],

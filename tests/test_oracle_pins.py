@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import exact, philox, stats
-from oracle.dqmc import BitSource, Chain, Model, RandomSource, g_down_from_up, hs_lambda
+from oracle.dqmc import BitSource, Chain, Model, RandomSource, g_down_from_up, hs_alpha, hs_lambda
 from oracle.lattice import Lattice
 
 
@@ -87,6 +87,18 @@ def test_hs_coupling_identity():
     for nu in (0, 1):
         for nd in (0, 1):
             lhs = 0.5 * sum(np.exp(lam * x * (nu - nd)) for x in (1, -1))
+            rhs = np.exp(-dtau * U * (nu * nd - (nu + nd) / 2))
+            assert abs(lhs - rhs) < 1e-15
+
+
+def test_hs_charge_coupling_identity():
+    # eq. DensityHS: (e^{dtau U/2}/2) sum_x exp(gamma_c x (n_up + n_dn - 1)) with
+    # gamma_c = i alpha, cos(alpha) = exp(-dtau U/2) (eq. coupling)
+    U, dtau = 3.73, 0.1
+    gc = 1j * hs_alpha(U, dtau)
+    for nu in (0, 1):
+        for nd in (0, 1):
+            lhs = 0.5 * np.exp(dtau * U / 2) * sum(np.exp(gc * x * (nu + nd - 1)) for x in (1, -1))
             rhs = np.exp(-dtau * U * (nu * nd - (nu + nd) / 2))
             assert abs(lhs - rhs) < 1e-15
 
