@@ -213,6 +213,15 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
 /* Estimator means of instance inst (see dqmc_obs); synchronises.
  * DQMC_ENUMERIC (out still filled) if the instance hit a numerical error. */
 dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out);
+/* How the full-length delayed vectors x_k, y_k of a window's accepted flips
+ * are formed (eq. DelayRgenk): mm = 0 (default) by the recursion itself, one
+ * row of X and column of Y per thread; mm = 1 in matrix form, X_new = A Tx
+ * and Y_new = Ty B with A, B the window's columns and rows of G - X Y and
+ * Tx, Ty the triangular coefficients of the recursion (the products on the
+ * matrix cores, the coefficients by a serial recursion per row).  The same
+ * vectors up to rounding; learned block moves always use the recursion.
+ * DQMC_EINVAL for other values. */
+dqmc_status dqmc_set_expand_kernel(dqmc_handle h, int32_t mm);
 /* How a recomputation applies Y^{-1} in G = U_L D_Lb^{-1} Y^{-1} D_Rb^{-1}
  * U_R^H (eq. GrFMat with the split of D into its large and small parts,
  * Sec. II B): lu = 1 (default) factors Y by LU with partial pivoting, whose

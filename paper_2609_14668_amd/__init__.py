@@ -74,6 +74,7 @@ _SIGS = {
     "dqmc_reset_obs": [_P],
     "dqmc_set_measure_k": [_P, ctypes.c_int32],
     "dqmc_set_y_solver": [_P, ctypes.c_int32],
+    "dqmc_set_expand_kernel": [_P, ctypes.c_int32],
     "dqmc_get_nk": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
@@ -269,6 +270,12 @@ class Simulation:
         return d
 
     measure = dqmc_measure
+
+    def dqmc_set_expand_kernel(self, mm):
+        """0: window vectors by the recursion (default); 1: in matrix form."""
+        self._chk(self.lib.dqmc_set_expand_kernel(self.h, int(mm)), "set_expand_kernel")
+
+    set_expand_kernel = dqmc_set_expand_kernel
 
     def dqmc_set_y_solver(self, lu):
         """1: Y^{-1} by pivoted LU (default); 0: by Householder QR."""

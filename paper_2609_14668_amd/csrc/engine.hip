@@ -215,6 +215,7 @@ struct dqmc_ctx {
   int flush_variant = 0;          // 0: wave-per-block flush, 1: LDS-tiled GEMM, 2: work-queue flush (FP64 only)
   bool measure_k = true;          // momentum distribution with every measurement
   bool y_lu = true;               // Y^{-1} by pivoted LU (false: by Householder QR)
+  bool expand_mm = false;         // window vectors in matrix form (false: by the recursion)
   int n_cu = 256;                 // compute units (persistent grids)
   // instance groups on their own streams (see issue_steps)
   int n_groups = 1;
@@ -601,7 +602,12 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
     }
     {
       TimedScope t(h, c.s, DQMC_T_EXPAND);
-      c.chk(launch_expand(c.di, c.n, h->Nmax, h->cplx, h->kcap_max, c.s));
+      if (h->expand_mm) {
+        c.chk(launch_expand_mm(c.di, c.n, h->Nmax, h->cplx, c.s));
+        c.chk(launch_bump(c.di, c.n, c.s));
+      } else {
+        c.chk(launch_expand(c.di, c.n, h->Nmax, h->cplx, h->kcap_max, c.s));
+      }
     }
     {
       TimedScope t(h, c.s, DQMC_T_FLUSH);
@@ -1013,7 +1019,7 @@ static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hip
 // memory: the launches of a step are fixed by these.
 static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, int groups) {
   std::vector<int> k = {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant,
-                        h->kcap_max, h->measure_k ? 1 : 0, h->y_lu ? 1 : 0};
+                        h->kcap_max, h->measure_k ? 1 : 0, h->y_lu ? 1 : 0, h->expand_mm ? 1 : 0};
   k.insert(k.end(), h->fft_tile.begin(), h->fft_tile.end());
   return k;
 }
@@ -1375,6 +1381,12 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
     o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM]; o[10] = row[OBS_CHI];
   }
   *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_expand_kernel(dqmc_handle h, int32_t mm) {
+  if (!h || (mm != 0 && mm != 1)) return DQMC_EINVAL;
+  h->expand_mm = mm != 0;
   return DQMC_OK;
 }
 

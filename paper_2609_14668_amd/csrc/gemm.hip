@@ -3,8 +3,10 @@
 // C = alpha op(A) op(B) + beta C per instance, on named per-instance matrices.
 // It serves the rank-k flush of the delayed update, G <- G - X Y
 // (eq. FinalDelay), and the dense products of the QR stabilisation.
-// Complex128 is done with four real MFMA products per tile (re*re - im*im,
-// re*im + im*re) on split real/imaginary LDS planes.
+// Complex128 is done with three real MFMA products per tile (Gauss: Re Re,
+// Im Im and (Re + Im)(Re + Im)) on split real/imaginary LDS planes.  It also
+// forms the delayed vectors of a window in matrix form (k_expand_coef,
+// k_expand_mm).
 //
 // Tiling: 64 x 64 output tile per workgroup of four 64-wide waves, each wave
 // a 32 x 32 block of 2 x 2 MFMA tiles; K is staged through LDS 16 at a time.
@@ -39,6 +41,9 @@ template <>
 __device__ __forceinline__ void split<double>(double v, double& re, double& im) { re = v; im = 0.0; }
 template <>
 __device__ __forceinline__ void split<cplx>(cplx v, double& re, double& im) { re = v.x; im = v.y; }
+
+__device__ __forceinline__ double shfl_xor_s(double v, int m) { return __shfl_xor(v, m); }
+__device__ __forceinline__ cplx shfl_xor_s(cplx v, int m) { return cmake(__shfl_xor(v.x, m), __shfl_xor(v.y, m)); }
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
 // dispatch order.  Map the dispatch index so that all workgroups of an
@@ -573,6 +578,151 @@ k_flush_f32(const InstDev* __restrict__ insts, int n_inst, int flags) {
   }
 }
 
+// ---- the delayed vectors of a window in matrix form (eq. DelayRgenk) --------------------
+// For the m accepted sites s_0 < .. < s_{m-1} of a window (positions in the
+// window, global w0 + s_k) the recursion
+//   x_k = c_k (a_k - sum_{q<k} x_q u_qk),   u_qk = y_q[w0 + s_k] (window part),
+//   y_k = b_k + sum_{q<k} v_kq y_q,          v_kq = x_q[w0 + s_k] (window part),
+// with a_k = (G - X Y)[:, w0 + s_k] and b_k = (1 - G + X Y)[w0 + s_k, :] over the
+// pending terms, is linear in the a's and b's:
+//   x_k = sum_r a_r Tx[r][k],  Tx[r][k] = c_k (delta_rk - sum_{r<=q<k} Tx[r][q] u_qk),
+//   y_k = sum_c Ty[k][c] b_c,  Ty[k][c] = delta_kc + sum_{c<=q<k} v_kq Ty[q][c].
+// k_expand_coef forms Tx (rows placed at the window positions s_r, in W2) and
+// Ty^T (rows at s_c, in QA), one workgroup per instance; k_expand_mm then forms
+// X[:, f:f+m] = A~ Tx~ and Y[f:f+m, :] = (B~^T Ty~^T)^T per 64-row block with the
+// GEMM tile body, A~ = (G - X Y)[:, w0 + 0..wn) in W1 and B~ = (1 - G + X Y)
+// restricted to the window rows in W3 (row a of the window at W3[a + j N]).
+// Both kernels read the window's table (c_k, window parts of x_q and y_q).
+template <typename S>
+__global__ void __launch_bounds__(256) k_expand_coef(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return;
+  const int m = st.m_w;
+  if (m == 0) return;
+  const int N = d.N, wn = st.wlen;
+  constexpr int WM = DQMC_WMAX;
+  const S* wc = reinterpret_cast<const S*>(d.wcoef);
+  S* Tx = matp<S>(d, MAT_W2);
+  S* TyT = matp<S>(d, MAT_QA);
+  __shared__ S Uk[WM][WM];   // Uk[k][q] = u_qk, later v_kq
+  __shared__ S Tq[WM][WM];   // Tq[q][r] = Tx[r][q], later Ty[q][c]
+  __shared__ int site[WM];
+  __shared__ S cks[WM];      // c_k
+  const int tid = threadIdx.x;
+  if (tid < WM) {
+    site[tid] = tid < m ? d.acc_site[tid] : 0;
+    cks[tid] = tid < m ? wc[tid] : ST<S>::zero();
+  }
+  // zero the window rows of both coefficient blocks
+  for (int e = tid; e < wn * m; e += 256) {
+    const int a = e % wn, k = e / wn;
+    Tx[a + (size_t)k * N] = ST<S>::zero();
+    TyT[a + (size_t)k * N] = ST<S>::zero();
+  }
+  __syncthreads();
+  for (int e = tid; e < m * m; e += 256) {
+    const int k = e / m, q = e % m;
+    Uk[k][q] = q < k ? wc[DQMC_WC_Y + q * WM + site[k]] : ST<S>::zero();
+  }
+  __syncthreads();
+  // Tx: four lanes per row r split the sum over q.  A row only reads its own
+  // earlier entries, written by a lane of the same wave: LDS operations of
+  // one wave take effect in program order, so no workgroup barrier is needed
+  // between the steps (the wavefront fences keep the compiler from moving
+  // them).
+  const int r = tid >> 2, part = tid & 3;
+  for (int k = 0; k < m; ++k) {
+    S sum = ST<S>::zero();
+    if (r < m && k >= r)
+      for (int q = r + part; q < k; q += 4) sum = sum + Tq[q][r] * Uk[k][q];
+    sum = sum + shfl_xor_s(sum, 1);
+    sum = sum + shfl_xor_s(sum, 2);
+    if (r < m && k >= r && part == 0) Tq[k][r] = cks[k] * ((k == r ? ST<S>::one() : ST<S>::zero()) - sum);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  for (int e = tid; e < m * m; e += 256) {
+    const int k = e / m, rr = e % m;
+    if (k >= rr) Tx[site[rr] + (size_t)k * N] = Tq[k][rr];
+  }
+  __syncthreads();
+  for (int e = tid; e < m * m; e += 256) {
+    const int k = e / m, q = e % m;
+    Uk[k][q] = q < k ? wc[DQMC_WC_X + q * WM + site[k]] : ST<S>::zero();
+  }
+  __syncthreads();
+  // Ty: four lanes per column c (a column only reads its own entries)
+  const int c = r;
+  for (int k = 0; k < m; ++k) {
+    S sum = ST<S>::zero();
+    if (c < m && k >= c)
+      for (int q = c + part; q < k; q += 4) sum = sum + Uk[k][q] * Tq[q][c];
+    sum = sum + shfl_xor_s(sum, 1);
+    sum = sum + shfl_xor_s(sum, 2);
+    if (c < m && k >= c && part == 0) Tq[k][c] = (k == c ? ST<S>::one() : ST<S>::zero()) + sum;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  for (int e = tid; e < m * m; e += 256) {
+    const int k = e / m, cc = e % m;
+    if (k >= cc) TyT[site[cc] + (size_t)k * N] = Tq[k][cc];
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(GEMM_THREADS, 2) k_expand_mm(const InstDev* __restrict__ insts, int n_inst) {
+  int inst, bx;
+  xcd_slot(n_inst, inst, bx);
+  if (inst < 0) return;
+  const InstDev& d = insts[inst];
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return;
+  const int m = st.m_w;
+  const int N = d.N;
+  const int j0 = bx * BM;
+  if (m == 0 || j0 >= N) return;
+  const int f = st.fill, w0 = st.wstart, wn = st.wlen;
+  const int rows = min(BM, N - j0);
+  const S* G = matp<S>(d, MAT_G);
+  S* X = matp<S>(d, MAT_X);
+  S* Y = matp<S>(d, MAT_Y);
+  S* W1 = matp<S>(d, MAT_W1);
+  S* W3 = matp<S>(d, MAT_W3);
+  const S* Tx = matp<S>(d, MAT_W2);
+  const S* TyT = matp<S>(d, MAT_QA);
+  __shared__ GemmSmem<ST<S>::is_complex> sm;
+  const int tid = threadIdx.x;
+  // A~ = G[j0.., w0..] and B~ (window rows of 1 - G, as W3[a + j N]); both
+  // copies read 64 consecutive elements per column
+  for (int e = tid; e < rows * wn; e += GEMM_THREADS) {
+    const int i = e % rows, a = e / rows;
+    W1[(j0 + i) + (size_t)a * N] = G[(j0 + i) + (size_t)(w0 + a) * N];
+  }
+  for (int e = tid; e < wn * rows; e += GEMM_THREADS) {
+    const int a = e % wn, j = e / wn;
+    S v = -G[(w0 + a) + (size_t)(j0 + j) * N];
+    if (w0 + a == j0 + j) v = v + ST<S>::one();
+    W3[a + (size_t)(j0 + j) * N] = v;
+  }
+  __syncthreads();
+  if (f > 0) {
+    // A~ -= X[j0.., :f] Y[:f, w0..];   B~ += X[w0.., :f] Y[:f, j0..]
+    gemm_tiles<S>(X + j0, Y + w0, W1 + j0, N, 0, 1, rows, wn, f, false, -1.0, 1.0, 0, 1, sm);
+    __syncthreads();
+    gemm_tiles<S>(X + w0, Y + j0, W3 + (size_t)j0 * N, N, 0, 1, wn, rows, f, false, 1.0, 1.0, 0, 1, sm);
+    __syncthreads();
+  }
+  // X[j0.., f..f+m) = A~ Tx~;  Y[f..f+m, j0..] = B~^T Ty~^T (as columns of Y's column-major view)
+  gemm_tiles<S>(W1 + j0, Tx, X + j0 + (size_t)f * N, N, 0, 0, rows, m, wn, false, 1.0, 0.0, 0, 1, sm);
+  __syncthreads();
+  gemm_tiles<S>(W3 + (size_t)j0 * N, TyT, Y + j0 + (size_t)f * N, N, 1, 0, rows, m, wn, false, 1.0, 0.0, 0, 1, sm);
+}
+
 }  // namespace
 
 hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, GemmOperand A,
@@ -619,5 +769,16 @@ hipError_t launch_flush_direct(const InstDev* insts, int n_inst, int Nmax, bool 
   }
   if (cplx_) hipLaunchKernelGGL(k_flush_direct<cplx>, grid, dim3(256), 0, s, insts, n_inst, flags);
   else hipLaunchKernelGGL(k_flush_direct<double>, grid, dim3(256), 0, s, insts, n_inst, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_mm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s) {
+  if (cplx_) hipLaunchKernelGGL(k_expand_coef<cplx>, dim3(1, n_inst), dim3(256), 0, s, insts);
+  else hipLaunchKernelGGL(k_expand_coef<double>, dim3(1, n_inst), dim3(256), 0, s, insts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((Nmax + BM - 1) / BM, xcd_grid_y(n_inst));
+  if (cplx_) hipLaunchKernelGGL(k_expand_mm<cplx>, grid, dim3(GEMM_THREADS), 0, s, insts, n_inst);
+  else hipLaunchKernelGGL(k_expand_mm<double>, grid, dim3(GEMM_THREADS), 0, s, insts, n_inst);
   return hipGetLastError();
 }

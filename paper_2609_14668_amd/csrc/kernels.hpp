@@ -67,6 +67,10 @@ hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, in
                          hipStream_t s);
 hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int kcap_max,
                          hipStream_t s);
+// The delayed vectors of the last window in matrix form (coefficients, then
+// MFMA tile products; uses W1, W2, W3 and QA as scratch), and the fill bump.
+hipError_t launch_expand_mm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
+hipError_t launch_bump(const InstDev* insts, int n_inst, hipStream_t s);
 hipError_t launch_flush_done(const InstDev* insts, int n_inst, int any, hipStream_t s);
 
 // ---- schedule -------------------------------------------------------------------------

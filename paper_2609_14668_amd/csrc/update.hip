@@ -483,6 +483,11 @@ hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_,
   return hipGetLastError();
 }
 
+hipError_t launch_bump(const InstDev* insts, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_bump, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst);
+  return hipGetLastError();
+}
+
 hipError_t launch_flush_done(const InstDev* insts, int n_inst, int any, hipStream_t s) {
   hipLaunchKernelGGL(k_flush_done, dim3((n_inst + 63) / 64), dim3(64), 0, s, insts, n_inst, any);
   return hipGetLastError();

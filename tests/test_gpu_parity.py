@@ -82,10 +82,11 @@ def test_initial_green_matches_oracle(L, th, beta):
     assert np.abs(sim.green(0, spin=1) - refd).max() < 1e-10
 
 
-def _replay_case(d, seed, p=0.4, sweeps=1, measure=False, y_solver=1):
+def _replay_case(d, seed, p=0.4, sweeps=1, measure=False, y_solver=1, expand=1):
     import torch
     sim = _sim([d])
     sim.set_y_solver(y_solver)
+    sim.set_expand_kernel(expand)
     m = _model(d)
     N, M, cx = sim.shapes[0]
     f0 = workloads.random_fields(seed, M, N)
@@ -138,6 +139,24 @@ def test_philox_chain_matches_oracle():
     ch.sweep(PhiloxSource(77), measure=False)
     assert np.array_equal(sim.fields(0), ch.fields)
     assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
+
+
+@pytest.mark.parametrize("expand", [1, 0])
+@pytest.mark.parametrize("L,th,k", [(4, (0.7, 2.2), 16), (12, (0.0, 0.0), 128), (12, (0.4, 1.9), 96)])
+def test_replay_expand_kernels_match_oracle(L, th, k, expand):
+    """Both ways of forming the window's delayed vectors (matrix form and
+    recursion, eq. DelayRgenk) reproduce the oracle's chain; at k = 96 and
+    128 on L = 12 (five windows per slice) windows start with pending terms
+    from earlier windows of the slice."""
+    d = workloads.desc(L, 3.7, 1.0, theta=th, k=k, n_stab=10)
+    sim, ch, ratios = _replay_case(d, 61, p=0.3, expand=expand)
+    assert np.array_equal(sim.fields(0), ch.fields)
+    assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
+    assert np.abs(ratios - np.array(ch.ratios)).max() / np.abs(ch.ratios).max() < 1e-10
+    st = sim.stats(0)
+    assert st["accepted"] == ch.accepted
+    if k >= 96:   # windows of ~19 accepted flips accumulate: most windows start with pending terms
+        assert st["accepted"] / st["flushes"] > 40
 
 
 def test_replay_larger_lattice():
