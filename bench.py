@@ -64,6 +64,8 @@ def parse():
                     help="only copy 256 MiB device to device three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--channel", choices=("spin", "charge"), default="spin",
                     help="Hubbard-Stratonovich channel of every instance (eq. SzHS or eq. DensityHS)")
+    ap.add_argument("--update", choices=("delayed", "submatrix"), default="delayed",
+                    help="single-site update scheme (delayed rank-k flushes or one block update per window)")
     ap.add_argument("--y-solver", choices=("lu", "qr"), default="lu",
                     help="how the recomputations apply Y^-1 (pivoted LU or Householder QR)")
     ap.add_argument("--no-graphs", action="store_true",
@@ -296,6 +298,7 @@ def main():
     if a.no_graphs:
         sim.set_graphs(False)
     sim.set_y_solver(1 if a.y_solver == "lu" else 0)
+    sim.set_update_scheme(1 if a.update == "submatrix" else 0)
     tuned = None
     if a.flush_kernel:
         sim.set_flush_kernel(FLUSH_NAMES.index(a.flush_kernel))
@@ -347,7 +350,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "instances": n, "Nmax": Nmax, "Mmax": Mmax, "U": descs[0]["U"],
                    "dtau": descs[0]["dtau"], "proposal": "plain", "y_solver": a.y_solver,
-                   "hs_channel": a.channel},
+                   "hs_channel": a.channel, "update": a.update},
         "autotune": tuned,
         "ess_per_s": plain["ess_per_s"],
         "ess_per_s_err": plain["ess_per_s_err"],

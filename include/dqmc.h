@@ -213,6 +213,18 @@ dqmc_status dqmc_flush_test(dqmc_handle h, int32_t inst, const double* host_X,
 /* Estimator means of instance inst (see dqmc_obs); synchronises.
  * DQMC_ENUMERIC (out still filled) if the instance hit a numerical error. */
 dqmc_status dqmc_measure(dqmc_handle h, int32_t inst, dqmc_obs* out);
+/* Update scheme of the single-site sweep (Sec. III B).  0 (default): the
+ * delayed update, rank-1 terms x_k y_k of eq. DelayRgenk accumulated across
+ * windows and flushed at rank k (eq. FinalDelay).  1: the submatrix update
+ * named in Sec. III B: after the window scan the accepted flips S of the
+ * window are applied as one multi-site update,
+ *   G' = G - G[:, S] Delta_S (1 + (1 - G)_SS Delta_S)^{-1} (1 - G)[S, :],
+ * with the m x m inverse by Gauss-Jordan elimination in the order of
+ * acceptance (its pivots are the sequential ratios), G[:, window] M~ on the
+ * matrix cores, and a flush after every window (the flush rank is then the
+ * window's accept count).  Same chain, G equal up to rounding.  DQMC_EINVAL
+ * for other values. */
+dqmc_status dqmc_set_update_scheme(dqmc_handle h, int32_t scheme);
 /* How the full-length delayed vectors x_k, y_k of a window's accepted flips
  * are formed (eq. DelayRgenk): mm = 0 (default) by the recursion itself, one
  * row of X and column of Y per thread; mm = 1 in matrix form, X_new = A Tx

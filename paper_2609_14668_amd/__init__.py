@@ -75,6 +75,7 @@ _SIGS = {
     "dqmc_set_measure_k": [_P, ctypes.c_int32],
     "dqmc_set_y_solver": [_P, ctypes.c_int32],
     "dqmc_set_expand_kernel": [_P, ctypes.c_int32],
+    "dqmc_set_update_scheme": [_P, ctypes.c_int32],
     "dqmc_get_nk": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
@@ -270,6 +271,12 @@ class Simulation:
         return d
 
     measure = dqmc_measure
+
+    def dqmc_set_update_scheme(self, scheme):
+        """0: delayed update (default); 1: submatrix update (one block update per window)."""
+        self._chk(self.lib.dqmc_set_update_scheme(self.h, int(scheme)), "set_update_scheme")
+
+    set_update_scheme = dqmc_set_update_scheme
 
     def dqmc_set_expand_kernel(self, mm):
         """0: window vectors by the recursion (default); 1: in matrix form."""

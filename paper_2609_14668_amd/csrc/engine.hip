@@ -128,7 +128,7 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.perm = o; o = al(o + sizeof(int32_t) * 2 * N);
     f.acc = o; o = al(o + sizeof(int32_t) * WINDOW);
     f.gsite = o; o = al(o + sizeof(int32_t) * WINDOW);
-    f.wcoef = o; o = al(o + ss * (WINDOW + 2 * WINDOW * WINDOW));
+    f.wcoef = o; o = al(o + ss * DQMC_WC_SIZE);
     f.targets = o; o = al(o + sizeof(float) * (size_t)M * N);
     f.learn = o; o = al(o + sizeof(LearnState));
     f.rsplit = o; o = al(o + ss * (size_t)RSPLIT_ROWS * N);
@@ -216,6 +216,7 @@ struct dqmc_ctx {
   bool measure_k = true;          // momentum distribution with every measurement
   bool y_lu = true;               // Y^{-1} by pivoted LU (false: by Householder QR)
   bool expand_mm = false;         // window vectors in matrix form (false: by the recursion)
+  bool submatrix = false;         // submatrix update: one block update per window
   int n_cu = 256;                 // compute units (persistent grids)
   // instance groups on their own streams (see issue_steps)
   int n_groups = 1;
@@ -599,6 +600,24 @@ void step(Ctx& c, int64_t s, bool measure, int replay) {
     {
       TimedScope t(h, c.s, DQMC_T_WINDOW);
       c.chk(launch_window(c.di, c.n, h->cplx, WINDOW, replay, c.s));
+    }
+    if (h->submatrix) {
+      // the window's accepted flips as one block update (every window flushes)
+      {
+        TimedScope t(h, c.s, DQMC_T_EXPAND);
+        const int w0 = w * WINDOW;
+        c.chk(launch_submatrix_coef(c.di, c.n, h->cplx, c.s));
+        c.gemm(opnd(MAT_G, 0, 0, 0, 0, w0), opnd(MAT_W2, 0), opnd(MAT_X, 0), dim(1, 0), dim(1, 0, WINDOW),
+               dim(1, -w0, WINDOW), 1.0, 0.0, GF_NC_MW);
+        c.chk(launch_submatrix_rows(c.di, c.n, h->Nmax, h->cplx, c.s));
+        c.chk(launch_bump(c.di, c.n, c.s));
+      }
+      {
+        TimedScope t(h, c.s, DQMC_T_FLUSH);
+        flush(c, GF_IF_ANY);
+      }
+      c.chk(launch_flush_done(c.di, c.n, 1, c.s));
+      continue;
     }
     {
       TimedScope t(h, c.s, DQMC_T_EXPAND);
@@ -1019,7 +1038,8 @@ static hipError_t issue_steps(dqmc_handle h, int64_t steps, int32_t measure, hip
 // memory: the launches of a step are fixed by these.
 static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, int groups) {
   std::vector<int> k = {measure != 0, replay, groups, h->learn_P, h->learn_m, h->collect_every, h->flush_variant,
-                        h->kcap_max, h->measure_k ? 1 : 0, h->y_lu ? 1 : 0, h->expand_mm ? 1 : 0};
+                        h->kcap_max, h->measure_k ? 1 : 0, h->y_lu ? 1 : 0, h->expand_mm ? 1 : 0,
+                        h->submatrix ? 1 : 0};
   k.insert(k.end(), h->fft_tile.begin(), h->fft_tile.end());
   return k;
 }
@@ -1381,6 +1401,12 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
     o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM]; o[10] = row[OBS_CHI];
   }
   *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_set_update_scheme(dqmc_handle h, int32_t scheme) {
+  if (!h || (scheme != 0 && scheme != 1)) return DQMC_EINVAL;
+  h->submatrix = scheme == 1;
   return DQMC_OK;
 }
 

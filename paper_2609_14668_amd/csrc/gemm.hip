@@ -282,7 +282,8 @@ k_gemm(const InstDev* __restrict__ insts, int n_inst, GemmOperand A, GemmOperand
   if ((flags & GF_IF_FULL) && st.fill < d.kflush) return;
   if ((flags & GF_IF_ANY) && st.fill <= 0) return;
   const int M = dimval(Md, Nn);
-  const int NC = dimval(Nd, Nn);
+  int NC = dimval(Nd, Nn);
+  if (flags & GF_NC_MW) NC = min(NC, st.m_w);
   const int K = (flags & GF_K_FILL) ? st.fill : dimval(Kd, Nn);
   if (M <= 0 || NC <= 0) return;
   const int ld = Nn;
@@ -578,6 +579,150 @@ k_flush_f32(const InstDev* __restrict__ insts, int n_inst, int flags) {
   }
 }
 
+// ---- submatrix update of a window (Sec. III B) ---------------------------------------------
+// The accepted flips S of a window change G as one multi-site flip (the final
+// G depends only on which fields flipped):
+//   G' = G - G[:, S] Delta_S (1 + (1 - G)_SS Delta_S)^{-1} (1 - G)[S, :],
+// block Sherman-Morrison with G the window's starting G (the previous window
+// flushed).  k_submatrix_coef inverts Q = 1 + (1 - G_SS) Delta_S (m x m) by
+// Gauss-Jordan elimination in the order of acceptance, whose pivots are the
+// sequential ratios r_k (no interchanges: the same divisions as the
+// single-site updates), and stores M~ = P Delta_S Q^{-1} in W2 (row s_r of
+// the window for accepted flip r, zero rows elsewhere).  X = G[:, window] M~
+// is then a GEMM and Y the rows (1 - G)[S, :] (k_submatrix_rows).
+template <typename S>
+__global__ void __launch_bounds__(256) k_submatrix_coef(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return;
+  const int m = st.m_w;
+  if (m == 0) return;
+  const int N = d.N, w0 = st.wstart, wn = st.wlen;
+  constexpr int WM = DQMC_WMAX, CPT = 2 * WM / 4;   // augmented columns per thread
+  const S* wc = reinterpret_cast<const S*>(d.wcoef);
+  const S* G = matp<S>(d, MAT_G);
+  S* Mt = matp<S>(d, MAT_W2);
+  // [Q | 1] held in registers: row rr = tid / 4 in the four lanes 4 rr .. 4 rr + 3
+  // (one wave), lane cg of them owns the augmented columns cg + 4 j.  The next
+  // pivot row (scaled) and pivot column go through a double-buffered LDS area,
+  // one barrier per elimination step.
+  __shared__ S prow[2][2 * WM], pcol[2][WM];
+  __shared__ S dl[WM];
+  __shared__ int site[WM];
+  const int tid = threadIdx.x, rr = tid >> 2, cg = tid & 3;
+  if (tid < WM) {
+    site[tid] = tid < m ? d.acc_site[tid] : 0;
+    dl[tid] = tid < m ? wc[DQMC_WC_D + tid] : ST<S>::zero();
+  }
+  for (int e = tid; e < wn * m; e += 256) {   // zero the window rows of M~
+    const int a = e % wn, c = e / wn;
+    Mt[a + (size_t)c * N] = ST<S>::zero();
+  }
+  __syncthreads();
+  const bool live = rr < m;
+  S q[CPT];
+  // all loads of G_SS first (clamped addresses), then the entries of Q
+  const int srow = w0 + site[min(rr, m - 1)];
+#pragma unroll
+  for (int j = 0; j < CPT / 2; ++j) {
+    const int c = min(cg + 4 * j, m - 1);
+    q[j] = gld(G + srow + (size_t)(w0 + site[c]) * N);
+  }
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int c = cg + 4 * j;
+    S v = ST<S>::zero();
+    if (j < CPT / 2 && c < m) {
+      v = ((rr == c ? ST<S>::one() : ST<S>::zero()) - q[j]) * dl[c];
+      if (rr == c) v = v + ST<S>::one();
+    } else if (c >= m && c - m == rr) {
+      v = ST<S>::one();
+    }
+    q[j] = live ? v : ST<S>::zero();
+  }
+  // publish row 0 (scaled) and column 0 for the first step
+  auto publish = [&](int k, int buf) {
+    // pivot Q[k][k] sits in lane cg = k % 4 of row k, slot k / 4
+    S piv = ST<S>::zero();
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (cg + 4 * j == k) piv = q[j];
+    piv = piv + shfl_xor_s(piv, 1);
+    piv = piv + shfl_xor_s(piv, 2);   // the other lanes of the row hold zero here
+    if (rr == k) {
+      const S inv = cdiv(ST<S>::one(), piv);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        const int c = cg + 4 * j;
+        if (c < 2 * m) prow[buf][c] = q[j] * inv;
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+        if (cg + 4 * j == k) pcol[buf][rr] = q[j];
+    }
+  };
+  publish(0, 0);
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    const int buf = k & 1;
+    if (live) {
+      const S f = pcol[buf][rr];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        const int c = cg + 4 * j;
+        if (c < 2 * m) q[j] = rr == k ? prow[buf][c] : q[j] - f * prow[buf][c];
+      }
+    }
+    if (k + 1 < m) publish(k + 1, buf ^ 1);
+    __syncthreads();
+  }
+  // M~[s_r][c] = Delta_r (Q^{-1})[r][c]
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int c = cg + 4 * j - m;
+      if (c >= 0 && c < m) Mt[site[rr] + (size_t)c * N] = dl[rr] * q[j];
+    }
+  }
+}
+
+// Y[k, j] = delta_{j, w0 + s_k} - G[w0 + s_k, j] for the accepted flips k of
+// the window; a 64-column tile through LDS, read down the window rows and
+// written along the rows of Y.
+template <typename S>
+__global__ void __launch_bounds__(256) k_submatrix_rows(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  const InstState& st = *d.st;
+  if (st.idle || st.init_mode) return;
+  const int m = st.m_w;
+  const int N = d.N;
+  const int j0 = blockIdx.x * 64;
+  if (m == 0 || j0 >= N) return;
+  const int w0 = st.wstart;
+  const S* G = matp<S>(d, MAT_G);
+  S* Y = matp<S>(d, MAT_Y);
+  __shared__ S T[DQMC_WMAX][65];
+  __shared__ int site[DQMC_WMAX];
+  const int tid = threadIdx.x;
+  if (tid < DQMC_WMAX) site[tid] = tid < m ? d.acc_site[tid] : 0;
+  __syncthreads();
+  const int cols = min(64, N - j0);
+  for (int e = tid; e < m * cols; e += 256) {
+    const int k = e % m, jj = e / m;
+    const int gi = w0 + site[k];
+    S v = -G[gi + (size_t)(j0 + jj) * N];
+    if (gi == j0 + jj) v = v + ST<S>::one();
+    T[k][jj] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < m * cols; e += 256) {
+    const int jj = e % cols, k = e / cols;
+    Y[(size_t)k * N + j0 + jj] = T[k][jj];
+  }
+}
+
 // ---- the delayed vectors of a window in matrix form (eq. DelayRgenk) --------------------
 // For the m accepted sites s_0 < .. < s_{m-1} of a window (positions in the
 // window, global w0 + s_k) the recursion
@@ -780,5 +925,18 @@ hipError_t launch_expand_mm(const InstDev* insts, int n_inst, int Nmax, bool cpl
   dim3 grid((Nmax + BM - 1) / BM, xcd_grid_y(n_inst));
   if (cplx_) hipLaunchKernelGGL(k_expand_mm<cplx>, grid, dim3(GEMM_THREADS), 0, s, insts, n_inst);
   else hipLaunchKernelGGL(k_expand_mm<double>, grid, dim3(GEMM_THREADS), 0, s, insts, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t launch_submatrix_coef(const InstDev* insts, int n_inst, bool cplx_, hipStream_t s) {
+  if (cplx_) hipLaunchKernelGGL(k_submatrix_coef<cplx>, dim3(1, n_inst), dim3(256), 0, s, insts);
+  else hipLaunchKernelGGL(k_submatrix_coef<double>, dim3(1, n_inst), dim3(256), 0, s, insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_submatrix_rows(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s) {
+  dim3 grid((Nmax + 63) / 64, n_inst);
+  if (cplx_) hipLaunchKernelGGL(k_submatrix_rows<cplx>, grid, dim3(256), 0, s, insts);
+  else hipLaunchKernelGGL(k_submatrix_rows<double>, grid, dim3(256), 0, s, insts);
   return hipGetLastError();
 }

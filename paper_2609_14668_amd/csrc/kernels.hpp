@@ -46,6 +46,7 @@ enum GemmFlags : int {
   GF_A_UPPER = 8,      // op(A) is upper triangular (entries below the diagonal read as 0)
   GF_SKIP_INIT = 16,   // skip while the initial stack is built
   GF_ONLY_INIT_END = 32,
+  GF_NC_MW = 64,       // NC = min(NC, the instance's accepts in the last window); skip if none
 };
 hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, GemmOperand A,
                        GemmOperand B, GemmOperand C, GemmDim M, GemmDim Nn, GemmDim K,
@@ -67,6 +68,11 @@ hipError_t launch_window(const InstDev* insts, int n_inst, bool cplx_, int W, in
                          hipStream_t s);
 hipError_t launch_expand(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int kcap_max,
                          hipStream_t s);
+// Submatrix update of the last window: M~ = P Delta_S (1 + (1 - G)_SS Delta_S)^{-1}
+// into W2 (rows at the window positions of the accepted sites) and the rows
+// (1 - G)[S, :] into Y; X = G[:, window] M~ is a GEMM with GF_NC_MW.
+hipError_t launch_submatrix_coef(const InstDev* insts, int n_inst, bool cplx_, hipStream_t s);
+hipError_t launch_submatrix_rows(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
 // The delayed vectors of the last window in matrix form (coefficients, then
 // MFMA tile products; uses W1, W2, W3 and QA as scratch), and the fill bump.
 hipError_t launch_expand_mm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, hipStream_t s);
@@ -212,7 +218,10 @@ hipError_t launch_learn_window(const InstDev* insts, int n_inst, int nc_max, int
 hipError_t launch_learn_propose(const InstDev* insts, int n_inst, bool cplx_, int move, int m, hipStream_t s);
 hipError_t launch_learn_decide(const InstDev* insts, int n_inst, bool cplx_, int move, hipStream_t s);
 // Window coefficient table (in units of the matrix element type): c_k at
-// [0, WMAX), x_k at [WC_X + k WMAX + a], y_k at [WC_Y + k WMAX + b].
+// [0, WMAX), x_k at [WC_X + k WMAX + a], y_k at [WC_Y + k WMAX + b], Delta_k
+// of the accepted flips at [WC_D + k].
 constexpr int DQMC_WMAX = 64;
 constexpr int DQMC_WC_X = DQMC_WMAX;
 constexpr int DQMC_WC_Y = DQMC_WMAX + DQMC_WMAX * DQMC_WMAX;
+constexpr int DQMC_WC_D = DQMC_WMAX + 2 * DQMC_WMAX * DQMC_WMAX;
+constexpr int DQMC_WC_SIZE = 2 * DQMC_WMAX + 2 * DQMC_WMAX * DQMC_WMAX;

@@ -175,6 +175,7 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
       if (qs < wn) {
         const S cfac = shfl_s(cdiv(dl, r), qs);
         const S rr = shfl_s(r, qs);
+        const S dsel = shfl_s(dl, qs);
         const bool tail = q > qs && q < wn;
         const S xv = tail ? C[q][qs] * cfac : ST<S>::zero();
         const S yv = tail ? -C[qs][q] : ST<S>::zero();
@@ -184,6 +185,7 @@ k_window(const InstDev* __restrict__ insts, int W, int replay) {
         wc[WC_Y + k * WMAX + q] = yv;
         if (lane == 0) {
           wc[k] = cfac;
+          wc[DQMC_WC_D + k] = dsel;
           d.acc_site[k] = qs;
           d.acc_gsite[k] = w0 + qs;
           // det(1 + B..B) of spin up changes by the factor r_up (eq. rRatioLocal)

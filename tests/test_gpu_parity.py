@@ -82,11 +82,12 @@ def test_initial_green_matches_oracle(L, th, beta):
     assert np.abs(sim.green(0, spin=1) - refd).max() < 1e-10
 
 
-def _replay_case(d, seed, p=0.4, sweeps=1, measure=False, y_solver=1, expand=1):
+def _replay_case(d, seed, p=0.4, sweeps=1, measure=False, y_solver=1, expand=0, scheme=0):
     import torch
     sim = _sim([d])
     sim.set_y_solver(y_solver)
     sim.set_expand_kernel(expand)
+    sim.set_update_scheme(scheme)
     m = _model(d)
     N, M, cx = sim.shapes[0]
     f0 = workloads.random_fields(seed, M, N)
@@ -157,6 +158,44 @@ def test_replay_expand_kernels_match_oracle(L, th, k, expand):
     assert st["accepted"] == ch.accepted
     if k >= 96:   # windows of ~19 accepted flips accumulate: most windows start with pending terms
         assert st["accepted"] / st["flushes"] > 40
+
+
+@pytest.mark.parametrize("L,th,beta,k", [(3, (0, 0), 3.0, 8), (4, (0.7, 2.2), 2.0, 16), (6, (0, 0), 2.0, 24),
+                                        (12, (0.4, 1.9), 1.0, 32)])
+def test_replay_submatrix_update_matches_oracle(L, th, beta, k):
+    """The submatrix update (each window's accepted flips as one block
+    Sherman-Morrison update) reproduces the oracle's sequential chain:
+    fields, G, every ratio and the counters; with measurements."""
+    d = workloads.desc(L, 3.8, beta, theta=th, k=k, n_stab=10)
+    sim, ch, ratios = _replay_case(d, 71, scheme=1, sweeps=2, measure=True)
+    assert np.array_equal(sim.fields(0), ch.fields)
+    assert np.abs(sim.green(0) - ch.G[0]).max() < 1e-10
+    assert np.abs(ratios - np.array(ch.ratios)).max() / np.abs(ch.ratios).max() < 1e-10
+    st = sim.stats(0)
+    assert st["accepted"] == ch.accepted and st["proposals"] == ch.proposals
+    assert st["drift_max"] < 1e-8
+    o = sim.measure(0)
+    for key in ("D", "ekin", "e", "Szz_G", "Szz_dk", "m2", "chi_e"):
+        ref = np.mean([x[key] for x in ch.samples])
+        assert abs(o[key] - ref) < 1e-10, key
+
+
+def test_submatrix_update_keeps_the_chain():
+    """Philox chains (no replay): the delayed and the submatrix update take the
+    same decisions on a twisted uneven batch."""
+    import torch
+    descs = [workloads.desc(4, 3.7, 2.0, theta=(0.3, 1.1), k=16, seed=5),
+             workloads.desc(6, 3.7, 2.0, k=24, seed=6)]
+    out = []
+    for scheme in (0, 1):
+        sim = _sim(descs)
+        sim.set_update_scheme(scheme)
+        sim.sweep(2, measure=False)
+        torch.cuda.synchronize()
+        out.append(([sim.fields(i) for i in range(2)], [sim.green(i) for i in range(2)]))
+    for i in range(2):
+        assert np.array_equal(out[0][0][i], out[1][0][i])
+        assert np.abs(out[0][1][i] - out[1][1][i]).max() < 1e-10
 
 
 def test_replay_larger_lattice():
