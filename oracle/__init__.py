@@ -15,8 +15,12 @@ lattice   honeycomb torus, dense hopping matrix K (Gauge-I / Gauge-II, twists),
           f(k) and the (shifted) momentum grid.             [Sec. II A, III C]
 dqmc      dense propagators B_l, UDV-stabilised G, sequential Sherman-Morrison
           sweep over both spins, replay mode, Wick observables. [Sec. II B-C, III B]
+tau       time-displaced G(tau,0), G(0,tau) from the block-cyclic inverse, the
+          per-configuration <H_I(tau) H_I(0)> by Wick's theorem, and the
+          integrals giving dD/dU and chi_F.                  [Sec. II C]
 exact     U=0 closed forms, brute-force HS enumeration and Fock-space exact
-          diagonalisation of the Trotterised partition function.
+          diagonalisation of the Trotterised partition function (also its
+          time-displaced interaction correlator on small clusters).
 stats     binning errors and integrated autocorrelation time.
 philox    Philox4x32-10 counter-based generator (Salmon et al., SC'11),
           implemented from its published definition.

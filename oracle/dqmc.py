@@ -88,6 +88,36 @@ class Model:
         self.Ehm = hermitian_expm(self.K, +self.dtau / 2).astype(dt)  # exp(+dtau K/2)
         self.dtype = dt
 
+    @classmethod
+    def from_hopping(cls, K, U, beta, dtau, n_stab=1, channel="spin"):
+        """A model on an arbitrary small bipartite cluster given by its
+        hopping matrix K (sites ordered sublattice A first); only the
+        propagators, weights and Green's functions are defined (no lattice)."""
+        M = beta / dtau
+        if abs(M - round(M)) > 1e-9:
+            raise ValueError("beta/dtau must be an integer")
+        if channel not in CHANNELS:
+            raise ValueError("channel must be 'spin' or 'charge'")
+        m = cls.__new__(cls)
+        m.lat = None
+        m.K = np.array(K)
+        m.N = m.K.shape[0]
+        m.L, m.Nc = None, m.N // 2
+        m.U, m.beta, m.dtau = float(U), float(beta), float(dtau)
+        m.M = int(round(M))
+        m.n_stab = int(n_stab)
+        m.channel = channel
+        m.lam = hs_lambda(U, dtau)
+        m.alpha = hs_alpha(U, dtau)
+        m.complex = np.iscomplexobj(m.K) or channel == "charge"
+        dt = complex if m.complex else float
+        m.Ep = hermitian_expm(m.K, -m.dtau).astype(dt)
+        m.Em = hermitian_expm(m.K, +m.dtau).astype(dt)
+        m.Ehp = hermitian_expm(m.K, -m.dtau / 2).astype(dt)
+        m.Ehm = hermitian_expm(m.K, +m.dtau / 2).astype(dt)
+        m.dtype = dt
+        return m
+
     # ---- propagators ----------------------------------------------------------
     def vdiag(self, spin, x):
         """Diagonal of exp(H_I^sigma(x)): exp(s_sigma lambda x) (spin channel)

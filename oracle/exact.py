@@ -285,5 +285,125 @@ def exact_trotter(model):
             "N2": (tr(Ntot * Ntot) / Z).real, "Ntot": (tr(Ntot) / Z).real, "rho": rho}
 
 
+# ---- time-displaced references (Sec. II C, eqs. DouOccDerive, fidelitysusp) -----------
+def fock_annihilators(n_modes):
+    """Jordan-Wigner annihilation operators of n_modes fermion modes (bit k of
+    a basis index = occupation of mode k)."""
+    dim = 1 << n_modes
+    ops = []
+    for k in range(n_modes):
+        c = np.zeros((dim, dim))
+        for a in range(dim):
+            if (a >> k) & 1:
+                c[a ^ (1 << k), a] = (-1) ** bin(a & ((1 << k) - 1)).count("1")
+        ops.append(c)
+    return ops
+
+
+def exact_tau_fock(K, U, dtau, M):
+    """Full Fock-space evaluation (both spins, 4^N states; N <= 4) of the
+    Trotterised ensemble Tr[T^M], T = exp(-dtau H_U) exp(-dtau H_0),
+    H_0 = sum_sigma sum_ij K_ij c^+_i c_j, H_U = U sum_i (n_up n_dn - (n_up + n_dn)/2):
+    <A(tau_l) A(0)> = Tr[T^{M-l} A T^l A] / Z for l = 0..M, <A>, the double
+    occupancy D and <N>; A = sum_i (n_up,i - 1/2)(n_dn,i - 1/2)."""
+    K = np.asarray(K)
+    N = K.shape[0]
+    if N > 4:
+        raise ValueError("at most 4 sites")
+    c = fock_annihilators(2 * N)            # modes 0..N-1 spin up, N..2N-1 spin down
+    cd = [x.T for x in c]
+    n = [cd[k] @ c[k] for k in range(2 * N)]
+    H0 = sum(K[i, j] * (cd[i] @ c[j] + cd[N + i] @ c[N + j]) for i in range(N) for j in range(N))
+    nud = [n[i] @ n[N + i] for i in range(N)]
+    HU = U * sum(nud[i] - 0.5 * (n[i] + n[N + i]) for i in range(N))
+    A = sum((n[i] - 0.5 * np.eye(len(H0))) @ (n[N + i] - 0.5 * np.eye(len(H0))) for i in range(N))
+    w, V = np.linalg.eigh(H0)
+    E0 = (V * np.exp(-dtau * w)) @ V.conj().T
+    T = np.diag(np.exp(-dtau * np.diag(HU))) @ E0
+    Tp = [np.eye(len(T))]
+    for _ in range(M):
+        Tp.append(Tp[-1] @ T)
+    Z = np.trace(Tp[M])
+    AA = np.array([np.trace(Tp[M - l] @ A @ Tp[l] @ A) / Z for l in range(M + 1)])
+    return {"Z": Z.real, "AA": AA.real, "A": (np.trace(A @ Tp[M]) / Z).real,
+            "D": (np.trace(sum(nud) @ Tp[M]) / Z).real / N,
+            "Ntot": (np.trace(sum(n) @ Tp[M]) / Z).real, "max_imag": float(np.max(np.abs(AA.imag)))}
+
+
+def exact_tau_trotter2(model):
+    """<A(tau_l) A(0)> for l = 0, 1 and <A> of an M = 2 model on the honeycomb
+    torus (N up to 8), with the Fock space as (spin-up state, spin-down state)
+    pairs: T = D_U o (E x E), so Tr[T X T Y] = sum P[a,c] (D_U X)[a,b] P[b,d]
+    (D_U Y)[c,d] with P = E o E^T for diagonal X, Y."""
+    if model.M != 2:
+        raise ValueError("M = 2 only")
+    N = model.N
+    dim = 1 << N
+    H = fock_hopping(model.K)
+    w, V = np.linalg.eigh(H)
+    E = (V * np.exp(-model.dtau * w)) @ V.conj().T
+    occ = np.array([[(a >> i) & 1 for i in range(N)] for a in range(dim)], dtype=float)
+    nn = occ @ occ.T
+    ntot = occ.sum(axis=1)
+    Dm = np.exp(-model.dtau * model.U * (nn - (ntot[:, None] + ntot[None, :]) / 2.0))
+    mm = occ - 0.5
+    A = mm @ mm.T                                     # sum_i m_up,i(a) m_dn,i(b)
+    P = E * E.T
+
+    def tr2(X, Y):
+        return np.sum(P * ((Dm * X) @ P @ (Dm * Y).T))
+
+    one = np.ones((dim, dim))
+    Z = tr2(one, one)
+    return {"Z": Z.real, "AA": np.array([(tr2(A * A, one) / Z).real, (tr2(A, A) / Z).real]),
+            "A": (tr2(A, one) / Z).real}
+
+
+def brute_force_tau(model, lmax, batch=2048):
+    """Exact weighted averages over every HS configuration of the oracle's
+    per-configuration <A(tau_l) A(0)>_X (l = 0..lmax) and <A>_X, with
+    W = P(X) det O_up det O_dn (eq. ConfgWeight)."""
+    from .tau import tau_correlator
+    M, N = model.M, model.N
+    nf = M * N
+    if nf > 24:
+        raise ValueError("too many fields for brute force")
+    Z = 0.0
+    aa = np.zeros(lmax + 1, dtype=complex)
+    a1 = 0.0 + 0.0j
+    wmin = np.inf
+    allcfg = np.array(list(itertools.product((1, -1), repeat=nf)), dtype=float).reshape(-1, M, N)
+    for s0 in range(0, len(allcfg), batch):
+        X = allcfg[s0:s0 + batch]
+        W = np.exp(np.array([model.log_prior(x) for x in X]))
+        for spin in (0, 1):
+            P = np.broadcast_to(np.eye(N, dtype=complex), (len(X), N, N)).copy()
+            for l in range(M):
+                P = model.vdiag(spin, X[:, l, :])[:, :, None] * (model.Ep[None] @ P)
+            W = W * np.linalg.det(np.eye(N)[None] + P)
+        AA, A1 = tau_correlator(model, X, lmax)
+        wmin = min(wmin, float(np.min(W.real)))
+        Z += W.sum().real
+        aa += W @ AA
+        a1 += W @ A1
+    return {"Z": Z, "AA": (aa / Z).real, "A": (a1 / Z).real, "AA_imag": float(np.max(np.abs((aa / Z).imag))),
+            "wmin": wmin}
+
+
+def dimer_hopping(t=1.0):
+    """Two sites (A, B) joined by one bond."""
+    return np.array([[0.0, -t], [-t, 0.0]])
+
+
+def ring4_hopping(t=1.0, phi=0.0):
+    """Four sites on a ring (A = 0, 1; B = 2, 3; bonds 0-2, 2-1, 1-3, 3-0),
+    each bond with the Peierls phase phi (a flux 4 phi through the ring)."""
+    K = np.zeros((4, 4), dtype=complex)
+    for a, b in ((0, 2), (2, 1), (1, 3), (3, 0)):
+        K[a, b] += -t * np.exp(1j * phi)
+        K[b, a] += -t * np.exp(-1j * phi)
+    return K if phi != 0.0 else K.real.copy()
+
+
 def tiny_model(U=3.8, dtau=0.25, M=2, theta1=0.0, theta2=0.0, L=2, channel="spin"):
     return Model(L, U, M * dtau, dtau, theta1=theta1, theta2=theta2, n_stab=max(1, M), channel=channel)
