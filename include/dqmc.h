@@ -259,8 +259,51 @@ dqmc_status dqmc_set_measure_k(dqmc_handle h, int32_t on);
  * DQMC_ESTATE if nothing was measured.  Synchronises. */
 dqmc_status dqmc_get_nk(dqmc_handle h, int32_t inst, int32_t raw, double* host_out);
 
-/* Restart the estimator means and the counters of dqmc_stats (proposals,
- * accepted, flushes, drifts, learned moves) and clear numeric_err. */
+/* ---- time-displaced estimators (Sec. II C, eqs. DouOccDerive, fidelitysusp) ----
+ * One pass over the current configuration of every instance that stands at
+ * the start of a sweep (right after creation or after whole sweeps of the
+ * handle; others are skipped): G(tau,tau), G(tau,0) = <c(tau) c^dagger(0)> and
+ * G(0,tau) = -<c^dagger(tau) c(0)> of spin up for tau_l = l dtau,
+ * l = 0 .. min(M/2, l_max) (l_max < 0: M/2), propagated slice by slice with
+ * the wraps and recomputed every n_stab slices from the UDV chain and the
+ * stack of the last downward pass (G(tau,0) = [B(tau,0)^{-1} + B(beta,tau)]^{-1},
+ * G(0,tau) = -[B(tau,0) + B(beta,tau)^{-1}]^{-1}, with the scale split of the
+ * equal-time recomputation; their drift enters dqmc_stats and the drift
+ * tolerance).  At every slice the Wick estimator of
+ *   <A(tau_l) A(0)>,  A = sum_i (n_up,i - 1/2)(n_dn,i - 1/2) = H_I + N_s/4
+ * (H_I of the correlator C_{H_I}(tau)) is accumulated, the spin-down
+ * functions being the particle-hole partners (spin channel) or equal to
+ * spin up (charge channel).  Fields, G, the stack and the sweep schedule are
+ * left unchanged.  Asynchronous on stream (NULL: the handle's stream);
+ * DQMC_EHIP on a launch failure. */
+dqmc_status dqmc_measure_tau(dqmc_handle h, int32_t l_max, void* stream);
+/* Means over the passes of instance inst since creation or dqmc_reset_obs:
+ * host_aa[l] = <A(tau_l) A(0)> for l = 0 .. M/2 (M/2 + 1 doubles; slices a
+ * pass did not reach count as 0), *host_a = <A> (equal time), *n_pass; the
+ * connected C_{H_I}(tau_l) is host_aa[l] - (*host_a)^2.  Synchronises;
+ * DQMC_ENUMERIC (outputs still filled) after a numerical error. */
+dqmc_status dqmc_get_tau(dqmc_handle h, int32_t inst, double* host_aa, double* host_a, int64_t* n_pass);
+/* The same values per pass, oldest first: the last min(passes, 1024,
+ * max_rows) passes of instance inst, M/2 + 2 doubles each (<A(tau_l) A(0)>
+ * for l = 0 .. M/2, then <A>); *n_rows receives the count.  Synchronises. */
+dqmc_status dqmc_get_tau_rows(dqmc_handle h, int32_t inst, double* host_rows, int32_t max_rows, int32_t* n_rows);
+/* Spin-up G(tau,tau) (which 0), G(tau,0) (1) or G(0,tau) (2) of instance inst
+ * at the last slice of the last pass, N x N row-major, elements as in
+ * dqmc_get_green.  Synchronises. */
+dqmc_status dqmc_get_green_tau(dqmc_handle h, int32_t inst, int32_t which, double* host_out);
+/* dD/dU = -(2/N_s) int_0^{beta/2} C dtau (eq. DouOccDerive) and
+ * chi_F = int_0^{beta/2} tau C dtau (eq. fidelitysusp) from host_c[l] =
+ * C_{H_I}(l dtau), l = 0 .. n-1 (the last point at beta/2).  degree < 0:
+ * trapezoid rule on the slice grid, which for the Trotterised partition
+ * function is exactly its derivative in U; degree >= 0: least-squares
+ * polynomial of that degree (< n, <= 12) integrated analytically, as the
+ * paper evaluates them.  Host arithmetic only; DQMC_EINVAL on bad sizes. */
+dqmc_status dqmc_tau_integrals(const double* host_c, int32_t n, double dtau, int32_t n_sites, int32_t degree,
+                               double* dD_dU, double* chi_F);
+
+/* Restart the estimator means (also the time-displaced ones) and the
+ * counters of dqmc_stats (proposals, accepted, flushes, drifts, learned
+ * moves) and clear numeric_err. */
 dqmc_status dqmc_reset_obs(dqmc_handle h);
 /* Per-sweep means of the estimators in the order of dqmc_obs up to chi_e
  * (11 doubles per sweep), most recent max_sweeps at most, oldest first;

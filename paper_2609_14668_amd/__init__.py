@@ -78,6 +78,12 @@ _SIGS = {
     "dqmc_set_update_scheme": [_P, ctypes.c_int32],
     "dqmc_get_nk": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "dqmc_measure_tau": [_P, ctypes.c_int32, _P],
+    "dqmc_get_tau": [_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "dqmc_get_tau_rows": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "dqmc_get_green_tau": [_P, ctypes.c_int32, ctypes.c_int32, _P],
+    "dqmc_tau_integrals": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "dqmc_get_stats": [_P, ctypes.c_int32, ctypes.POINTER(Stats)],
     "dqmc_set_drift_tol": [_P, ctypes.c_double],
     "dqmc_shape": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -148,6 +154,22 @@ def dqmc_workspace_size(descs):
     if st != DQMC_OK:
         raise DqmcError(st, "workspace_size")
     return out.value
+
+
+def dqmc_tau_integrals(c, dtau, n_sites, degree=-1):
+    """(dD/dU, chi_F) from C_{H_I}(l dtau), l = 0 .. n-1 (last point beta/2):
+    degree < 0 trapezoid rule, else the integrated least-squares polynomial."""
+    lib = load()
+    buf = np.ascontiguousarray(c, dtype=np.float64)
+    d, x = ctypes.c_double(), ctypes.c_double()
+    st = lib.dqmc_tau_integrals(buf.ctypes.data, len(buf), float(dtau), int(n_sites), int(degree),
+                                ctypes.byref(d), ctypes.byref(x))
+    if st != DQMC_OK:
+        raise DqmcError(st, "tau_integrals")
+    return d.value, x.value
+
+
+tau_integrals = dqmc_tau_integrals
 
 
 class Simulation:
@@ -322,6 +344,38 @@ class Simulation:
         return {f: out[:n.value, k].copy() for k, f in enumerate(SERIES_FIELDS)}
 
     series = dqmc_get_series
+
+    def dqmc_measure_tau(self, l_max=-1):
+        self._chk(self.lib.dqmc_measure_tau(self.h, int(l_max), None), "measure_tau")
+
+    measure_tau = dqmc_measure_tau
+
+    def dqmc_get_tau(self, inst=0):
+        """(<A(tau_l) A(0)> for l = 0..M/2, <A>, number of passes)."""
+        M = self.shapes[inst][1]
+        aa = np.zeros(M // 2 + 1, dtype=np.float64)
+        a, n = ctypes.c_double(), ctypes.c_int64()
+        self._chk(self.lib.dqmc_get_tau(self.h, inst, aa.ctypes.data, ctypes.byref(a), ctypes.byref(n)), "get_tau")
+        return aa, a.value, n.value
+
+    get_tau = dqmc_get_tau
+
+    def dqmc_get_tau_rows(self, inst=0, max_rows=1024):
+        M = self.shapes[inst][1]
+        out = np.zeros((max_rows, M // 2 + 2), dtype=np.float64)
+        n = ctypes.c_int32()
+        self._chk(self.lib.dqmc_get_tau_rows(self.h, inst, out.ctypes.data, max_rows, ctypes.byref(n)), "tau_rows")
+        return out[:n.value].copy()
+
+    tau_rows = dqmc_get_tau_rows
+
+    def dqmc_get_green_tau(self, inst=0, which=1):
+        N, _, cx = self.shapes[inst]
+        out = np.empty((N, N, 2) if cx else (N, N), dtype=np.float64)
+        self._chk(self.lib.dqmc_get_green_tau(self.h, inst, which, out.ctypes.data), "get_green_tau")
+        return out[..., 0] + 1j * out[..., 1] if cx else out
+
+    green_tau = dqmc_get_green_tau
 
     def dqmc_get_stats(self, inst=0, check=False):
         """Counters of one instance.  DQMC_ENUMERIC still fills them: it is

@@ -113,6 +113,9 @@ enum MatId : int {
   MAT_W3,        // scratch
   MAT_SU,        // stack slot U (resolved from the checkpoint index)
   MAT_ST,        // stack slot T (resolved from the checkpoint index)
+  MAT_GTT,       // time-displaced pass: G(tau, tau)
+  MAT_GT0,       // time-displaced pass: G(tau, 0)
+  MAT_G0T,       // time-displaced pass: G(0, tau)
   MAT_COUNT,
   // roles in G = (1 + R L)^{-1}: R = U_R D_R T_R, L^dagger = U_L D_L T_L.
   // Upward pass: R is the working chain, L the stack slot; downward: swapped.
@@ -159,6 +162,9 @@ struct InstState {
   // this is: next ticket and finished workgroups per queue (reset to zero by
   // the last workgroup of each queue)
   int32_t fq_next[8], fq_done[8];
+  // time-displaced pass: 1 while the instance takes part, the last slice it
+  // measures (tau_lmax dtau), and its idle flag before the pass
+  int32_t tau_active, tau_lmax, tau_saved_idle, pad1;
 };
 // numeric_err bits
 constexpr int NUMERR_RATIO = 1;    // non-finite or zero acceptance ratio
@@ -232,6 +238,13 @@ struct InstDev {
   double* series;           // per-sweep means [max_series x OBS_COUNT]
   double* nk_sum;           // momentum distribution sums: Nc x 8 (AA, AB, BA, BB as re, im)
   int32_t max_series;
+  // time-displaced estimators: tau_sum[l] (l = 0 .. M/2) sums of
+  // <A(tau_l) A(0)>_X over passes, tau_sum[M/2 + 1] the sum of <A>_X,
+  // tau_sum[M/2 + 2] the number of passes; tau_rows holds the same values per
+  // pass (row stride M/2 + 2, tau_cap rows, the oldest overwritten)
+  double* tau_sum;
+  double* tau_rows;
+  int32_t tau_cap;
   const uint8_t* replay_bits;  // nullable
   double* replay_ratio;        // nullable
   int64_t replay_len;

@@ -31,6 +31,7 @@ constexpr int QR_NB = 16;
 constexpr int TRSM_ROWS = 32;
 constexpr int GROUPS_MAX = 4;   // instance groups on separate streams
 constexpr int MAX_SERIES = 4096;
+constexpr int TAU_ROWS = 1024;     // per-pass rows kept of the time-displaced estimators
 constexpr int MAX_DELAY = 192;
 constexpr int FLUSH_KERNELS = 3;   // direct, LDS-tiled, work queue
 // Default tolerance of max |G_wrap - G_scratch| at a recomputation.  FP64
@@ -57,6 +58,7 @@ bool is_twisted(const dqmc_instance_desc& d) {
 
 struct Offs {
   size_t st, obs, series, nk, fields, tab, roots, factors, perm, acc, gsite, wcoef, targets, learn, rsplit;
+  size_t tau_sum, tau_rows;
   size_t vec[VEC_COUNT];
   size_t mat[MAT_COUNT];
   size_t stackU, stackT, stackD, stackPh;
@@ -121,6 +123,8 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.obs = o; o = al(o + sizeof(double) * (2 * OBS_COUNT + 1));
     f.series = o; o = al(o + sizeof(double) * OBS_COUNT * MAX_SERIES);
     f.nk = o; o = al(o + sizeof(double) * 8 * Nc);
+    f.tau_sum = o; o = al(o + sizeof(double) * (M / 2 + 3));
+    f.tau_rows = o; o = al(o + sizeof(double) * (size_t)TAU_ROWS * (M / 2 + 2));
     f.fields = o; o = al(o + (size_t)M * N);
     f.tab = o; o = al(o + sizeof(cplx) * 16 * Nc);
     f.roots = o; o = al(o + sizeof(cplx) * 64);
@@ -449,24 +453,32 @@ void lower_solve(Ctx& c, int r0, int r1, int col0, int col1, int target) {
   lower_solve(c, rm, r1, col0, col1, target);
 }
 
-// One checkpoint: advance the working UDV chain by n_stab slices, recompute
-// G against the stack partner, record the drift, replace G, store the chain.
-void stabilise(Ctx& c, bool measure) {
+// Advance the working UDV chain by n_stab slices: A = B_chunk U D (the
+// n_stab B's in one pass over U, columns scaled by D), pre-pivoted QR,
+// U' = Q, D' = |diag R|, T' = D'^{-1} R P^T T; with phase = true the phase of
+// det Q is recorded for the stack.
+void chain_step(Ctx& c, bool phase) {
   dqmc_ctx* h = c.h;
   c.elem(EO_RESET_CHAIN);
-  // A = B_chunk U D: the n_stab B's in one pass over U, columns scaled by D
   c.fft(FOP_STAB_CHAIN, 0, MAT_UW);
   c.chk(launch_colnorm_sort(c.di, c.n, h->Nmax, h->cplx, MAT_UW, c.s));
   c.elem(EO_GATHER_COLS, MAT_UW, 0, MAT_QA);
   c.elem(EO_GATHER_ROWS, MAT_TW, 0, MAT_W3);
   qr_factor(c);
-  c.chk(launch_detphase(c.di, c.n, h->cplx, 0, c.s));
+  if (phase) c.chk(launch_detphase(c.di, c.n, h->cplx, 0, c.s));
   c.chk(launch_diag_abs(c.di, c.n, h->Nmax, h->cplx, c.s));
   c.gemm(opnd(MAT_QA, 0), opnd(MAT_W3, 0), opnd(MAT_TW, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0,
          GF_A_UPPER);
   c.elem(EO_SCALE_ROWS_INV, 0, 0, MAT_TW, VEC_DW);
   c.elem(EO_IDENTITY, 0, 0, MAT_UW);
   apply_q(c, MAT_UW);
+}
+
+// One checkpoint: advance the working UDV chain by n_stab slices, recompute
+// G against the stack partner, record the drift, replace G, store the chain.
+void stabilise(Ctx& c, bool measure) {
+  dqmc_ctx* h = c.h;
+  chain_step(c, true);
   // G = U_L D_Lb^-1 Y^-1 D_Rb^-1 U_R^H
   c.gemm(opnd(MAT_RU, 2), opnd(MAT_LU, 0), opnd(MAT_W1, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
   c.gemm(opnd(MAT_RT, 0), opnd(MAT_LT, 2), opnd(MAT_W2, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
@@ -511,6 +523,67 @@ void stabilise(Ctx& c, bool measure) {
       c.chk(launch_measure_k(c.di, c.n, h->Nmax, h->cplx, MAT_GS, c.s));
     }
   }
+}
+
+// Checkpoint of the time-displaced pass at tau = c n_stab dtau (Sec. II C):
+// with R = B(tau, 0) = U_R D_R T_R (the working chain) and
+// L^dagger = B(beta, tau)^dagger = U_L D_L T_L (the stack slot of the last
+// downward pass), the three functions share the Y of the equal-time
+// recomputation:
+//   G(tau,tau) = U_L D_Lb^{-1} Y^{-1} D_Rb^{-1} U_R^H
+//   G(0,tau)   = -T_L^H D_Ls Y^{-1} D_Rb^{-1} U_R^H      (= -[B(tau,0) + B(beta,tau)^{-1}]^{-1})
+//   G(tau,0)   = U_L D_Lb^{-1} Y^{-1} D_Rs T_R            (= [B(tau,0)^{-1} + B(beta,tau)]^{-1})
+// so one LU of Y serves two right-hand sides.  The propagated functions are
+// compared with these (drift) and replaced; the stack is not written.
+void stabilise_tau(Ctx& c) {
+  dqmc_ctx* h = c.h;
+  chain_step(c, false);
+  c.gemm(opnd(MAT_RU, 2), opnd(MAT_LU, 0), opnd(MAT_W1, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.gemm(opnd(MAT_RT, 0), opnd(MAT_LT, 2), opnd(MAT_W2, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.elem(EO_BUILD_Y, MAT_W1, MAT_W2, MAT_QA);
+  lu_factor(c, 0, h->Nmax);
+  // W3 = D_Lb^{-1} Y^{-1} D_Rb^{-1} U_R^H
+  c.elem(EO_BUILD_RHS, 0, 0, MAT_W3, 1);
+  lower_solve(c, 0, h->Nmax, 0, h->Nmax, MAT_W3);
+  upper_solve(c);
+  c.elem(EO_SCALE_ROWS_DLB, 0, 0, MAT_W3);
+  c.gemm(opnd(MAT_LU, 0), opnd(MAT_W3, 0), opnd(MAT_GS, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.elem(EO_SCALE_ROWS_DL, 0, 0, MAT_W3);   // D_Ls Y^{-1} D_Rb^{-1} U_R^H
+  c.gemm(opnd(MAT_LT, 2), opnd(MAT_W3, 0), opnd(MAT_W1, 0), dim(1, 0), dim(1, 0), dim(1, 0), -1.0, 0.0);
+  // W3 = D_Lb^{-1} Y^{-1} D_Rs T_R
+  c.elem(EO_BUILD_RHS_T, 0, 0, MAT_W3);
+  lower_solve(c, 0, h->Nmax, 0, h->Nmax, MAT_W3);
+  upper_solve(c);
+  c.elem(EO_SCALE_ROWS_DLB, 0, 0, MAT_W3);
+  c.gemm(opnd(MAT_LU, 0), opnd(MAT_W3, 0), opnd(MAT_W2, 0), dim(1, 0), dim(1, 0), dim(1, 0), 1.0, 0.0);
+  c.elem(EO_TAU_REPLACE);
+  c.chk(launch_stab_finish(c.di, c.n, c.s));
+}
+
+// Time-displaced pass over the current configuration of every instance at
+// the start of a sweep: G(tau,tau), G(tau,0), G(0,tau) for tau_l = l dtau,
+// l = 0 .. min(M/2, lmax_req), propagated slice by slice (both sides, the
+// left side, the right side of the upward wrap) and recomputed at every
+// n_stab-th slice; the estimator of every slice is accumulated.  The fields,
+// G, the stack and the schedule state are left as they were.
+hipError_t tau_pass(dqmc_ctx* h, int lmax_req, hipStream_t s) {
+  Ctx c{h, s, h->dinst, h->n, 0};
+  int lmax = 0;
+  for (auto& d : h->hd) lmax = std::max(lmax, lmax_req < 0 ? d.M / 2 : std::min(d.M / 2, lmax_req));
+  c.chk(launch_tau_state(c.di, c.n, 0, 0, lmax_req, s));
+  c.elem(EO_TAU_INIT);
+  c.chk(launch_measure_tau(c.di, c.n, h->Nmax, h->cplx, 0, s));
+  for (int l = 1; l <= lmax && c.e == hipSuccess; ++l) {
+    c.chk(launch_tau_state(c.di, c.n, 1, l, lmax_req, s));
+    c.fft(FOP_WRAP_PRE, 0, MAT_GTT);
+    c.fft(FOP_WRAP_PRE, 1, MAT_GTT);
+    c.fft(FOP_WRAP_PRE, 0, MAT_GT0);
+    c.fft(FOP_WRAP_PRE, 1, MAT_G0T);
+    if (l % h->n_stab == 0) stabilise_tau(c);
+    c.chk(launch_measure_tau(c.di, c.n, h->Nmax, h->cplx, l, s));
+  }
+  c.chk(launch_tau_state(c.di, c.n, 2, 0, lmax_req, s));
+  return c.e;
 }
 
 // One step of every instance (one slice of its sweep).
@@ -856,6 +929,9 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
     dv.series = (double*)(b + f.series);
     dv.nk_sum = (double*)(b + f.nk);
     dv.max_series = MAX_SERIES;
+    dv.tau_sum = (double*)(b + f.tau_sum);
+    dv.tau_rows = (double*)(b + f.tau_rows);
+    dv.tau_cap = TAU_ROWS;
     h->hd.push_back(dv);
 
     // momentum tables at k = ((l1 + Theta1/2pi)/L) b1 + ((l2 + Theta2/2pi)/L) b2 (eq. kpoints)
@@ -892,6 +968,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
         (e = hipMemsetAsync(b + f.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.series, 0, sizeof(double) * OBS_COUNT * MAX_SERIES, s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.nk, 0, sizeof(double) * 8 * Nc, s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.tau_sum, 0, sizeof(double) * (dv.M / 2 + 3), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.targets, 0, sizeof(float) * (size_t)dv.M * dv.N, s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.learn, 0, sizeof(LearnState), s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
@@ -1374,6 +1451,7 @@ dqmc_status dqmc_reset_obs(dqmc_handle h) {
   for (auto& d : h->hd) {
     HIPCHK(h, hipMemsetAsync(d.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), h->stream));
     HIPCHK(h, hipMemsetAsync(d.nk_sum, 0, sizeof(double) * 8 * d.Nc, h->stream));
+    HIPCHK(h, hipMemsetAsync(d.tau_sum, 0, sizeof(double) * (d.M / 2 + 3), h->stream));
   }
   Ctx c{h, h->stream, h->dinst, h->n, 0};
   c.chk(launch_reset_counters(h->dinst, h->n, h->stream));
@@ -1401,6 +1479,123 @@ dqmc_status dqmc_get_series(dqmc_handle h, int32_t inst, double* host_out, int32
     o[8] = row[OBS_PHASE_RE]; o[9] = row[OBS_PHASE_IM]; o[10] = row[OBS_CHI];
   }
   *n_out = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_measure_tau(dqmc_handle h, int32_t l_max, void* stream) {
+  if (!h) return DQMC_EINVAL;
+  hipError_t e = tau_pass(h, l_max, pick(h, stream));
+  if (e != hipSuccess) return fail(h, DQMC_EHIP, std::string("time-displaced pass: ") + hipGetErrorString(e));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_tau(dqmc_handle h, int32_t inst, double* host_aa, double* host_a, int64_t* n_pass) {
+  if (!h || inst < 0 || inst >= h->n || !host_aa || !host_a || !n_pass) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  const int lc = d.M / 2;
+  std::vector<double> sum(lc + 3);
+  InstState st;
+  HIPCHK(h, hipMemcpyAsync(sum.data(), d.tau_sum, sizeof(double) * sum.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&st, d.st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const double n = sum[lc + 2];
+  *n_pass = (int64_t)n;
+  for (int l = 0; l <= lc; ++l) host_aa[l] = n > 0 ? sum[l] / n : 0.0;
+  *host_a = n > 0 ? sum[lc + 1] / n : 0.0;
+  if (st.numeric_err) return fail(h, DQMC_ENUMERIC, numeric_message(st.numeric_err));
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_tau_rows(dqmc_handle h, int32_t inst, double* host_rows, int32_t max_rows, int32_t* n_rows) {
+  if (!h || inst < 0 || inst >= h->n || !host_rows || !n_rows || max_rows < 0) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  const int lc = d.M / 2, stride = lc + 2;
+  double n = 0;
+  std::vector<double> rows((size_t)TAU_ROWS * stride);
+  HIPCHK(h, hipMemcpyAsync(&n, d.tau_sum + lc + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(rows.data(), d.tau_rows, sizeof(double) * rows.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const int64_t have = std::min<int64_t>((int64_t)n, TAU_ROWS);
+  const int64_t cnt = std::min<int64_t>(have, max_rows);
+  for (int64_t q = 0; q < cnt; ++q) {
+    const int64_t pass = (int64_t)n - cnt + q;
+    std::memcpy(host_rows + q * stride, &rows[(size_t)(pass % TAU_ROWS) * stride], sizeof(double) * stride);
+  }
+  *n_rows = (int32_t)cnt;
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_get_green_tau(dqmc_handle h, int32_t inst, int32_t which, double* host_out) {
+  if (!h || inst < 0 || inst >= h->n || !host_out || which < 0 || which > 2) return DQMC_EINVAL;
+  const InstDev& d = h->hd[inst];
+  const int N = d.N;
+  const int w = h->cplx ? 2 : 1;
+  const int mat = which == 0 ? MAT_GTT : (which == 1 ? MAT_GT0 : MAT_G0T);
+  std::vector<double> g((size_t)N * N * w);
+  HIPCHK(h, hipMemcpyAsync(g.data(), d.mat[mat], sizeof(double) * g.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      for (int c = 0; c < w; ++c) host_out[((size_t)i * N + j) * w + c] = g[((size_t)j * N + i) * w + c];
+  return DQMC_OK;
+}
+
+dqmc_status dqmc_tau_integrals(const double* host_c, int32_t n, double dtau, int32_t n_sites, int32_t degree,
+                               double* dD_dU, double* chi_F) {
+  if (!host_c || n < 2 || !(dtau > 0) || n_sites < 1 || !dD_dU || !chi_F || degree > 12 ||
+      (degree >= 0 && degree >= n))
+    return DQMC_EINVAL;
+  const double b = dtau * (n - 1);
+  double i0 = 0, i1 = 0;
+  if (degree < 0) {
+    for (int l = 0; l < n; ++l) {
+      const double w = (l == 0 || l == n - 1) ? 0.5 * dtau : dtau;
+      i0 += w * host_c[l];
+      i1 += w * (dtau * l) * host_c[l];
+    }
+  } else {
+    // least squares C(tau) = sum_k a_k x^k, x = tau / b, by Householder QR of
+    // the n x (degree + 1) Vandermonde matrix
+    const int p = degree + 1;
+    std::vector<double> A((size_t)n * p), r(host_c, host_c + n);
+    for (int l = 0; l < n; ++l) {
+      double x = (double)l / (n - 1), v = 1.0;
+      for (int k = 0; k < p; ++k, v *= x) A[(size_t)k * n + l] = v;
+    }
+    for (int k = 0; k < p; ++k) {
+      double* col = &A[(size_t)k * n];
+      double nrm = 0;
+      for (int l = k; l < n; ++l) nrm += col[l] * col[l];
+      nrm = std::sqrt(nrm);
+      if (nrm == 0) return DQMC_EINVAL;
+      const double alpha = col[k] > 0 ? -nrm : nrm;
+      col[k] -= alpha;   // v = x - alpha e_k, H = 1 - 2 v v^T / (v^T v)
+      double vv = 0;
+      for (int l = k; l < n; ++l) vv += col[l] * col[l];
+      for (int q = k + 1; q < p; ++q) {
+        double* cq = &A[(size_t)q * n];
+        double dot = 0;
+        for (int l = k; l < n; ++l) dot += col[l] * cq[l];
+        for (int l = k; l < n; ++l) cq[l] -= 2.0 * dot / vv * col[l];
+      }
+      double dot = 0;
+      for (int l = k; l < n; ++l) dot += col[l] * r[l];
+      for (int l = k; l < n; ++l) r[l] -= 2.0 * dot / vv * col[l];
+      col[k] = alpha;   // R_kk (the rest of the column below is no longer needed)
+    }
+    std::vector<double> a(p);
+    for (int k = p - 1; k >= 0; --k) {
+      double v = r[k];
+      for (int q = k + 1; q < p; ++q) v -= A[(size_t)q * n + k] * a[q];
+      a[k] = v / A[(size_t)k * n + k];
+    }
+    for (int k = 0; k < p; ++k) {
+      i0 += b * a[k] / (k + 1);
+      i1 += b * b * a[k] / (k + 2);
+    }
+  }
+  *dD_dU = -2.0 * i0 / n_sites;
+  *chi_F = i1;
   return DQMC_OK;
 }
 

@@ -103,6 +103,11 @@ enum ElemOp : int {
   EO_DRIFT_REPLACE,   // drift = max |G - GS|; G <- GS
   EO_RESET_CHAIN,     // working chain <- identity at the first checkpoint of a pass
   EO_SET_ONES,        // vec v <- 1
+  // time-displaced pass
+  EO_TAU_INIT,        // G(0,0), G(0,0), G(0,0) - 1 into MAT_GTT, MAT_GT0, MAT_G0T
+  EO_SCALE_ROWS_DL,   // c[i, :] *= D_L[i]
+  EO_BUILD_RHS_T,     // c = D_Rs T_R with rows in the LU's row order (row i from row perm[N + i])
+  EO_TAU_REPLACE,     // drift = max of |GTT - GS|, |GT0 - W2|, |G0T - W1|; then replaced by them
 };
 struct ElemArgs { int op, a, b, c, v; };
 hipError_t launch_elem(const InstDev* insts, int n_inst, int Nmax, bool cplx_, ElemArgs e, hipStream_t s);
@@ -136,6 +141,10 @@ hipError_t launch_diag_abs(const InstDev* insts, int n_inst, int Nmax, bool cplx
 hipError_t launch_trsm_diag(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int blk, hipStream_t s);
 hipError_t launch_measure(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
 // momentum distribution sums from the forward-transformed G in mat
+// time-displaced pass: instance state (mode 0 begin, 1 slice l, 2 end) and
+// the estimator of slice l from MAT_GTT, MAT_GT0, MAT_G0T and MAT_G
+hipError_t launch_tau_state(const InstDev* insts, int n_inst, int mode, int l, int lmax_req, hipStream_t s);
+hipError_t launch_measure_tau(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int l, hipStream_t s);
 hipError_t launch_measure_k(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s);
 
 // ---- proposal network (BF16 operands, FP32 accumulation) ---------------------------

@@ -217,7 +217,159 @@ __global__ void __launch_bounds__(MT) k_measure_k(const InstDev* __restrict__ in
     }
 }
 
+// ---- time-displaced pass (Sec. II C, eqs. DouOccDerive, fidelitysusp) ----------------
+// With A = sum_i m_up,i m_dn,i (m = n - 1/2; H_I = A - N_s/4) and, per spin,
+//   t_ij = a_i b_j - G(0,tau)_ji G(tau,0)_ij,  a_i = 1/2 - G(tau,tau)_ii,
+//   b_j = 1/2 - G(0,0)_jj,
+// Wick's theorem gives <A(tau) A(0)>_X = sum_ij t_ij^up t_ij^dn.  In the spin
+// channel the spin-down functions are the particle-hole partners
+// G_dn(tau,0) = -P G_up(0,tau)^dagger P, G_dn(0,tau) = -P G_up(tau,0)^dagger P,
+// G_dn(tau,tau) = P (1 - G_up(tau,tau)^dagger) P, so t^dn = conj(t^up) and the
+// sum is sum_ij |t_ij|^2; in the charge channel G_dn = G_up and it is
+// sum_ij t_ij^2 (real part: only the weighted average is real).  The
+// equal-time <A>_X = sum_i m_up,i m_dn,i is -sum_i |1/2 - G_ii|^2 (spin) or
+// Re sum_i (1/2 - G_ii)^2 (charge).
+
+// Instance state around a pass.  mode 0: instances at the start of a sweep
+// (phase 0) take part up to slice min(M/2, lmax_req) (lmax_req < 0: M/2); the
+// others are parked idle.  mode 1, slice l: a taking part instance whose last
+// slice is below l is parked, the others get the upward phase of slice l (so
+// that the chain steps, stack slots and wraps resolve to slice l).  mode 2:
+// phases back to 0, idle flags restored.
+__global__ void k_tau_state(const InstDev* __restrict__ insts, int mode, int l, int lmax_req) {
+  const InstDev& d = insts[blockIdx.y];
+  InstState* st = d.st;
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    const int ok = !st->idle && !st->init_mode && st->phase == 0;
+    st->tau_saved_idle = st->idle;
+    st->tau_active = ok;
+    st->tau_lmax = ok ? (lmax_req < 0 ? d.M / 2 : min(d.M / 2, lmax_req)) : -1;
+    if (!ok) st->idle = 1;
+  } else if (mode == 1) {
+    if (!st->tau_active) return;
+    if (l > st->tau_lmax) st->idle = 1;
+    else st->phase = l - 1;
+  } else {
+    if (st->tau_active) st->phase = 0;
+    st->idle = st->tau_saved_idle;
+    st->tau_active = 0;
+  }
+}
+
+// Partial sums of sum_ij term(t_ij) over one strip of PB rows i per
+// workgroup: G(tau,0)[i, j] and G(0,tau)[j, i] tiles both read down columns
+// into LDS; the partial goes to VEC_NORM[strip].
+template <typename S>
+__global__ void __launch_bounds__(MT) k_measure_tau_pairs(const InstDev* __restrict__ insts) {
+  const InstDev& d = insts[blockIdx.y];
+  const InstState* st = d.st;
+  if (st->idle || !st->tau_active) return;
+  const int N = d.N;
+  const int nb = (N + PB - 1) / PB;
+  if ((int)blockIdx.x >= nb) return;
+  const int I0 = blockIdx.x * PB;
+  const S* gt0 = matp<S>(d, MAT_GT0);
+  const S* g0t = matp<S>(d, MAT_G0T);
+  const S* gtt = matp<S>(d, MAT_GTT);
+  const S* g = matp<S>(d, MAT_G);
+  const bool charge = d.channel != 0;
+  __shared__ S At[PB][PB + 1], Bt[PB][PB + 1];
+  __shared__ S ai[PB], bj[PB];
+  __shared__ double red[4];
+  const S half = ST<S>::from_re(0.5);
+  if (threadIdx.x < PB) {
+    const int i = min(I0 + (int)threadIdx.x, N - 1);
+    ai[threadIdx.x] = half - gtt[i + (size_t)i * N];
+  }
+  const int r = threadIdx.x % PB, c0 = threadIdx.x / PB;   // 8 column groups
+  double acc = 0.0;
+  for (int J0 = 0; J0 < N; J0 += PB) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PB / 8; ++u) {
+      const int cc = c0 + 8 * u;
+      const int i = min(I0 + r, N - 1), j = min(J0 + cc, N - 1);
+      const int jr = min(J0 + r, N - 1), ic = min(I0 + cc, N - 1);
+      At[r][cc] = gld(gt0 + i + (size_t)j * N);    // G(tau,0)[I0 + r, J0 + cc]
+      Bt[r][cc] = gld(g0t + jr + (size_t)ic * N);  // G(0,tau)[J0 + r, I0 + cc]
+    }
+    if (threadIdx.x < PB) {
+      const int j = min(J0 + (int)threadIdx.x, N - 1);
+      bj[threadIdx.x] = half - g[j + (size_t)j * N];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PB / 8; ++u) {
+      const int a = r, b = c0 + 8 * u;
+      if (I0 + a < N && J0 + b < N) {
+        const S t = ai[a] * bj[b] - Bt[b][a] * At[a][b];
+        acc += charge ? real_part(t * t) : absq(t);
+      }
+    }
+  }
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) d.vec[VEC_NORM][blockIdx.x] = acc;
+}
+
+// Strip partials summed in strip order into slice l's sums and this pass's
+// row; at l = 0 also <A>_X; the pass count advances at the instance's last slice.
+template <typename S>
+__global__ void __launch_bounds__(MT) k_measure_tau_fin(const InstDev* __restrict__ insts, int l) {
+  const InstDev& d = insts[blockIdx.y];
+  InstState* st = d.st;
+  if (st->idle || !st->tau_active) return;
+  const int N = d.N;
+  const int nb = (N + PB - 1) / PB;
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int x = threadIdx.x; x < nb; x += MT) v += d.vec[VEC_NORM][x];
+  v = bsum(v, red);
+  double a1 = 0.0;
+  if (l == 0) {
+    const S* g = matp<S>(d, MAT_G);
+    const S half = ST<S>::from_re(0.5);
+    for (int i = threadIdx.x; i < N; i += MT) {
+      const S m = half - g[i + (size_t)i * N];
+      a1 += d.channel != 0 ? real_part(m * m) : -absq(m);
+    }
+    a1 = bsum(a1, red);
+  }
+  const int lc = d.M / 2, stride = lc + 2;
+  const int64_t pass = (int64_t)d.tau_sum[lc + 2];
+  double* row = d.tau_rows + (size_t)(pass % d.tau_cap) * stride;
+  if (l == 0)
+    for (int x = threadIdx.x + 1; x <= lc; x += MT) row[x] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d.tau_sum[l] += v;
+    row[l] = v;
+    if (l == 0) {
+      d.tau_sum[lc + 1] += a1;
+      row[lc + 1] = a1;
+    }
+    if (l == st->tau_lmax) d.tau_sum[lc + 2] += 1.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_tau_state(const InstDev* insts, int n_inst, int mode, int l, int lmax_req, hipStream_t s) {
+  hipLaunchKernelGGL(k_tau_state, dim3(1, n_inst), dim3(64), 0, s, insts, mode, l, lmax_req);
+  return hipGetLastError();
+}
+
+hipError_t launch_measure_tau(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int l, hipStream_t s) {
+  dim3 grid((Nmax + PB - 1) / PB, n_inst);
+  if (cplx_) {
+    hipLaunchKernelGGL(k_measure_tau_pairs<cplx>, grid, dim3(MT), 0, s, insts);
+    hipLaunchKernelGGL(k_measure_tau_fin<cplx>, dim3(1, n_inst), dim3(MT), 0, s, insts, l);
+  } else {
+    hipLaunchKernelGGL(k_measure_tau_pairs<double>, grid, dim3(MT), 0, s, insts);
+    hipLaunchKernelGGL(k_measure_tau_fin<double>, dim3(1, n_inst), dim3(MT), 0, s, insts, l);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_measure_k(const InstDev* insts, int n_inst, int Nmax, bool cplx_, int mat, hipStream_t s) {
   const int ncm = Nmax / 2;

@@ -177,6 +177,57 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
       for (size_t x = e0; x < (size_t)N; x += stride) v[x] = 1.0;
       break;
     }
+    case EO_TAU_INIT: {
+      if (!st->tau_active) break;
+      const S* g = matp<S>(d, MAT_G);
+      S* gtt = matp<S>(d, MAT_GTT);
+      S* gt0 = matp<S>(d, MAT_GT0);
+      S* g0t = matp<S>(d, MAT_G0T);
+      for (size_t x = e0; x < NN; x += stride) {
+        const S v = g[x];
+        gtt[x] = v;
+        gt0[x] = v;
+        g0t[x] = (x % N == x / N) ? v - ST<S>::one() : v;
+      }
+      break;
+    }
+    case EO_SCALE_ROWS_DL: {
+      S* c = matp<S>(d, e.c);
+      const double* v = vec_ptr(d, VEC_LD);
+      for (size_t x = e0; x < NN; x += stride) c[x] = c[x] * v[x % N];
+      break;
+    }
+    case EO_BUILD_RHS_T: {
+      const S* t = matp<S>(d, MAT_RT);
+      S* c = matp<S>(d, e.c);
+      const double* dr = vec_ptr(d, VEC_RD);
+      const int* rp = d.perm + N;
+      for (size_t x = e0; x < NN; x += stride) {
+        const size_t i = (size_t)rp[x % N], j = x / N;
+        c[x] = t[i + j * N] * fmin(dr[i], 1.0);
+      }
+      break;
+    }
+    case EO_TAU_REPLACE: {
+      S* gtt = matp<S>(d, MAT_GTT);
+      S* gt0 = matp<S>(d, MAT_GT0);
+      S* g0t = matp<S>(d, MAT_G0T);
+      const S* gs = matp<S>(d, MAT_GS);
+      const S* w2 = matp<S>(d, MAT_W2);
+      const S* w1 = matp<S>(d, MAT_W1);
+      double m = 0.0;
+      for (size_t x = e0; x < NN; x += stride) {
+        double a = fmax(absval(gtt[x] - gs[x]), fmax(absval(gt0[x] - w2[x]), absval(g0t[x] - w1[x])));
+        if (!(a == a)) a = INFINITY;
+        m = fmax(m, a);
+        gtt[x] = gs[x];
+        gt0[x] = w2[x];
+        g0t[x] = w1[x];
+      }
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+      if ((threadIdx.x & 63) == 0) atomic_max_pos(&st->drift_acc, m);
+      break;
+    }
     case EO_DRIFT_REPLACE: {
       S* g = matp<S>(d, MAT_G);
       const S* gs = matp<S>(d, MAT_GS);

@@ -63,3 +63,28 @@ def test_status_strings():
         pytest.skip("libdqmc.so not built")
     assert lib.dqmc_status_string(0) == b"ok"
     assert b"invalid" in lib.dqmc_status_string(-1)
+
+
+def test_tau_integrals_host_entry_point():
+    """dqmc_tau_integrals (host arithmetic only) against the oracle's
+    integrals: trapezoid and least-squares polynomial fits, and its argument
+    checks."""
+    p = pytest.importorskip("paper_2609_14668_amd")
+    try:
+        p.load()
+    except ImportError:
+        pytest.skip("libdqmc.so not built")
+    import numpy as np
+    from oracle import tau
+    rng = np.random.default_rng(4)
+    for n, dt in ((91, 0.1), (11, 0.2), (2, 0.05)):
+        t = dt * np.arange(n)
+        c = 0.3 * np.exp(-2.0 * t) + 0.05 + 0.01 * rng.standard_normal(n)
+        for deg in [None] + [k for k in (1, 3, 6, 9) if k < n]:
+            got = p.tau_integrals(c, dt, 648, -1 if deg is None else deg)
+            ref = tau.tau_integrals(c, dt, 648, deg)
+            np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-15)
+    for bad in ((np.ones(1), 0.1, 8, -1), (np.ones(5), 0.0, 8, -1), (np.ones(5), 0.1, 0, -1),
+                (np.ones(5), 0.1, 8, 5), (np.ones(20), 0.1, 8, 13)):
+        with pytest.raises(p.DqmcError):
+            p.tau_integrals(*bad)

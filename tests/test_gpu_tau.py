@@ -1,0 +1,181 @@
+"""The time-displaced pass (Sec. II C, eqs. DouOccDerive, fidelitysusp) on
+the GPU against the oracle on the same configuration: G(tau,tau), G(tau,0),
+G(0,tau) at chosen slices (before and after the recomputations), the series
+<A(tau_l) A(0)> and <A> of one pass, both HS channels, PBC and twisted, an
+uneven batch, a pass after sweeps (the stack of the last downward pass), and
+sampled checks at the full L = 18 shape.  A pass must leave the chain
+untouched: a sweep after it is bit-identical to one without it.
+
+Tolerances: the functions 1e-10 relative to their largest entry (at least 1;
+the charge channel's functions have entries far above 1), since wraps and
+recomputations agree with the oracle's block inverse to rounding amplified by
+the conditioning of n_stab slices, as for the equal-time G; the series 1e-10
+relative.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import tau
+from oracle.dqmc import Model
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(descs):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_14668_amd import Simulation
+    return Simulation(descs)
+
+
+def _model(d):
+    return Model(d["L"], d["U"], d["beta"], d["dtau"], t=d["t"], theta1=d["theta1"], theta2=d["theta2"],
+                 n_stab=d["n_stab"], channel="charge" if d.get("channel", 0) else "spin")
+
+
+CASES = [  # L, twist, beta, n_stab, channel
+    (3, (0.0, 0.0), 2.0, 5, 0),
+    (4, (0.7, 2.1), 2.0, 5, 0),
+    (4, (0.5, -1.2), 2.0, 5, 1),
+    (6, (0.0, 0.0), 2.0, 10, 0),
+]
+
+
+@pytest.mark.parametrize("L,th,beta,ns,ch", CASES)
+def test_tau_greens_match_oracle(L, th, beta, ns, ch):
+    d = workloads.desc(L, 3.8, beta, theta=th, n_stab=ns, channel=ch, seed=7)
+    sim = _sim([d])
+    m = _model(d)
+    f = sim.fields(0)
+    M = m.M
+    ref = tau.tau_greens(m, f, 0, M // 2)
+    for lstop in sorted(x for x in {1, ns - 1, ns, ns + 1, M // 2} if x <= M // 2):
+        print("case", L, th, ch, "slice", lstop, flush=True)
+        sim.measure_tau(lstop)
+        for which in range(3):
+            got = sim.green_tau(0, which)
+            scale = max(1.0, np.abs(ref[lstop][which]).max())
+            err = np.abs(got - ref[lstop][which]).max()
+            assert err < 1e-10 * scale, (lstop, which, err, scale)
+    st = sim.stats(0)
+    assert st["drift_last"] < 1e-9
+
+
+@pytest.mark.parametrize("L,th,beta,ns,ch", CASES)
+def test_tau_series_matches_oracle(L, th, beta, ns, ch):
+    d = workloads.desc(L, 3.8, beta, theta=th, n_stab=ns, channel=ch, seed=3)
+    sim = _sim([d])
+    m = _model(d)
+    f = sim.fields(0)
+    sim.measure_tau()
+    aa, a1, n = sim.get_tau(0)
+    assert n == 1
+    AA, A1 = tau.tau_correlator(m, f, m.M // 2)
+    np.testing.assert_allclose(aa, AA.real, rtol=1e-10, atol=0)
+    assert abs(a1 - A1.real) < 1e-10 * abs(A1)
+    rows = sim.tau_rows(0)
+    assert rows.shape == (1, m.M // 2 + 2)
+    np.testing.assert_array_equal(rows[0, :-1], aa)
+    # a second pass on the same configuration doubles nothing but the count
+    sim.measure_tau()
+    aa2, a12, n2 = sim.get_tau(0)
+    assert n2 == 2
+    np.testing.assert_allclose(aa2, aa, rtol=1e-13, atol=0)
+
+
+def test_uneven_batch_tau():
+    """Instances of different M end their passes at their own M/2; a shorter
+    l_max cuts every instance."""
+    ds = [workloads.desc(4, 3.8, 2.0, theta=(0.7, 2.1), n_stab=5, seed=5),
+          workloads.desc(3, 3.7, 3.0, n_stab=5, seed=6)]
+    sim = _sim(ds)
+    sim.measure_tau()
+    for i, d in enumerate(ds):
+        m = _model(d)
+        AA, A1 = tau.tau_correlator(m, sim.fields(i), m.M // 2)
+        aa, a1, n = sim.get_tau(i)
+        assert n == 1
+        np.testing.assert_allclose(aa, AA.real, rtol=1e-10, atol=0)
+    sim.reset_obs()
+    sim.measure_tau(7)
+    for i, d in enumerate(ds):
+        m = _model(d)
+        AA, _ = tau.tau_correlator(m, sim.fields(i), 7)
+        aa, _, n = sim.get_tau(i)
+        assert n == 1
+        np.testing.assert_allclose(aa[:8], AA.real, rtol=1e-10, atol=0)
+        assert np.all(aa[8:] == 0.0)
+
+
+@pytest.mark.parametrize("ch", [0, 1])
+def test_tau_after_sweeps(ch):
+    """After whole sweeps the partner chains come from the last downward pass."""
+    d = workloads.desc(4, 3.8, 2.0, theta=(0.3, 1.1), n_stab=5, channel=ch, seed=9)
+    sim = _sim([d])
+    sim.sweep(2, measure=False)
+    m = _model(d)
+    f = sim.fields(0)
+    sim.measure_tau()
+    AA, A1 = tau.tau_correlator(m, f, m.M // 2)
+    aa, a1, n = sim.get_tau(0)
+    np.testing.assert_allclose(aa, AA.real, rtol=1e-10, atol=0)
+    assert abs(a1 - A1.real) < 1e-10 * abs(A1)
+    ref = tau.tau_greens(m, f, 0, m.M // 2)[m.M // 2]
+    for which in range(3):
+        scale = max(1.0, np.abs(ref[which]).max())
+        assert np.abs(sim.green_tau(0, which) - ref[which]).max() < 1e-10 * scale
+
+
+def test_tau_pass_leaves_the_chain():
+    """Same seed, same replayed decisions: a pass between sweeps changes
+    neither the fields nor G of the following sweep."""
+    import torch
+    d = workloads.desc(4, 3.8, 2.0, theta=(0.7, 2.1), n_stab=5, seed=4)
+    out = []
+    for with_pass in (False, True):
+        sim = _sim([d])
+        N, M, _ = sim.shapes[0]
+        bits = workloads.accept_bits(17, 2 * 2 * M * N, 0.4)
+        b = torch.from_numpy(bits).reshape(1, -1).cuda()
+        sim.replay(b[:, :2 * M * N].contiguous(), None, n_sweeps=1)
+        if with_pass:
+            sim.measure_tau()
+        sim.replay(b[:, 2 * M * N:].contiguous(), None, n_sweeps=1)
+        out.append((sim.fields(0), sim.green(0)))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_tau_full_size_sampled():
+    """Twisted L = 18, beta = 18 (N = 648, M = 180), the benched shape: the
+    pass up to l = 10 (one recomputation) against the oracle's pinned UDV G
+    at slices 0 and 10 and explicit propagation over the 10 slices, and the
+    series at l = 0 and l = 10 from those matrices."""
+    d = workloads.desc(18, 3.73, 18.0, theta=(0.9, 2.3), n_stab=10, k=32, seed=2)
+    sim = _sim([d])
+    m = _model(d)
+    f = sim.fields(0)
+    lm = 10
+    sim.measure_tau(lm)
+    G0 = m.green_scratch(f, 0, 0)
+    Gt = m.green_scratch(f, lm, 0)
+    P = np.eye(m.N, dtype=complex)
+    Pi = np.eye(m.N, dtype=complex)
+    for l in range(1, lm + 1):
+        P = m.B(0, f[l - 1]) @ P
+        Pi = Pi @ m.Binv(0, f[l - 1])
+    Gt0 = P @ G0
+    G0t = -(np.eye(m.N) - G0) @ Pi
+    for which, ref in enumerate((Gt, Gt0, G0t)):
+        err = np.abs(sim.green_tau(0, which) - ref).max()
+        assert err < 1e-8, (which, err)
+    assert sim.stats(0)["drift_last"] < 1e-8
+    aa, a1, n = sim.get_tau(0)
+    assert n == 1
+    for l, (gtt, gt0, g0t) in ((0, (G0, G0, G0 - np.eye(m.N))), (lm, (Gt, Gt0, G0t))):
+        t = (0.5 - np.diag(gtt))[:, None] * (0.5 - np.diag(G0))[None, :] - g0t.T * gt0
+        ref = np.sum(np.abs(t) ** 2)
+        assert abs(aa[l] - ref) < 1e-8 * ref, (l, aa[l], ref)
+    assert abs(a1 + np.sum(np.abs(0.5 - np.diag(G0)) ** 2)) < 1e-9 * abs(a1)
