@@ -75,6 +75,10 @@ def parse():
                          "default: the library's choice for the batch size)")
     ap.add_argument("--plain-steps", type=int, default=None,
                     help="sweeps of the plain leg (default --steps); lets a long learned leg run on its own")
+    ap.add_argument("--tau-passes", type=int, default=2,
+                    help="time-displaced passes after the timed legs (one after each extra sweep; 0: none)")
+    ap.add_argument("--tau-only", action="store_true",
+                    help="only the time-displaced leg (for profiles of the pass)")
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -259,6 +263,53 @@ def timed_leg(sim, steps, label, learn_m=0, events=False):
             "drift": max(s["drift_max"] for s in st1)}
 
 
+def tau_leg(sim, descs, passes):
+    """Time-displaced estimators (Sec. II C, eqs. DouOccDerive, fidelitysusp):
+    one pass after each of `passes` further sweeps, timed alone.  C(tau) is
+    formed per twist from the pooled means of that twist's chains of the
+    largest L, then averaged over the twists (twist-averaged boundary
+    conditions), and integrated by the trapezoid rule (the exact derivative of
+    the Trotterised ensemble) and by a degree-6 polynomial fit."""
+    import torch
+    from paper_2609_14668_amd import tau_integrals
+    sim.reset_obs()
+    sec = 0.0
+    for _ in range(passes):
+        sim.sweep(1, measure=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.measure_tau()
+        torch.cuda.synchronize()
+        sec += time.perf_counter() - t0
+        print("time-displaced pass done", file=sys.stderr, flush=True)
+    Lmax = max(d["L"] for d in descs)
+    groups = {}
+    for i, d in enumerate(descs):
+        if d["L"] != Lmax:
+            continue
+        aa, a1, n = sim.get_tau(i)
+        if n > 0:
+            groups.setdefault((d["theta1"], d["theta2"]), []).append((aa, a1))
+    if not groups:
+        return None
+    cs = []
+    for v in groups.values():
+        aa = np.mean([x[0] for x in v], axis=0)
+        a1 = np.mean([x[1] for x in v])
+        cs.append(aa - a1 * a1)
+    c = np.mean(cs, axis=0)
+    d0 = next(d for d in descs if d["L"] == Lmax)
+    Ns = 2 * Lmax * Lmax
+    dd, chi = tau_integrals(c, d0["dtau"], Ns, -1)
+    dd6, chi6 = tau_integrals(c, d0["dtau"], Ns, 6)
+    nch = sum(len(v) for v in groups.values())
+    return {"passes": passes, "chains": nch, "twists": len(groups), "L": Lmax, "slices": len(c),
+            "ms_per_pass": 1e3 * sec / max(passes, 1),
+            "tau_slices_per_s": nch * len(c) * passes / sec if sec > 0 else None,
+            "C_tau0": float(c[0]), "C_beta_half": float(c[-1]),
+            "dD_dU": dd, "chi_F_per_site": chi / Ns, "dD_dU_fit6": dd6, "chi_F_per_site_fit6": chi6 / Ns}
+
+
 def copy_calibration():
     """A plain device copy of known size: what FETCH_SIZE and WRITE_SIZE read
     for it converts their counts of other kernels to bytes."""
@@ -319,6 +370,10 @@ def main():
         tuned["fft_us"] = {"L%d/%s/%s" % (L, ("cols", "rows")[sd], ("wide", "narrow", "eight")[t]): round(u, 1)
                            for (L, sd, t), u in ftimes.items() if u > 0}
         print("autotuned fft tiles %s" % tuned["fft_tiles"], file=sys.stderr, flush=True)
+    if a.tau_only:
+        print(json.dumps({"config": {"workload": a.workload, "instances": n, "hs_channel": a.channel},
+                          "tau": tau_leg(sim, descs, max(a.tau_passes, 1))}))
+        return
     for w in range(a.warmup):
         if learned and w == a.warmup - 1:
             sim.collect(8)     # training windows from the last warm-up sweep
@@ -423,6 +478,8 @@ def main():
             "time_split_ms": {k: round(ltim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab",
                                                                     "learn")},
         }
+    if a.tau_passes > 0:
+        line["tau"] = tau_leg(sim, descs, a.tau_passes)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(descs, a.cpu_seconds)
     print(json.dumps(line))

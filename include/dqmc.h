@@ -468,7 +468,9 @@ dqmc_status dqmc_set_flush_kernel(dqmc_handle h, int32_t variant);
  * multiple of n_stab; the chains advance as in a sweep, without estimators),
  * time them with HIP events, and keep the fastest pair (best[0] = rank,
  * best[1] = kernel; ms_per_step[3 q + v], nullable, gets the time per step
- * of rank q with kernel v, 0 where not tried).  Synchronises. */
+ * of rank q with kernel v, 0 where not tried).  The chains then take the
+ * steps (at most one sweep) that bring the instances of the largest M back
+ * to the start of a sweep.  Synchronises. */
 dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int32_t n_cand, int32_t* best,
                           double* ms_per_step);
 

@@ -249,6 +249,7 @@ struct dqmc_ctx {
   double wrap_bytes = 0;
   std::vector<int64_t> rank_base;   // flush_rank_sum at timing reset
   int64_t sweeps_done = 0;
+  int64_t steps_issued = 0;         // slice steps since the last initial build (all instances start at phase 0)
   int device = 0;                   // HIP device the handle was created on
 };
 
@@ -754,6 +755,7 @@ dqmc_status init_green(dqmc_ctx* h, hipStream_t s) {
     c.chk(launch_advance(h->dinst, h->n, s));
   }
   c.chk(launch_init_state(h->dinst, h->n, 0, s));
+  h->steps_issued = 0;
   if (c.e != hipSuccess) return fail(h, DQMC_EHIP, std::string("init: ") + hipGetErrorString(c.e));
   return DQMC_OK;
 }
@@ -1129,6 +1131,7 @@ static std::vector<int> graph_key(dqmc_handle h, int32_t measure, int replay, in
 // timing and step counts that are not a whole number of blocks.
 static dqmc_status run_steps(dqmc_handle h, int64_t steps, int32_t measure, hipStream_t s, int replay) {
   const int groups = h->timing ? 1 : h->n_groups;
+  h->steps_issued += steps;
   if (!h->use_graphs || !h->cap || h->timing || steps % h->n_stab != 0) {
     hipError_t e = issue_steps(h, steps, measure, s, replay, groups);
     if (e != hipSuccess) return fail(h, DQMC_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
@@ -1239,7 +1242,13 @@ dqmc_status dqmc_autotune(dqmc_handle h, int32_t steps, const int32_t* cand, int
   (void)hipEventDestroy(e1);
   if (st != DQMC_OK) return st;
   if (best) { best[0] = bk; best[1] = bv; }
-  return dqmc_set_delay(h, bk);
+  st = dqmc_set_delay(h, bk);
+  // back to a sweep boundary of the instances with the largest M, so that
+  // later whole sweeps end where a sweep of those chains ends
+  const int64_t per = 2 * (int64_t)h->Mmax, pad = (per - h->steps_issued % per) % per;
+  if (st == DQMC_OK && pad > 0) st = run_steps(h, pad, 0, s, 0);
+  if (st == DQMC_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(h, DQMC_EHIP, "autotune sync");
+  return st;
 }
 
 dqmc_status dqmc_set_fft_tile(dqmc_handle h, int32_t L, int32_t side, int32_t tile) {

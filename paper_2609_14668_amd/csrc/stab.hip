@@ -47,7 +47,11 @@ k_elem(const InstDev* __restrict__ insts, ElemArgs e) {
   const size_t NN = (size_t)N * N;
   const size_t stride = (size_t)gridDim.x * EW_THREADS;
   const size_t e0 = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
-  if (st->idle && e.op != EO_STACK_IDENTITY && e.op != EO_IDENTITY && e.op != EO_SET_ONES) return;
+  // idle instances skip everything, except the identity fills of the initial
+  // stack build (an instance parked by a time-displaced pass may be in the
+  // middle of a sweep: its working chain must survive)
+  if (st->idle && !(st->init_mode && (e.op == EO_STACK_IDENTITY || e.op == EO_IDENTITY || e.op == EO_SET_ONES)))
+    return;
   switch (e.op) {
     case EO_COPY: {
       const S* a = matp<S>(d, e.a);

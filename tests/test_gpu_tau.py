@@ -148,6 +148,47 @@ def test_tau_pass_leaves_the_chain():
     np.testing.assert_array_equal(out[0][1], out[1][1])
 
 
+def test_tau_pass_leaves_parked_chains():
+    """An instance that is not at the start of a sweep is parked during a
+    pass; its working chain (mid upward pass) must come through unchanged.
+    M = 20 and M = 25: after one handle sweep (50 steps) the first instance
+    stands at phase 10 with two chain steps done, the second at phase 0."""
+    import torch
+    ds = [workloads.desc(4, 3.8, 2.0, theta=(0.7, 2.1), n_stab=5, seed=4),
+          workloads.desc(3, 3.7, 2.5, n_stab=5, seed=8)]
+    out = []
+    for with_pass in (False, True):
+        sim = _sim(ds)
+        per = 2 * 25 * 32
+        bits = workloads.accept_bits(23, 2 * per * 2, 0.4).reshape(2, -1)
+        b = torch.from_numpy(bits).cuda()
+        sim.replay(b[:, :per].contiguous(), None, n_sweeps=1)
+        if with_pass:
+            sim.measure_tau()
+            assert sim.get_tau(0)[2] == 0 and sim.get_tau(1)[2] == 1
+        sim.replay(b[:, per:2 * per].contiguous(), None, n_sweeps=1)
+        out.append([(sim.fields(i), sim.green(i)) for i in range(2)])
+    for i in range(2):
+        np.testing.assert_array_equal(out[0][i][0], out[1][i][0])
+        np.testing.assert_array_equal(out[0][i][1], out[1][i][1])
+
+
+def test_autotune_returns_to_a_sweep_boundary():
+    """The flush autotuner runs slice steps that are not whole sweeps; it ends
+    with the steps that put the instances of the largest M back at the start
+    of a sweep, where a pass can measure them."""
+    ds = [workloads.desc(4, 3.8, 2.0, theta=(0.7, 2.1), n_stab=5, seed=4, k=8),
+          workloads.desc(3, 3.7, 1.0, n_stab=5, seed=8, k=8)]
+    sim = _sim(ds)
+    sim.autotune([8, 16], 10)
+    sim.sweep(1, measure=False)
+    sim.measure_tau()
+    assert sim.get_tau(0)[2] == 1
+    m = _model(ds[0])
+    AA, _ = tau.tau_correlator(m, sim.fields(0), m.M // 2)
+    np.testing.assert_allclose(sim.get_tau(0)[0], AA.real, rtol=1e-10, atol=0)
+
+
 def test_tau_full_size_sampled():
     """Twisted L = 18, beta = 18 (N = 648, M = 180), the benched shape: the
     pass up to l = 10 (one recomputation) against the oracle's pinned UDV G
