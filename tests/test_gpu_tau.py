@@ -189,6 +189,49 @@ def test_autotune_returns_to_a_sweep_boundary():
     np.testing.assert_allclose(sim.get_tau(0)[0], AA.real, rtol=1e-10, atol=0)
 
 
+@pytest.mark.parametrize("ch,th", [(0, (0.0, 0.0)), (0, (0.7, -0.4)), (1, (0.7, -0.4))])
+def test_tau_chains_match_exact_l2(ch, th):
+    """End to end against exact diagonalisation: 128 independent GPU chains
+    on the L = 2 honeycomb torus at M = 2 (the Trotterised ensemble that the
+    Fock-space ED evaluates exactly), one pass after every sweep.  The chain
+    means of <A(tau_l) A(0)> (l = 0, 1) and <A> agree with the ED values, and
+    dD/dU from the trapezoid of C with the central difference of the exact D,
+    within 4 standard errors over chains (jackknife for dD/dU)."""
+    from oracle import exact
+    from paper_2609_14668_amd import tau_integrals
+    U, dt, M = 3.8, 0.25, 2
+    n, sweeps = 128, 150
+    ds = [workloads.desc(2, U, M * dt, dtau=dt, theta=th, k=8, n_stab=2, seed=300 + i, channel=ch)
+          for i in range(n)]
+    sim = _sim(ds)
+    sim.sweep(20, measure=False)
+    for _ in range(sweeps):
+        sim.sweep(1, measure=False)
+        sim.measure_tau()
+    X = np.array([np.concatenate([sim.get_tau(i)[0], [sim.get_tau(i)[1]]]) for i in range(n)])
+    assert all(sim.get_tau(i)[2] == sweeps for i in range(n))
+    kw = dict(U=U, dtau=dt, M=M, theta1=th[0], theta2=th[1], channel="charge" if ch else "spin")
+    ed = exact.exact_tau_trotter2(exact.tiny_model(**kw))
+    ref = np.concatenate([ed["AA"], [ed["A"]]])
+    mean = X.mean(axis=0)
+    err = X.std(axis=0, ddof=1) / np.sqrt(n)
+    assert np.all(np.abs(mean - ref) < 4 * err), (mean, ref, err)
+    Ns = 8
+
+    def dd(rows):
+        m = rows.mean(axis=0)
+        return tau_integrals(m[:2] - m[2] ** 2, dt, Ns, -1)[0]
+
+    jk = np.array([dd(np.delete(X, i, axis=0)) for i in range(n)])
+    d_err = np.sqrt((n - 1) * np.mean((jk - jk.mean()) ** 2))
+    h = 1e-4
+    fd = (exact.exact_trotter(exact.tiny_model(**dict(kw, U=U + h)))["D"]
+          - exact.exact_trotter(exact.tiny_model(**dict(kw, U=U - h)))["D"]) / (2 * h)
+    print("dD/dU", dd(X), "+-", d_err, "exact", fd, flush=True)
+    assert d_err < 0.02 * abs(fd)              # the comparison resolves dD/dU
+    assert abs(dd(X) - fd) < 4 * d_err, (dd(X), fd, d_err)
+
+
 def test_tau_full_size_sampled():
     """Twisted L = 18, beta = 18 (N = 648, M = 180), the benched shape: the
     pass up to l = 10 (one recomputation) against the oracle's pinned UDV G
