@@ -297,7 +297,9 @@ k_fft_apply(const InstDev* __restrict__ insts, FftArgs a, int nv, int generic_on
   const int L = LC > 0 ? LC : d.L;
   const int Nc = L * L, N = 2 * Nc;
   const int nvec = ST<S>::is_complex ? N : N / 2;
-  const int v0 = blockIdx.x * nv;
+  // XCD-aware tile order (gridDim.x a multiple of 8), as in k_fft_reg
+  const int tile = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int v0 = tile * nv;
   if (v0 >= nvec) return;
   const int nvl = min(nv, nvec - v0);
   C* buf = reinterpret_cast<C*>(smem_raw);
@@ -517,7 +519,11 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
   Resolved rs = resolve(d, a);
   if (!rs.active) return;
   constexpr int nvec = ST<S>::is_complex ? N : N / 2;
-  const int v0 = blockIdx.x * NV;
+  // gridDim.x is a multiple of 8, so workgroup x of every instance runs on
+  // XCD x % 8; each XCD takes a run of consecutive tiles, whose row segments
+  // share cache lines in that XCD's L2
+  const int tile = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int v0 = tile * NV;
   if (v0 >= nvec) return;
   const int nvl = min(NV, nvec - v0);
   const int tid = threadIdx.x;
@@ -527,9 +533,11 @@ __global__ void __launch_bounds__(NT) k_fft_reg(const InstDev* __restrict__ inst
   const bool rows = a.side != 0;
   const HsDiag<C, ST<S>::is_complex> hd(d, rows);
   const bool chain = a.op == FOP_STAB_CHAIN;
-  // load (+ pre diagonal): clamped loads issued in groups, then masked
+  // load (+ pre diagonal): clamped loads issued in groups, then masked; a
+  // group covers the thread's whole share of the tile, so the workgroup
+  // waits for memory once
   const int tot = nvl * N;
-  constexpr int LU = 8;
+  constexpr int LU = (NV * N + NT - 1) / NT < 24 ? (NV * N + NT - 1) / NT : 24;
   for (int e0 = tid; e0 < tot; e0 += LU * FFT_THREADS) {
     S raw[LU][ST<S>::is_complex ? 1 : 2];
     int8_t xr[LU];
@@ -672,7 +680,8 @@ void launch_reg(const InstDev* insts, int n_inst, const FftArgs& a, hipStream_t 
   constexpr int N = 2 * LC * LC;
   constexpr int NV = reg_nv(LC, TILE), NT = reg_nt(LC, TILE);
   constexpr int nvec = ST<S>::is_complex ? N : N / 2;
-  hipLaunchKernelGGL((k_fft_reg<S, LC, C, NV, NT>), dim3((nvec + NV - 1) / NV, n_inst), dim3(NT), 0, s, insts, a);
+  const int tiles = ((nvec + NV - 1) / NV + 7) / 8 * 8;   // a multiple of 8 (XCD-aware tile order)
+  hipLaunchKernelGGL((k_fft_reg<S, LC, C, NV, NT>), dim3(tiles, n_inst), dim3(NT), 0, s, insts, a);
 }
 
 template <typename S, int LC, typename C>
@@ -694,7 +703,7 @@ void launch_fixed(const InstDev* insts, int n_inst, const FftArgs& a, size_t lds
     (void)tile;
     int nv = fft_vectors_per_block(N, lds_budget, sizeof(C));
     int nvec = ST<S>::is_complex ? N : N / 2;
-    dim3 grid((nvec + nv - 1) / nv, n_inst);
+    dim3 grid(((nvec + nv - 1) / nv + 7) / 8 * 8, n_inst);
     size_t lds = 2 * (size_t)nv * N * sizeof(C);
     constexpr int R = 13;  // unused by the fixed path
     hipLaunchKernelGGL((k_fft_apply<S, R, LC, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 0);
@@ -706,7 +715,7 @@ void launch_generic(const InstDev* insts, int n_inst, int Nmax, const FftArgs& a
                     hipStream_t s) {
   int nv = fft_vectors_per_block(Nmax, lds_budget, sizeof(C));
   int nvec = ST<S>::is_complex ? Nmax : Nmax / 2;
-  dim3 grid((nvec + nv - 1) / nv, n_inst);
+  dim3 grid(((nvec + nv - 1) / nv + 7) / 8 * 8, n_inst);
   size_t lds = 2 * (size_t)nv * Nmax * sizeof(C);
   if (rmax <= 4) hipLaunchKernelGGL((k_fft_apply<S, 4, 0, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);
   else if (rmax <= 7) hipLaunchKernelGGL((k_fft_apply<S, 7, 0, C>), grid, dim3(FFT_THREADS), lds, s, insts, a, nv, 1);

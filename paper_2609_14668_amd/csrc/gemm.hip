@@ -45,33 +45,6 @@ __device__ __forceinline__ void split<cplx>(cplx v, double& re, double& im) { re
 __device__ __forceinline__ double shfl_xor_s(double v, int m) { return __shfl_xor(v, m); }
 __device__ __forceinline__ cplx shfl_xor_s(cplx v, int m) { return cmake(__shfl_xor(v.x, m), __shfl_xor(v.y, m)); }
 
-// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
-// dispatch order.  Map the dispatch index so that all workgroups of an
-// instance sit on one XCD: instance xcd + 8 q is served by the slots
-// q * gx .. q * gx + gx - 1 of that XCD, and its operands stay in one L2
-// instead of being fetched into all eight.  The grid's y extent is the
-// instance count rounded up to a multiple of 8; slots past the last instance
-// return.  Only the placement depends on the dispatch order, not the result.
-// With fewer instances than XCDs the placement would leave XCDs idle, so the
-// plain mapping (instance = blockIdx.y) is used and the grid is not padded.
-constexpr int N_XCD = 8;
-__host__ __device__ __forceinline__ int xcd_grid_y(int n_inst) {
-  return n_inst >= N_XCD ? (n_inst + N_XCD - 1) / N_XCD * N_XCD : n_inst;
-}
-__device__ __forceinline__ void xcd_slot(int n_inst, int& inst, int& bx) {
-  if (n_inst < N_XCD) {
-    inst = blockIdx.y;
-    bx = blockIdx.x;
-    return;
-  }
-  const int gx = gridDim.x;
-  const int lin = blockIdx.x + gx * blockIdx.y;
-  const int xcd = lin % N_XCD, slot = lin / N_XCD;
-  inst = xcd + N_XCD * (slot / gx);
-  bx = slot % gx;
-  if (inst >= n_inst) inst = -1;
-}
-
 // Shared memory of one 64 x 64 output tile (op(A) and op(B) chunks, real
 // and imaginary planes).
 template <bool CX, int KB = BK>

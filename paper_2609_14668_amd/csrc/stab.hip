@@ -805,17 +805,20 @@ __global__ void __launch_bounds__(256) k_pair_t(const InstDev* __restrict__ inst
 // cols: 0 -> [j0 + 32, N), 1 -> [j0, N), 2 -> [0, N).  The second panel's
 // vectors are read as zero above their own first row.
 template <typename S>
-__global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__ insts, int q, int target,
-                                                     int cols, int use_th) {
+__global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__ insts, int n_inst, int q,
+                                                     int target, int cols, int use_th) {
   constexpr bool CX = ST<S>::is_complex;
-  const InstDev& d = insts[blockIdx.y];
+  int inst, bx;
+  xcd_slot(n_inst, inst, bx);   // all column tiles of an instance on one XCD: V is read into one L2
+  if (inst < 0) return;
+  const InstDev& d = insts[inst];
   if (d.st->idle) return;
   const int N = d.N;
   const int j0 = q * PR;
   if (j0 >= N) return;
   const int nbe = min(PR, N - j0);
   const int cbeg = cols == 0 ? j0 + PR : (cols == 1 ? j0 : 0);
-  const int c0 = cbeg + blockIdx.x * AR_CT;
+  const int c0 = cbeg + bx * AR_CT;
   if (c0 >= N) return;
   const S* V = matp<S>(d, MAT_V);
   const S* TB = matp<S>(d, MAT_TB);
@@ -1731,9 +1734,9 @@ hipError_t launch_apply_refl2(const InstDev* insts, int n_inst, int Nmax, bool c
   if (ncol <= 0 || j0 >= Nmax) return hipSuccess;
   const int ns = refl_split(n_inst, ncol, Nmax - j0, PR);
   if (ns > 1) return launch_refl_split<PR>(insts, n_inst, cplx_, q, target, cols, use_th, ncol, ns, s);
-  dim3 grid((ncol + AR_CT - 1) / AR_CT, n_inst);
-  if (cplx_) hipLaunchKernelGGL(k_apply_refl2<cplx>, grid, dim3(256), 0, s, insts, q, target, cols, use_th);
-  else hipLaunchKernelGGL(k_apply_refl2<double>, grid, dim3(256), 0, s, insts, q, target, cols, use_th);
+  dim3 grid((ncol + AR_CT - 1) / AR_CT, xcd_grid_y(n_inst));
+  if (cplx_) hipLaunchKernelGGL(k_apply_refl2<cplx>, grid, dim3(256), 0, s, insts, n_inst, q, target, cols, use_th);
+  else hipLaunchKernelGGL(k_apply_refl2<double>, grid, dim3(256), 0, s, insts, n_inst, q, target, cols, use_th);
   return hipGetLastError();
 }
 
