@@ -846,9 +846,9 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
     wi[t] = d4{0, 0, 0, 0};
     if constexpr (CX) wq[t] = d4{0, 0, 0, 0};
   }
-#pragma unroll 1
-  for (int i0 = j0; i0 < N; i0 += RB) {
-    S vv[NV], cv[NC];
+  // the loads of row chunk i0 + RB are issued before chunk i0 is multiplied
+  S vv[NV], cv[NC];
+  auto load_chunk = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
       const int x = tid + 256 * u, r = x % RB, m = x / RB;
@@ -859,6 +859,10 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
       const int x = tid + 256 * u, r = x % RB, cc = x / RB;
       cv[u] = gld(C + min(i0 + r, N - 1) + (size_t)min(c0 + cc, N - 1) * N);
     }
+  };
+  load_chunk(j0);
+#pragma unroll 1
+  for (int i0 = j0; i0 < N; i0 += RB) {
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
       const int x = tid + 256 * u, r = x % RB, m = x / RB;
@@ -879,6 +883,7 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
       if constexpr (CX) Ci[r * (AR_CT + 1) + cc] = in ? im : 0.0;
     }
     __syncthreads();
+    if (i0 + RB < N) load_chunk(i0 + RB);
 #pragma unroll 2
     for (int ks = 0; ks < RB / 4; ++ks) {
       const int k = ks * 4 + lk;
@@ -931,16 +936,21 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
     for (int u = 0; u < 8; ++u) Ws[m * (AR_CT + 1) + cb + 8 * u] = wp[u];
   }
   __syncthreads();
-  // C -= V W': wave w updates columns 16w .. 16w+15, 16 rows at a time, K = 32
+  // C -= V W': wave w updates columns 16w .. 16w+15, 16 rows at a time, K = 32;
+  // the next 16 rows' C and V are loaded while these are multiplied
   const int cw = c0 + wave * 16;
-#pragma unroll 1
-  for (int i0 = j0; i0 < N; i0 += 16) {
-    const int i = i0 + lr, ic = min(i, N - 1);
-    S cl[4], vl[8];
+  S cl[4], vl[8];
+  auto load_rows = [&](int i0) {
+    const int ic = min(i0 + lr, N - 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) cl[r] = gld(C + ic + (size_t)min(cw + lk + 4 * r, N - 1) * N);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) vl[ks] = gld(V + ic + (size_t)(j0 + min(ks * 4 + lk, nbe - 1)) * N);
+  };
+  load_rows(j0);
+#pragma unroll 1
+  for (int i0 = j0; i0 < N; i0 += 16) {
+    const int i = i0 + lr;
     // (W' V)(c, i) with three real products: Q1 = br vr (q1), Q2 = bi vi (q2),
     // Q3 = (br + bi)(vr + vi) (q3), started at -C so that
     // C - W'V = -((q1 - q2) + i (q3 - q1 - q2)) with q1 = -Cre, q3 = -Cre - Cim
@@ -953,18 +963,23 @@ __global__ void __launch_bounds__(256) k_apply_refl2(const InstDev* __restrict__
       q2[r] = 0.0;
       q3[r] = -re - im;
     }
+    double vr[8], vi[8];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int m = ks * 4 + lk;
-      double vr, vi;
-      split_s<S>(vl[ks], vr, vi);
-      if (!(i < N && m < nbe && i >= j0 + (m / NBR) * NBR)) { vr = 0.0; vi = 0.0; }
+      split_s<S>(vl[ks], vr[ks], vi[ks]);
+      if (!(i < N && m < nbe && i >= j0 + (m / NBR) * NBR)) { vr[ks] = 0.0; vi[ks] = 0.0; }
+    }
+    if (i0 + 16 < N) load_rows(i0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int m = ks * 4 + lk;
       double br, bi;
       split_s<S>(Ws[m * (AR_CT + 1) + wave * 16 + lr], br, bi);
-      q1 = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr, q1, 0, 0, 0);
+      q1 = __builtin_amdgcn_mfma_f64_16x16x4f64(br, vr[ks], q1, 0, 0, 0);
       if constexpr (CX) {
-        q2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vi, q2, 0, 0, 0);
-        q3 = __builtin_amdgcn_mfma_f64_16x16x4f64(br + bi, vr + vi, q3, 0, 0, 0);
+        q2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bi, vi[ks], q2, 0, 0, 0);
+        q3 = __builtin_amdgcn_mfma_f64_16x16x4f64(br + bi, vr[ks] + vi[ks], q3, 0, 0, 0);
       }
     }
 #pragma unroll
