@@ -265,11 +265,15 @@ def timed_leg(sim, steps, label, learn_m=0, events=False):
 
 def tau_leg(sim, descs, passes):
     """Time-displaced estimators (Sec. II C, eqs. DouOccDerive, fidelitysusp):
-    one pass after each of `passes` further sweeps, timed alone.  C(tau) is
-    formed per twist from the pooled means of that twist's chains of the
-    largest L, then averaged over the twists (twist-averaged boundary
-    conditions), and integrated by the trapezoid rule (the exact derivative of
-    the Trotterised ensemble) and by a degree-6 polynomial fit."""
+    one pass after each of `passes` further sweeps, timed alone.  Per twist
+    of the largest L, C(tau) is formed from the per-pass rows of that twist's
+    chains as mean(<A(tau)A(0)>_X - <A>_X(tau) <A>_X(0)) + Cov(<A>_X(tau),
+    <A>_X(0)) (about the mean of <A>_X over all rows and slices), which avoids
+    subtracting two numbers of order N_s^2 / 16; dD/dU and chi_F are then
+    integrated per twist by the trapezoid rule (the exact derivative of the
+    Trotterised ensemble) and by a degree-6 polynomial fit, and averaged over
+    the twists (twist-averaged boundary conditions), with the standard error
+    over twists."""
     import torch
     from paper_2609_14668_amd import tau_integrals
     sim.reset_obs()
@@ -287,27 +291,34 @@ def tau_leg(sim, descs, passes):
     for i, d in enumerate(descs):
         if d["L"] != Lmax:
             continue
-        aa, a1, n = sim.get_tau(i)
-        if n > 0:
-            groups.setdefault((d["theta1"], d["theta2"]), []).append((aa, a1))
+        rows = sim.tau_rows(i)
+        if len(rows):
+            groups.setdefault((d["theta1"], d["theta2"]), []).append(rows)
     if not groups:
         return None
-    cs = []
-    for v in groups.values():
-        aa = np.mean([x[0] for x in v], axis=0)
-        a1 = np.mean([x[1] for x in v])
-        cs.append(aa - a1 * a1)
-    c = np.mean(cs, axis=0)
     d0 = next(d for d in descs if d["L"] == Lmax)
     Ns = 2 * Lmax * Lmax
-    dd, chi = tau_integrals(c, d0["dtau"], Ns, -1)
-    dd6, chi6 = tau_integrals(c, d0["dtau"], Ns, 6)
+    lc = sim.shapes[descs.index(d0)][1] // 2
+    cs, per = [], []
+    for v in groups.values():
+        r = np.concatenate(v)
+        aa, at = r[:, :lc + 1], r[:, lc + 1:]
+        ma = at.mean()
+        c = np.mean(aa - at * at[:, :1], axis=0) + np.mean((at - ma) * (at[:, :1] - ma), axis=0)
+        cs.append(c)
+        per.append(tau_integrals(c, d0["dtau"], Ns, -1) + tau_integrals(c, d0["dtau"], Ns, 6))
+    c = np.mean(cs, axis=0)
+    per = np.array(per)
+    mean = per.mean(axis=0)
+    sem = per.std(axis=0, ddof=1) / np.sqrt(len(per)) if len(per) > 1 else np.zeros(4)
     nch = sum(len(v) for v in groups.values())
     return {"passes": passes, "chains": nch, "twists": len(groups), "L": Lmax, "slices": len(c),
             "ms_per_pass": 1e3 * sec / max(passes, 1),
             "tau_slices_per_s": nch * len(c) * passes / sec if sec > 0 else None,
             "C_tau0": float(c[0]), "C_beta_half": float(c[-1]),
-            "dD_dU": dd, "chi_F_per_site": chi / Ns, "dD_dU_fit6": dd6, "chi_F_per_site_fit6": chi6 / Ns}
+            "dD_dU": mean[0], "dD_dU_err": sem[0], "chi_F_per_site": mean[1] / Ns, "chi_F_per_site_err": sem[1] / Ns,
+            "dD_dU_fit6": mean[2], "chi_F_per_site_fit6": mean[3] / Ns,
+            "estimator": "fermionic part + covariance of <A>_X(tau), per twist; error over twists"}
 
 
 def copy_calibration():

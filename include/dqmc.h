@@ -277,15 +277,19 @@ dqmc_status dqmc_get_nk(dqmc_handle h, int32_t inst, int32_t raw, double* host_o
  * left unchanged.  Asynchronous on stream (NULL: the handle's stream);
  * DQMC_EHIP on a launch failure. */
 dqmc_status dqmc_measure_tau(dqmc_handle h, int32_t l_max, void* stream);
-/* Means over the passes of instance inst since creation or dqmc_reset_obs:
- * host_aa[l] = <A(tau_l) A(0)> for l = 0 .. M/2 (M/2 + 1 doubles; slices a
- * pass did not reach count as 0), *host_a = <A> (equal time), *n_pass; the
- * connected C_{H_I}(tau_l) is host_aa[l] - (*host_a)^2.  Synchronises;
+/* Means over the passes of instance inst since creation or dqmc_reset_obs,
+ * l = 0 .. M/2 (M/2 + 1 doubles each; slices a pass did not reach count as
+ * 0): host_aa[l] = <A(tau_l) A(0)>, host_a[l] = the equal-time <A> measured
+ * at slice l (the same in expectation for every l), and *n_pass.  The
+ * connected C_{H_I}(tau_l) is host_aa[l] - host_a[0]^2; with few passes the
+ * per-pass rows give the lower-variance form mean(<A(tau)A(0)>_X -
+ * <A>_X(tau) <A>_X(0)) + Cov(<A>_X(tau), <A>_X(0)).  Synchronises;
  * DQMC_ENUMERIC (outputs still filled) after a numerical error. */
 dqmc_status dqmc_get_tau(dqmc_handle h, int32_t inst, double* host_aa, double* host_a, int64_t* n_pass);
 /* The same values per pass, oldest first: the last min(passes, 1024,
- * max_rows) passes of instance inst, M/2 + 2 doubles each (<A(tau_l) A(0)>
- * for l = 0 .. M/2, then <A>); *n_rows receives the count.  Synchronises. */
+ * max_rows) passes of instance inst, M + 2 doubles each for even M (<A(tau_l)
+ * A(0)>_X for l = 0 .. M/2, then <A>_X(tau_l) for l = 0 .. M/2); *n_rows
+ * receives the count.  Synchronises. */
 dqmc_status dqmc_get_tau_rows(dqmc_handle h, int32_t inst, double* host_rows, int32_t max_rows, int32_t* n_rows);
 /* Spin-up G(tau,tau) (which 0), G(tau,0) (1) or G(0,tau) (2) of instance inst
  * at the last slice of the last pass, N x N row-major, elements as in

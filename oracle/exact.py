@@ -381,11 +381,11 @@ def brute_force_tau(model, lmax, batch=2048):
             for l in range(M):
                 P = model.vdiag(spin, X[:, l, :])[:, :, None] * (model.Ep[None] @ P)
             W = W * np.linalg.det(np.eye(N)[None] + P)
-        AA, A1 = tau_correlator(model, X, lmax)
+        AA, At = tau_correlator(model, X, lmax)
         wmin = min(wmin, float(np.min(W.real)))
         Z += W.sum().real
         aa += W @ AA
-        a1 += W @ A1
+        a1 += W @ At[:, 0]
     return {"Z": Z, "AA": (aa / Z).real, "A": (a1 / Z).real, "AA_imag": float(np.max(np.abs((aa / Z).imag))),
             "wmin": wmin}
 

@@ -23,8 +23,8 @@ one spin species, B_l as in ``dqmc.Model.B``):
   spins are independent and Wick's theorem gives
       <A(tau) A(0)>_X = sum_ij prod_sigma [ m_sigma,i(tau) m_sigma,j(0)
                                  - G_sigma(0,tau)_ji G_sigma(tau,0)_ij ],
-  m_sigma,i(tau) = 1/2 - G_sigma(tau,tau)_ii; the equal-time <A>_X is
-  sum_i m_up,i(0) m_dn,i(0).  Both spins are propagated explicitly here.
+  m_sigma,i(tau) = 1/2 - G_sigma(tau,tau)_ii; the equal-time <A>_X(tau) is
+  sum_i m_up,i(tau) m_dn,i(tau).  Both spins are propagated explicitly here.
 * C(tau) = <A(tau) A(0)> - <A>^2 (the constant in H_I drops out).
   dD/dU = -(2/N_s) int_0^{beta/2} C dtau (eq. DouOccDerive) and
   chi_F = int_0^{beta/2} tau C dtau (eq. fidelitysusp).  For the Trotterised
@@ -78,26 +78,45 @@ def tau_greens(model, fields, spin, lmax):
 
 
 def tau_correlator(model, fields, lmax):
-    """Per configuration: (<A(tau_l) A(0)>_X for l = 0..lmax, <A>_X), both
-    complex in general (their weighted averages are real); batched like
-    ``tau_greens``."""
+    """Per configuration: (<A(tau_l) A(0)>_X, <A>_X at slice tau_l) for
+    l = 0..lmax, both complex in general (their weighted averages are real);
+    batched like ``tau_greens``.  The equal-time <A>_X(tau) = sum_i
+    m_up,i(tau) m_dn,i(tau) depends on the slice for a fixed configuration;
+    its average does not."""
     gs = [tau_greens(model, fields, s, lmax) for s in (0, 1)]
     m0 = [0.5 - np.diagonal(g[0][0], axis1=-2, axis2=-1) for g in gs]
-    AA = []
+    AA, At = [], []
     for l in range(lmax + 1):
-        P = []
+        P, mts = [], []
         for s in (0, 1):
             gtt, gt0, g0t = gs[s][l]
             mt = 0.5 - np.diagonal(gtt, axis1=-2, axis2=-1)
+            mts.append(mt)
             P.append(mt[..., :, None] * m0[s][..., None, :] - np.swapaxes(g0t, -1, -2) * gt0)
         AA.append(np.sum(P[0] * P[1], axis=(-2, -1)))
-    A1 = np.sum(m0[0] * m0[1], axis=-1)
-    return np.stack(AA, axis=-1), A1
+        At.append(np.sum(mts[0] * mts[1], axis=-1))
+    return np.stack(AA, axis=-1), np.stack(At, axis=-1)
 
 
 def connected(aa, a1):
     """C(tau_l) = <A(tau_l) A(0)> - <A>^2 from the averaged series."""
     return np.asarray(aa) - np.asarray(a1) ** 2
+
+
+def connected_improved(aa_rows, at_rows):
+    """C(tau_l) from per-configuration rows (aa_rows[n, l] = <A(tau_l) A(0)>_X,
+    at_rows[n, l] = <A>_X(tau_l)) as the mean of the fermionic part
+    <A(tau) A(0)>_X - <A>_X(tau) <A>_X(0) plus the covariance over
+    configurations of <A>_X(tau) and <A>_X(0) about the mean of <A>_X over all
+    rows and slices (the same in every slice by time-translation invariance).
+    Equal to ``connected`` of the averages up to O(1/n) terms, without the
+    cancellation of two large numbers."""
+    aa = np.asarray(aa_rows, dtype=float)
+    at = np.asarray(at_rows, dtype=float)
+    mean_a = at.mean()
+    ferm = np.mean(aa - at * at[:, :1], axis=0)
+    cov = np.mean((at - mean_a) * (at[:, :1] - mean_a), axis=0)
+    return ferm + cov
 
 
 def tau_integrals(c, dtau, n_sites, degree=None):

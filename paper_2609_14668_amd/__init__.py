@@ -79,7 +79,7 @@ _SIGS = {
     "dqmc_get_nk": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_get_series": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_measure_tau": [_P, ctypes.c_int32, _P],
-    "dqmc_get_tau": [_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "dqmc_get_tau": [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int64)],
     "dqmc_get_tau_rows": [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "dqmc_get_green_tau": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "dqmc_tau_integrals": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
@@ -351,18 +351,20 @@ class Simulation:
     measure_tau = dqmc_measure_tau
 
     def dqmc_get_tau(self, inst=0):
-        """(<A(tau_l) A(0)> for l = 0..M/2, <A>, number of passes)."""
+        """(<A(tau_l) A(0)>, <A> at slice l, for l = 0..M/2; number of passes)."""
         M = self.shapes[inst][1]
         aa = np.zeros(M // 2 + 1, dtype=np.float64)
-        a, n = ctypes.c_double(), ctypes.c_int64()
-        self._chk(self.lib.dqmc_get_tau(self.h, inst, aa.ctypes.data, ctypes.byref(a), ctypes.byref(n)), "get_tau")
-        return aa, a.value, n.value
+        at = np.zeros(M // 2 + 1, dtype=np.float64)
+        n = ctypes.c_int64()
+        self._chk(self.lib.dqmc_get_tau(self.h, inst, aa.ctypes.data, at.ctypes.data, ctypes.byref(n)), "get_tau")
+        return aa, at, n.value
 
     get_tau = dqmc_get_tau
 
     def dqmc_get_tau_rows(self, inst=0, max_rows=1024):
+        """Per pass: columns 0..M/2 <A(tau_l) A(0)>_X, then M/2+1.. <A>_X(tau_l)."""
         M = self.shapes[inst][1]
-        out = np.zeros((max_rows, M // 2 + 2), dtype=np.float64)
+        out = np.zeros((max_rows, 2 * (M // 2) + 2), dtype=np.float64)
         n = ctypes.c_int32()
         self._chk(self.lib.dqmc_get_tau_rows(self.h, inst, out.ctypes.data, max_rows, ctypes.byref(n)), "tau_rows")
         return out[:n.value].copy()

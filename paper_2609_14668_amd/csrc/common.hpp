@@ -238,10 +238,10 @@ struct InstDev {
   double* series;           // per-sweep means [max_series x OBS_COUNT]
   double* nk_sum;           // momentum distribution sums: Nc x 8 (AA, AB, BA, BB as re, im)
   int32_t max_series;
-  // time-displaced estimators: tau_sum[l] (l = 0 .. M/2) sums of
-  // <A(tau_l) A(0)>_X over passes, tau_sum[M/2 + 1] the sum of <A>_X,
-  // tau_sum[M/2 + 2] the number of passes; tau_rows holds the same values per
-  // pass (row stride M/2 + 2, tau_cap rows, the oldest overwritten)
+  // time-displaced estimators (lc = M/2): tau_sum[l] (l = 0 .. lc) sums of
+  // <A(tau_l) A(0)>_X over passes, tau_sum[lc + 1 + l] sums of <A>_X(tau_l),
+  // tau_sum[2 lc + 2] the number of passes; tau_rows holds the same values per
+  // pass (row stride 2 lc + 2, tau_cap rows, the oldest overwritten)
   double* tau_sum;
   double* tau_rows;
   int32_t tau_cap;

@@ -123,8 +123,8 @@ Plan make_plan(const dqmc_instance_desc* d, int n) {
     f.obs = o; o = al(o + sizeof(double) * (2 * OBS_COUNT + 1));
     f.series = o; o = al(o + sizeof(double) * OBS_COUNT * MAX_SERIES);
     f.nk = o; o = al(o + sizeof(double) * 8 * Nc);
-    f.tau_sum = o; o = al(o + sizeof(double) * (M / 2 + 3));
-    f.tau_rows = o; o = al(o + sizeof(double) * (size_t)TAU_ROWS * (M / 2 + 2));
+    f.tau_sum = o; o = al(o + sizeof(double) * (2 * (M / 2) + 3));
+    f.tau_rows = o; o = al(o + sizeof(double) * (size_t)TAU_ROWS * (2 * (M / 2) + 2));
     f.fields = o; o = al(o + (size_t)M * N);
     f.tab = o; o = al(o + sizeof(cplx) * 16 * Nc);
     f.roots = o; o = al(o + sizeof(cplx) * 64);
@@ -970,7 +970,7 @@ dqmc_status dqmc_create(const dqmc_instance_desc* d, int32_t n, void* dev_ws, si
         (e = hipMemsetAsync(b + f.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.series, 0, sizeof(double) * OBS_COUNT * MAX_SERIES, s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.nk, 0, sizeof(double) * 8 * Nc, s)) != hipSuccess ||
-        (e = hipMemsetAsync(b + f.tau_sum, 0, sizeof(double) * (dv.M / 2 + 3), s)) != hipSuccess ||
+        (e = hipMemsetAsync(b + f.tau_sum, 0, sizeof(double) * (2 * (dv.M / 2) + 3), s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.targets, 0, sizeof(float) * (size_t)dv.M * dv.N, s)) != hipSuccess ||
         (e = hipMemsetAsync(b + f.learn, 0, sizeof(LearnState), s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
@@ -1460,7 +1460,7 @@ dqmc_status dqmc_reset_obs(dqmc_handle h) {
   for (auto& d : h->hd) {
     HIPCHK(h, hipMemsetAsync(d.obs, 0, sizeof(double) * (2 * OBS_COUNT + 1), h->stream));
     HIPCHK(h, hipMemsetAsync(d.nk_sum, 0, sizeof(double) * 8 * d.Nc, h->stream));
-    HIPCHK(h, hipMemsetAsync(d.tau_sum, 0, sizeof(double) * (d.M / 2 + 3), h->stream));
+    HIPCHK(h, hipMemsetAsync(d.tau_sum, 0, sizeof(double) * (2 * (d.M / 2) + 3), h->stream));
   }
   Ctx c{h, h->stream, h->dinst, h->n, 0};
   c.chk(launch_reset_counters(h->dinst, h->n, h->stream));
@@ -1502,15 +1502,17 @@ dqmc_status dqmc_get_tau(dqmc_handle h, int32_t inst, double* host_aa, double* h
   if (!h || inst < 0 || inst >= h->n || !host_aa || !host_a || !n_pass) return DQMC_EINVAL;
   const InstDev& d = h->hd[inst];
   const int lc = d.M / 2;
-  std::vector<double> sum(lc + 3);
+  std::vector<double> sum(2 * lc + 3);
   InstState st;
   HIPCHK(h, hipMemcpyAsync(sum.data(), d.tau_sum, sizeof(double) * sum.size(), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(&st, d.st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  const double n = sum[lc + 2];
+  const double n = sum[2 * lc + 2];
   *n_pass = (int64_t)n;
-  for (int l = 0; l <= lc; ++l) host_aa[l] = n > 0 ? sum[l] / n : 0.0;
-  *host_a = n > 0 ? sum[lc + 1] / n : 0.0;
+  for (int l = 0; l <= lc; ++l) {
+    host_aa[l] = n > 0 ? sum[l] / n : 0.0;
+    host_a[l] = n > 0 ? sum[lc + 1 + l] / n : 0.0;
+  }
   if (st.numeric_err) return fail(h, DQMC_ENUMERIC, numeric_message(st.numeric_err));
   return DQMC_OK;
 }
@@ -1518,10 +1520,10 @@ dqmc_status dqmc_get_tau(dqmc_handle h, int32_t inst, double* host_aa, double* h
 dqmc_status dqmc_get_tau_rows(dqmc_handle h, int32_t inst, double* host_rows, int32_t max_rows, int32_t* n_rows) {
   if (!h || inst < 0 || inst >= h->n || !host_rows || !n_rows || max_rows < 0) return DQMC_EINVAL;
   const InstDev& d = h->hd[inst];
-  const int lc = d.M / 2, stride = lc + 2;
+  const int lc = d.M / 2, stride = 2 * lc + 2;
   double n = 0;
   std::vector<double> rows((size_t)TAU_ROWS * stride);
-  HIPCHK(h, hipMemcpyAsync(&n, d.tau_sum + lc + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&n, d.tau_sum + 2 * lc + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(rows.data(), d.tau_rows, sizeof(double) * rows.size(), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   const int64_t have = std::min<int64_t>((int64_t)n, TAU_ROWS);

@@ -313,7 +313,10 @@ __global__ void __launch_bounds__(MT) k_measure_tau_pairs(const InstDev* __restr
 }
 
 // Strip partials summed in strip order into slice l's sums and this pass's
-// row; at l = 0 also <A>_X; the pass count advances at the instance's last slice.
+// row, with <A>_X(tau_l) from the diagonal of G(tau_l, tau_l); the pass count
+// advances at the instance's last slice.  Layout (lc = M/2): sums and rows
+// hold <A(tau_l) A(0)>_X at [l] and <A>_X(tau_l) at [lc + 1 + l]; the sums end
+// with the pass count at [2 lc + 2].
 template <typename S>
 __global__ void __launch_bounds__(MT) k_measure_tau_fin(const InstDev* __restrict__ insts, int l) {
   const InstDev& d = insts[blockIdx.y];
@@ -325,30 +328,28 @@ __global__ void __launch_bounds__(MT) k_measure_tau_fin(const InstDev* __restric
   double v = 0.0;
   for (int x = threadIdx.x; x < nb; x += MT) v += d.vec[VEC_NORM][x];
   v = bsum(v, red);
-  double a1 = 0.0;
-  if (l == 0) {
-    const S* g = matp<S>(d, MAT_G);
+  double at = 0.0;
+  {
+    const S* g = matp<S>(d, MAT_GTT);
     const S half = ST<S>::from_re(0.5);
     for (int i = threadIdx.x; i < N; i += MT) {
       const S m = half - g[i + (size_t)i * N];
-      a1 += d.channel != 0 ? real_part(m * m) : -absq(m);
+      at += d.channel != 0 ? real_part(m * m) : -absq(m);
     }
-    a1 = bsum(a1, red);
+    at = bsum(at, red);
   }
-  const int lc = d.M / 2, stride = lc + 2;
-  const int64_t pass = (int64_t)d.tau_sum[lc + 2];
+  const int lc = d.M / 2, stride = 2 * lc + 2;
+  const int64_t pass = (int64_t)d.tau_sum[2 * lc + 2];
   double* row = d.tau_rows + (size_t)(pass % d.tau_cap) * stride;
   if (l == 0)
-    for (int x = threadIdx.x + 1; x <= lc; x += MT) row[x] = 0.0;
+    for (int x = threadIdx.x; x < stride; x += MT) row[x] = 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     d.tau_sum[l] += v;
+    d.tau_sum[lc + 1 + l] += at;
     row[l] = v;
-    if (l == 0) {
-      d.tau_sum[lc + 1] += a1;
-      row[lc + 1] = a1;
-    }
-    if (l == st->tau_lmax) d.tau_sum[lc + 2] += 1.0;
+    row[lc + 1 + l] = at;
+    if (l == st->tau_lmax) d.tau_sum[2 * lc + 2] += 1.0;
   }
 }
 

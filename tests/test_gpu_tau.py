@@ -70,19 +70,22 @@ def test_tau_series_matches_oracle(L, th, beta, ns, ch):
     m = _model(d)
     f = sim.fields(0)
     sim.measure_tau()
-    aa, a1, n = sim.get_tau(0)
+    aa, at, n = sim.get_tau(0)
     assert n == 1
-    AA, A1 = tau.tau_correlator(m, f, m.M // 2)
+    AA, At = tau.tau_correlator(m, f, m.M // 2)
     np.testing.assert_allclose(aa, AA.real, rtol=1e-10, atol=0)
-    assert abs(a1 - A1.real) < 1e-10 * abs(A1)
+    np.testing.assert_allclose(at, At.real, rtol=1e-10, atol=0)
+    lc = m.M // 2
     rows = sim.tau_rows(0)
-    assert rows.shape == (1, m.M // 2 + 2)
-    np.testing.assert_array_equal(rows[0, :-1], aa)
+    assert rows.shape == (1, 2 * lc + 2)
+    np.testing.assert_array_equal(rows[0, :lc + 1], aa)
+    np.testing.assert_array_equal(rows[0, lc + 1:], at)
     # a second pass on the same configuration doubles nothing but the count
     sim.measure_tau()
-    aa2, a12, n2 = sim.get_tau(0)
+    aa2, at2, n2 = sim.get_tau(0)
     assert n2 == 2
     np.testing.assert_allclose(aa2, aa, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(at2, at, rtol=1e-13, atol=0)
 
 
 def test_uneven_batch_tau():
@@ -94,10 +97,11 @@ def test_uneven_batch_tau():
     sim.measure_tau()
     for i, d in enumerate(ds):
         m = _model(d)
-        AA, A1 = tau.tau_correlator(m, sim.fields(i), m.M // 2)
-        aa, a1, n = sim.get_tau(i)
+        AA, At = tau.tau_correlator(m, sim.fields(i), m.M // 2)
+        aa, at, n = sim.get_tau(i)
         assert n == 1
         np.testing.assert_allclose(aa, AA.real, rtol=1e-10, atol=0)
+        np.testing.assert_allclose(at, At.real, rtol=1e-10, atol=0)
     sim.reset_obs()
     sim.measure_tau(7)
     for i, d in enumerate(ds):
@@ -118,10 +122,10 @@ def test_tau_after_sweeps(ch):
     m = _model(d)
     f = sim.fields(0)
     sim.measure_tau()
-    AA, A1 = tau.tau_correlator(m, f, m.M // 2)
-    aa, a1, n = sim.get_tau(0)
+    AA, At = tau.tau_correlator(m, f, m.M // 2)
+    aa, at, n = sim.get_tau(0)
     np.testing.assert_allclose(aa, AA.real, rtol=1e-10, atol=0)
-    assert abs(a1 - A1.real) < 1e-10 * abs(A1)
+    np.testing.assert_allclose(at, At.real, rtol=1e-10, atol=0)
     ref = tau.tau_greens(m, f, 0, m.M // 2)[m.M // 2]
     for which in range(3):
         scale = max(1.0, np.abs(ref[which]).max())
@@ -208,11 +212,12 @@ def test_tau_chains_match_exact_l2(ch, th):
     for _ in range(sweeps):
         sim.sweep(1, measure=False)
         sim.measure_tau()
-    X = np.array([np.concatenate([sim.get_tau(i)[0], [sim.get_tau(i)[1]]]) for i in range(n)])
+    # per chain: <A(tau_l) A(0)> (l = 0, 1), <A> at slice 0 and at slice 1
+    X = np.array([np.concatenate([sim.get_tau(i)[0], sim.get_tau(i)[1]]) for i in range(n)])
     assert all(sim.get_tau(i)[2] == sweeps for i in range(n))
     kw = dict(U=U, dtau=dt, M=M, theta1=th[0], theta2=th[1], channel="charge" if ch else "spin")
     ed = exact.exact_tau_trotter2(exact.tiny_model(**kw))
-    ref = np.concatenate([ed["AA"], [ed["A"]]])
+    ref = np.concatenate([ed["AA"], [ed["A"], ed["A"]]])
     mean = X.mean(axis=0)
     err = X.std(axis=0, ddof=1) / np.sqrt(n)
     assert np.all(np.abs(mean - ref) < 4 * err), (mean, ref, err)
@@ -256,10 +261,11 @@ def test_tau_full_size_sampled():
         err = np.abs(sim.green_tau(0, which) - ref).max()
         assert err < 1e-8, (which, err)
     assert sim.stats(0)["drift_last"] < 1e-8
-    aa, a1, n = sim.get_tau(0)
+    aa, at, n = sim.get_tau(0)
     assert n == 1
     for l, (gtt, gt0, g0t) in ((0, (G0, G0, G0 - np.eye(m.N))), (lm, (Gt, Gt0, G0t))):
         t = (0.5 - np.diag(gtt))[:, None] * (0.5 - np.diag(G0))[None, :] - g0t.T * gt0
         ref = np.sum(np.abs(t) ** 2)
         assert abs(aa[l] - ref) < 1e-8 * ref, (l, aa[l], ref)
-    assert abs(a1 + np.sum(np.abs(0.5 - np.diag(G0)) ** 2)) < 1e-9 * abs(a1)
+        a_ref = -np.sum(np.abs(0.5 - np.diag(gtt)) ** 2)
+        assert abs(at[l] - a_ref) < 1e-9 * abs(a_ref), (l, at[l], a_ref)

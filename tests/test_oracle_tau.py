@@ -113,12 +113,28 @@ def test_equal_time_correlator_matches_observables():
     m = dqmc.Model(3, 3.73, 1.0, 0.1, theta1=0.3, theta2=0.2, n_stab=5)
     rng = np.random.default_rng(2)
     X = rng.choice([-1, 1], size=(m.M, m.N))
-    AA, A1 = tau.tau_correlator(m, X, 0)
+    AA, At = tau.tau_correlator(m, X, 0)
+    A1 = At[0]
     Gu, Gd = m.green_scratch(X, 0, 0), m.green_scratch(X, 0, 1)
     D = np.mean((1 - np.diag(Gu)) * (1 - np.diag(Gd)))
     # sum_i (n_up - 1/2)(n_dn - 1/2) = sum n_up n_dn - (N_up + N_dn)/2 + N/4
     nt = np.sum(2 - np.diag(Gu) - np.diag(Gd))
     assert abs(A1 - (m.N * D - nt / 2 + m.N / 4)) < 1e-12
+
+
+def test_improved_estimator_matches_plain_average():
+    """The improved connected estimator equals <AA> - <A>^2 of the same
+    rows exactly when <A>_X(tau) is the same in every slice of a row
+    (constructed rows)."""
+    rng = np.random.default_rng(0)
+    n, lt = 400, 6
+    a0 = -3.0 + 0.7 * rng.standard_normal(n)
+    at = np.repeat(a0[:, None], lt, axis=1)
+    ferm = 0.4 * np.exp(-np.arange(lt))[None, :] + 0.05 * rng.standard_normal((n, lt))
+    aa = ferm + at * at[:, :1]
+    imp = tau.connected_improved(aa, at)
+    plain = tau.connected(aa.mean(axis=0), a0.mean())
+    np.testing.assert_allclose(imp, plain, rtol=0, atol=1e-12)
 
 
 def test_integrals_closed_forms():
