@@ -32,7 +32,8 @@ def measured_traffic(workload, k, kernel):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
-    src = {"k_flush_direct": "gemm.hip", "k_gemm<S, 1>": "gemm.hip", "k_flush_queue": "gemm.hip"}.get(kernel)
+    src = {"k_flush_direct": "gemm.hip", "k_gemm<S, 1>": "gemm.hip", "k_flush_queue": "gemm.hip",
+           "k_fft_reg<S, 18> active": "fft_wrap.hip"}.get(kernel)
     if not src or not os.path.exists(path):
         return None
     with open(os.path.join(ROOT, "paper_2609_14668_amd", "csrc", src), "rb") as f:
@@ -448,9 +449,12 @@ def main():
         ach = tim["wrap_bytes"] / (wr["ms"] * 1e-3)
         ls = {x["L"] for x in descs}
         wk = ("k_fft_reg" if max(ls) <= 24 else ("k_fft_apply" if min(ls) > 24 else "k_fft_reg + k_fft_apply"))
+        kk = tuned["k"] if tuned and tuned.get("k") else descs[0]["n_delay"]
         line["roofline_wrap"] = {"bound": "hbm", "kernel": wk + " (wrap)", "achieved": ach / 1e9,
                                  "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
-                                 "traffic": None, "launches": wr["launches"],
+                                 "traffic": measured_traffic(a.workload, kk, "k_fft_reg<S, 18> active"),
+                                 "traffic_unit": "bytes per active L=18 side pass (counters)",
+                                 "launches": wr["launches"],
                                  "avg_launch_us": 1e3 * wr["ms"] / max(wr["launches"], 1)}
     line["time_split_ms"] = {k: round(tim[k]["ms"], 1) for k in ("wrap", "window", "expand", "flush", "stab")}
     if descs[0]["precision"] == 1 and "roofline" in line:
