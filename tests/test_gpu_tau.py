@@ -237,6 +237,35 @@ def test_tau_chains_match_exact_l2(ch, th):
     assert abs(dd(X) - fd) < 4 * d_err, (dd(X), fd, d_err)
 
 
+def test_tau_large_l_stockham_path():
+    """L = 30 twisted (N = 1800, the LDS Stockham FFT path), beta = 1, n_stab = 5:
+    the pass to l = 5 (one recomputation) against the oracle's UDV G and
+    explicit propagation, and its series at l = 5 from those matrices."""
+    d = workloads.desc(30, 3.73, 1.0, theta=(0.4, 1.7), n_stab=5, k=64, seed=5)
+    sim = _sim([d])
+    m = _model(d)
+    f = sim.fields(0)
+    lm = 5
+    sim.measure_tau(lm)
+    G0 = m.green_scratch(f, 0, 0)
+    Gt = m.green_scratch(f, lm, 0)
+    P = np.eye(m.N, dtype=complex)
+    Pi = np.eye(m.N, dtype=complex)
+    for l in range(1, lm + 1):
+        P = m.B(0, f[l - 1]) @ P
+        Pi = Pi @ m.Binv(0, f[l - 1])
+    Gt0 = P @ G0
+    G0t = -(np.eye(m.N) - G0) @ Pi
+    for which, ref in enumerate((Gt, Gt0, G0t)):
+        err = np.abs(sim.green_tau(0, which) - ref).max()
+        assert err < 1e-9, (which, err)
+    aa, at, n = sim.get_tau(0)
+    assert n == 1
+    t = (0.5 - np.diag(Gt))[:, None] * (0.5 - np.diag(G0))[None, :] - G0t.T * Gt0
+    ref = np.sum(np.abs(t) ** 2)
+    assert abs(aa[lm] - ref) < 1e-9 * ref, (aa[lm], ref)
+
+
 def test_tau_full_size_sampled():
     """Twisted L = 18, beta = 18 (N = 648, M = 180), the benched shape: the
     pass up to l = 10 (one recomputation) against the oracle's pinned UDV G
