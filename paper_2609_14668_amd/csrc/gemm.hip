@@ -149,7 +149,23 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
     // (beta/alpha) C, loaded before the K loop so that the read of C overlaps
     // the products; the result is alpha * acc.
     const double cscale = (beta != 0.0 && alpha != 0.0) ? beta / alpha : 0.0;
+    // upper-triangular op(A): chunks with k < m0 contribute nothing
+    const int kbeg = a_upper ? (m0 / KB) * KB : 0;
     if (cscale != 0.0) {
+      // the C loads, then the first chunk's loads, then C into the
+      // accumulators: both round trips overlap
+      S craw[2][2][4];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int gi = m0 + wr + ti * 16 + (lane & 15);
+            int gj = n0 + wc + tj * 16 + (lane >> 4) + 4 * r;
+            craw[ti][tj][r] = gld(pc + min(gi, M - 1) + (size_t)min(gj, NC - 1) * ld);
+          }
+      if (kbeg < K) load_chunk(m0, n0, kbeg);
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -160,10 +176,12 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
             int gj = n0 + wc + tj * 16 + (lane >> 4) + 4 * r;
             const bool in = gi < M && gj < NC;
             double re, im;
-            split<S>(gld(pc + min(gi, M - 1) + (size_t)min(gj, NC - 1) * ld), re, im);
+            split<S>(craw[ti][tj][r], re, im);
             acc_r[ti][tj][r] = in ? cscale * re : 0.0;
             if constexpr (CX) acc_p[ti][tj][r] = in ? cscale * (re + im) : 0.0;
           }
+    } else if (kbeg < K) {
+      load_chunk(m0, n0, kbeg);
     }
     // 16 x 16 blocks wholly outside the output are not multiplied (edge tiles
     // of sizes that are not multiples of 64 leave up to 3/4 of a tile empty)
@@ -193,9 +211,6 @@ __device__ __forceinline__ void gemm_tiles(const S* __restrict__ pa, const S* __
           }
         }
     };
-    // upper-triangular op(A): chunks with k < m0 contribute nothing
-    const int kbeg = a_upper ? (m0 / KB) * KB : 0;
-    if (kbeg < K) load_chunk(m0, n0, kbeg);
     for (int k0 = kbeg; k0 < K; k0 += KB) {
       store_chunk();
       __syncthreads();
