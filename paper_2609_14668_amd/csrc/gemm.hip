@@ -863,10 +863,8 @@ hipError_t launch_gemm(const InstDev* insts, int n_inst, int Nmax, bool cplx_, G
                        double alpha, double beta, int flags, hipStream_t s) {
   int Mx = dimval(M, Nmax), Nx = dimval(Nn, Nmax);
   if (Mx <= 0 || Nx <= 0) return hipSuccess;
-  int tiles = ((Mx + BM - 1) / BM) * ((Nx + BN - 1) / BN);
-  int cap = 4096 / (n_inst > 0 ? n_inst : 1);
-  if (cap < 8) cap = 8;
-  int gx = tiles < cap ? tiles : cap;
+  // one output tile per workgroup (the grid's x extent is the tile count)
+  int gx = ((Mx + BM - 1) / BM) * ((Nx + BN - 1) / BN);
   dim3 grid(gx, xcd_grid_y(n_inst));
   const bool fl = flags & GF_K_FILL;
   if (cplx_) {
