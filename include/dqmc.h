@@ -269,7 +269,8 @@ dqmc_status dqmc_get_nk(dqmc_handle h, int32_t inst, int32_t raw, double* host_o
  * stack of the last downward pass (G(tau,0) = [B(tau,0)^{-1} + B(beta,tau)]^{-1},
  * G(0,tau) = -[B(tau,0) + B(beta,tau)^{-1}]^{-1}, with the scale split of the
  * equal-time recomputation; their drift enters dqmc_stats and the drift
- * tolerance).  At every slice the Wick estimator of
+ * tolerance; in DQMC_MIXED handles the wraps run in complex64 as in the
+ * sweep).  At every slice the Wick estimator of
  *   <A(tau_l) A(0)>,  A = sum_i (n_up,i - 1/2)(n_dn,i - 1/2) = H_I + N_s/4
  * (H_I of the correlator C_{H_I}(tau)) is accumulated, the spin-down
  * functions being the particle-hole partners (spin channel) or equal to
