@@ -117,3 +117,29 @@ def test_mixed_replay_against_fp64_oracle(L, th, beta, k):
     rmax = np.sqrt(e2 * ref.max())
     assert np.abs(r - ref).max() <= e2 * (2 * rmax + dr) * dr
     print("mixed replay L=%d: drift %.3g, max |dR| %.3g" % (L, delta, np.abs(r - ref).max()))
+
+
+def test_mixed_time_displaced_pass():
+    """A time-displaced pass in a mixed-precision handle: its wraps run in
+    complex64, its recomputations in FP64.  After one slice each function
+    carries one complex64 side pass (G(tau,tau): two) and obeys the wrap
+    bound above; right after a recomputation (l = n_stab, M/2) all three
+    match the FP64 oracle to 1e-10 of their largest entry."""
+    from oracle import tau
+    d = workloads.desc(4, 3.8, 2.0, theta=(0.7, 2.1), n_stab=5, precision=1, seed=3)
+    sim = _sim([d])
+    m = _model(d)
+    N, M, _ = sim.shapes[0]
+    f = sim.fields(0)
+    ref = tau.tau_greens(m, f, 0, M // 2)
+    sim.measure_tau(1)
+    for which, sides in ((0, 2), (1, 1), (2, 1)):
+        got, r = sim.green_tau(0, which), ref[1][which]
+        bound = sides * 64 * np.log2(N) * U32 * np.linalg.norm(r)
+        assert np.linalg.norm(got - r) <= bound, (which, np.linalg.norm(got - r), bound)
+    for lstop in (5, M // 2):
+        sim.measure_tau(lstop)
+        for which in range(3):
+            r = ref[lstop][which]
+            err = np.abs(sim.green_tau(0, which) - r).max()
+            assert err < 1e-10 * max(1.0, np.abs(r).max()), (lstop, which, err)
