@@ -266,6 +266,32 @@ def test_tau_large_l_stockham_path():
     assert abs(aa[lm] - ref) < 1e-9 * ref, (aa[lm], ref)
 
 
+def test_tau_rows_ring():
+    """The per-pass rows keep the last 1024 passes (oldest overwritten) while
+    the sums and the count cover all of them; passes do not touch the
+    equal-time estimators."""
+    d = workloads.desc(3, 3.8, 0.6, n_stab=3, seed=12)
+    sim = _sim([d])
+    sim.sweep(1, measure=True)
+    n_meas0 = sim.measure(0)["n_meas"]
+    assert n_meas0 > 0
+    sim.measure_tau()
+    one_aa, one_at, n = sim.get_tau(0)
+    assert n == 1
+    for _ in range(1029):
+        sim.measure_tau()
+    aa, at, n = sim.get_tau(0)
+    assert n == 1030
+    np.testing.assert_allclose(aa, one_aa, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(at, one_at, rtol=1e-13, atol=0)
+    rows = sim.tau_rows(0, max_rows=2000)
+    lc = sim.shapes[0][1] // 2
+    assert rows.shape == (1024, 2 * lc + 2)
+    np.testing.assert_array_equal(rows, np.broadcast_to(np.concatenate([one_aa, one_at]), rows.shape))
+    assert sim.tau_rows(0, max_rows=5).shape == (5, 2 * lc + 2)
+    assert sim.measure(0)["n_meas"] == n_meas0
+
+
 def test_tau_full_size_sampled():
     """Twisted L = 18, beta = 18 (N = 648, M = 180), the benched shape: the
     pass up to l = 10 (one recomputation) against the oracle's pinned UDV G
