@@ -24,6 +24,8 @@
 #include "kernels.hpp"
 #include "philox.hpp"
 
+#include <type_traits>
+
 namespace {
 
 constexpr int WMAX = 64;
@@ -310,34 +312,30 @@ k_expand(const InstDev* __restrict__ insts, int lcap) {
         if (jc == gi) ay[q] = ay[q] + ST<S>::one();
         if (kk >= kn) { ax[q] = ST<S>::zero(); ay[q] = ST<S>::zero(); }
       }
-      constexpr int MU = 4;   // rows of X / columns of Y loaded per group
-      int m = 0;
-      for (; m + MU <= mpre; m += MU) {
-        S xv[MU], yv[MU];
+      // rows m .. m+U-1 of X and columns of Y: all 2U loads issued as one
+      // group (one memory round trip), then accumulated in ascending m
+      auto rows = [&](auto count, int mb) {
+        constexpr int U = decltype(count)::value;
+        S xv[U], yv[U];
 #pragma unroll
-        for (int u = 0; u < MU; ++u) {
-          xv[u] = gld(X + jc + (size_t)(m + u) * N);
-          yv[u] = gld(Y + (size_t)(m + u) * N + jc);
+        for (int u = 0; u < U; ++u) {
+          xv[u] = gld(X + jc + (size_t)(mb + u) * N);
+          yv[u] = gld(Y + (size_t)(mb + u) * N + jc);
         }
 #pragma unroll
-        for (int u = 0; u < MU; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int q = 0; q < KW; ++q) {
             const int kk = wave * KW + q;
-            ax[q] = ax[q] - xv[u] * ycf[(m + u) * KC + kk];
-            ay[q] = ay[q] + xcf[(m + u) * KC + kk] * yv[u];
+            ax[q] = ax[q] - xv[u] * ycf[(mb + u) * KC + kk];
+            ay[q] = ay[q] + xcf[(mb + u) * KC + kk] * yv[u];
           }
-      }
-      for (; m < mpre; ++m) {
-        S xv = gld(X + jc + (size_t)m * N);
-        S yv = gld(Y + (size_t)m * N + jc);
-#pragma unroll
-        for (int q = 0; q < KW; ++q) {
-          const int kk = wave * KW + q;
-          ax[q] = ax[q] - xv * ycf[m * KC + kk];
-          ay[q] = ay[q] + xcf[m * KC + kk] * yv;
-        }
-      }
+      };
+      int m = 0;
+      for (; m + 8 <= mpre; m += 8) rows(std::integral_constant<int, 8>{}, m);
+      if (m + 4 <= mpre) { rows(std::integral_constant<int, 4>{}, m); m += 4; }
+      if (m + 2 <= mpre) { rows(std::integral_constant<int, 2>{}, m); m += 2; }
+      if (m < mpre) rows(std::integral_constant<int, 1>{}, m);
 #pragma unroll
       for (int q = 0; q < KW; ++q) {
         pax[wave * KW + q][lane] = ax[q];
