@@ -293,8 +293,10 @@ dqmc_status dqmc_get_tau(dqmc_handle h, int32_t inst, double* host_aa, double* h
  * receives the count.  Synchronises. */
 dqmc_status dqmc_get_tau_rows(dqmc_handle h, int32_t inst, double* host_rows, int32_t max_rows, int32_t* n_rows);
 /* Spin-up G(tau,tau) (which 0), G(tau,0) (1) or G(0,tau) (2) of instance inst
- * at the last slice of the last pass, N x N row-major, elements as in
- * dqmc_get_green.  Synchronises. */
+ * at the last slice of the last pass that instance took part in, N x N
+ * row-major, elements as in dqmc_get_green (the three matrices have storage of
+ * their own, so later sweeps leave them alone; their contents are unspecified
+ * before the instance's first pass).  Synchronises. */
 dqmc_status dqmc_get_green_tau(dqmc_handle h, int32_t inst, int32_t which, double* host_out);
 /* dD/dU = -(2/N_s) int_0^{beta/2} C dtau (eq. DouOccDerive) and
  * chi_F = int_0^{beta/2} tau C dtau (eq. fidelitysusp) from host_c[l] =
