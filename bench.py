@@ -80,6 +80,11 @@ def parse():
                     help="time-displaced passes after the timed legs (one after each extra sweep; 0: none)")
     ap.add_argument("--tau-only", action="store_true",
                     help="only the time-displaced leg (for profiles of the pass)")
+    ap.add_argument("--tau-check", action="store_true",
+                    help="cross-check of the time-displaced dD/dU against the central difference of the "
+                         "equal-time D at U -+ dU on the 64 twisted L=18 chains (uses --warmup, --steps, "
+                         "--tau-passes)")
+    ap.add_argument("--tau-check-du", type=float, default=0.2)
     ap.add_argument("--learn-per-slice", type=int, default=4)
     ap.add_argument("--learn-m", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=400)
@@ -322,6 +327,73 @@ def tau_leg(sim, descs, passes):
             "estimator": "fermionic part + covariance of <A>_X(tau), per twist; error over twists"}
 
 
+def tau_check(a):
+    """Full-size check of the time-displaced path (eq. DouOccDerive) on the 64
+    twisted L=18 chains of the benchmark batch (flush rank 32, three groups):
+    dD/dU at U = 3.73 from the trapezoid integral of C(tau) (a.tau_passes
+    passes, one after each further sweep; C per twist as in tau_leg), against
+    the central difference of the equal-time D measured over a.steps sweeps
+    at U -+ dU with the same twists and seeds, both per twist.  For the
+    Trotterised ensemble the two are equal: the exact derivative identity that
+    exact diagonalisation pins on small clusters."""
+    import torch
+    from paper_2609_14668_amd import Simulation, tau_integrals
+    U0, dU = 3.73, a.tau_check_du
+
+    def run(U, passes):
+        descs = [dict(d, U=U) for d in workloads.twist_L18(n_small=0, k=32)]
+        sim = Simulation(descs)
+        sim.set_streams(3)
+        sim.set_flush_kernel(FLUSH_NAMES.index("tiled"))
+        for s in range(a.warmup + a.steps):
+            if s == a.warmup:
+                sim.reset_obs()
+            sim.sweep(1, measure=s >= a.warmup)
+            torch.cuda.synchronize()
+            print("U=%.3f sweep %d done" % (U, s + 1), file=sys.stderr, flush=True)
+        twists = {}
+        for i, d in enumerate(descs):
+            twists.setdefault((d["theta1"], d["theta2"]), []).append(i)
+        D = np.array([np.mean([sim.measure(i)["D"] for i in v]) for v in twists.values()])
+        tau = None
+        if passes:
+            sim.reset_obs()
+            for p in range(passes):
+                sim.sweep(1, measure=False)
+                sim.measure_tau()
+                torch.cuda.synchronize()
+                print("U=%.3f time-displaced pass %d done" % (U, p + 1), file=sys.stderr, flush=True)
+            lc = sim.shapes[0][1] // 2
+            Ns = 2 * 18 * 18
+            tau = []
+            for v in twists.values():
+                r = np.concatenate([sim.tau_rows(i) for i in v])
+                aa, at = r[:, :lc + 1], r[:, lc + 1:]
+                ma = at.mean()
+                c = np.mean(aa - at * at[:, :1], axis=0) + np.mean((at - ma) * (at[:, :1] - ma), axis=0)
+                tau.append(tau_integrals(c, descs[0]["dtau"], Ns, -1)[0])
+            tau = np.array(tau)
+        sim.close()
+        torch.cuda.empty_cache()
+        return D, tau
+
+    def mean_err(x):
+        return [float(x.mean()), float(x.std(ddof=1) / np.sqrt(len(x)))]
+
+    D0, tau = run(U0, max(a.tau_passes, 1))
+    Dlo, _ = run(U0 - dU, 0)
+    Dhi, _ = run(U0 + dU, 0)
+    fd = (Dhi - Dlo) / (2 * dU)
+    print(json.dumps({"check": "dD/dU: time-displaced pass against the central difference of D",
+                      "config": {"workload": "twist_L18 without the L=12 chains", "chains": 64, "twists": len(D0),
+                                 "U": U0, "dU": dU, "warmup": a.warmup, "sweeps": a.steps,
+                                 "tau_passes": max(a.tau_passes, 1)},
+                      "D": {"U-dU": mean_err(Dlo), "U": mean_err(D0), "U+dU": mean_err(Dhi)},
+                      "dD_dU_tau": mean_err(tau), "dD_dU_central_difference": mean_err(fd),
+                      "difference_per_twist": mean_err(tau - fd),
+                      "errors": "standard error over twists"}))
+
+
 def copy_calibration():
     """A plain device copy of known size: what FETCH_SIZE and WRITE_SIZE read
     for it converts their counts of other kernels to bytes."""
@@ -344,6 +416,9 @@ def main():
         print("bench.py measures one GPU only: the chains are independent and would be sharded "
               "across GPUs with no communication; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if a.tau_check:
+        tau_check(a)
+        return
     import torch
     from paper_2609_14668_amd import Simulation
     descs = make_descs(a.workload, a.k)
