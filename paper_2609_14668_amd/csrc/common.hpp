@@ -70,6 +70,9 @@ __device__ __forceinline__ cplx gld(const cplx* p) {
   gdptr q = (gdptr)p;   // component loads: a struct load through the cast stays FLAT
   return cmake(q[0], q[1]);
 }
+__device__ __forceinline__ int32_t gldi(const int32_t* p) {
+  return *(const __attribute__((address_space(1))) int32_t*)p;
+}
 __device__ __forceinline__ void gst(double* p, double v) { *(gdptr_w)p = v; }
 __device__ __forceinline__ void gst(cplx* p, cplx v) {
   gdptr_w q = (gdptr_w)p;

@@ -248,16 +248,16 @@ k_expand(const InstDev* __restrict__ insts, int lcap) {
   constexpr int KW = KC / EXP_WAVES;
   const InstDev& d = insts[blockIdx.y];
   const InstState* st = d.st;
-  if (st->init_mode || st->idle) return;
-  const int mw = st->m_w;
-  if (mw == 0) return;
+  // the state fields read here, loaded together before the exit tests
+  const int init_mode = gldi(&st->init_mode), idle = gldi(&st->idle);
+  const int mw = gldi(&st->m_w), fill0 = gldi(&st->fill);
+  if (init_mode || idle || mw == 0) return;
   const int N = d.N;
   const int j0 = blockIdx.x * 64;
   if (j0 >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j = j0 + lane;
   const bool ok = j < N;
-  const int fill0 = st->fill;
   const S* G = matp<S>(d, MAT_G);
   S* X = matp<S>(d, MAT_X);
   S* Y = matp<S>(d, MAT_Y);
@@ -271,8 +271,8 @@ k_expand(const InstDev* __restrict__ insts, int lcap) {
   __shared__ S pax[KC][64], pay[KC][64];
   __shared__ int sites[WMAX], gsites[WMAX];   // table position, site index
   if (tid < WMAX) {
-    sites[tid] = tid < mw ? d.acc_site[tid] : 0;
-    gsites[tid] = tid < mw ? d.acc_gsite[tid] : 0;
+    sites[tid] = tid < mw ? gldi(d.acc_site + tid) : 0;
+    gsites[tid] = tid < mw ? gldi(d.acc_gsite + tid) : 0;
   }
   __syncthreads();
 
