@@ -30,27 +30,29 @@ template <typename C> using real_of_t = decltype(C::x);
 
 __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) {
   Resolved r{0, 0, 0, 0, TAB_P, 0};
-  const InstState& st = *d.st;
-  if (st.idle) return r;
+  // the state fields read here, loaded together before the first test
+  const InstState* st = d.st;
+  const int idle = gldi(&st->idle), phase = gldi(&st->phase), init_mode = gldi(&st->init_mode);
+  if (idle) return r;
   int M = d.M;
-  int up = sched_is_up(st.phase, M);
-  int l = sched_slice(st.phase, M);
+  int up = sched_is_up(phase, M);
+  int l = sched_slice(phase, M);
   switch (a.op) {
     case FOP_WRAP_PRE:  // G <- e^{V} E+ G E- e^{-V} before updating slice l (upward)
-      if (!up || st.init_mode) return r;
+      if (!up || init_mode) return r;
       r.active = 1; r.slice = l;
       if (a.side == 0) { r.pre = 0; r.tab = TAB_P; r.post = +1; }
       else { r.pre = 0; r.tab = TAB_M; r.post = -1; }
       return r;
     case FOP_WRAP_POST:  // G <- E- e^{-V} G e^{V} E+ after updating slice l (downward)
-      if (up || st.init_mode) return r;
+      if (up || init_mode) return r;
       r.active = 1; r.slice = l;
       if (a.side == 0) { r.pre = -1; r.tab = TAB_M; r.post = 0; }
       else { r.pre = +1; r.tab = TAB_P; r.post = 0; }
       return r;
     case FOP_STAB_B: {  // columns of the working U: B (upward) or B^dagger (downward)
       if (a.side != 0) return r;
-      int c = sched_ckpt(st.phase, M, d.n_stab);
+      int c = sched_ckpt(phase, M, d.n_stab);
       r.active = 1;
       if (up) {  // R_c = B_{c ns} .. B_{(c-1) ns + 1} R_{c-1}: lowest slice first
         r.slice = (c - 1) * d.n_stab + 1 + a.j;
@@ -75,7 +77,7 @@ __device__ __forceinline__ Resolved resolve(const InstDev& d, const FftArgs& a) 
       r.active = 1;
       return r;
     case FOP_FOURIER:
-      if (st.init_mode) return r;
+      if (init_mode) return r;
       r.active = 1;
       return r;
   }
